@@ -1,0 +1,176 @@
+"""Seeded synthetic inputs shaped like the paper's workloads.
+
+This module generates inputs only; it holds no part of any sort.  The tests,
+the benchmark and the smoke check use it for both the GPU library and the CPU
+oracle, so that both sort the same data.
+
+Random numbers come from the counter-based SplitMix64 generator (Steele, Lea,
+Flood, "Fast splittable pseudorandom number generators", OOPSLA 2014):
+``x_i = mix(seed + (i + 1) * 0x9E3779B97F4A7C15)`` so that any element can be
+generated on its own.
+
+Families (the seven of the large single-sort workload, in the spirit of the
+paper's SVI/SIX inputs, whose exact definitions in its reference [3] are not
+available):
+
+``uniform``        low 32 bits of ``x_i`` (int32/uint32), all 64 bits (int64/uint64),
+                   N(0,1) by Box-Muller for float32 (with the special values below)
+``sorted``         ``k_i = i``
+``reversed``       ``k_i = n - 1 - i``
+``nearly_sorted``  ``k_i = i``, then ``n // 200`` sequential swaps of positions
+                   ``(x_{2j} mod n, x_{2j+1} mod n)`` (about 1% of positions moved)
+``many_equals``    ``x_i mod 100``
+``stair_steps``    ``i // 1000`` (ascending runs of 1000 equal values)
+``organ_pipe``     ``1..n/2`` then ``n/2..1`` (``i + 1`` for ``i < n/2``, ``n - i`` after)
+
+float32 families other than ``uniform`` are the float value of the integer family
+(exact below 2^24).  ``special_float32`` salts N(0,1) with 0.1% each of -0.0,
++0.0, +inf, -inf and a quiet NaN.  ``distinct10_u64`` draws uint64 keys from a
+pool of n/10 random values.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+GOLDEN = np.uint64(0x9E3779B97F4A7C15)
+M1 = np.uint64(0xBF58476D1CE4E5B9)
+M2 = np.uint64(0x94D049BB133111EB)
+FAMILIES = ["uniform", "sorted", "reversed", "nearly_sorted", "many_equals",
+            "stair_steps", "organ_pipe"]
+DTYPES = {"int32": np.int32, "uint32": np.uint32, "int64": np.int64,
+          "uint64": np.uint64, "float32": np.float32}
+BASE_SEED = 0x75C50000
+CHUNK = 1 << 23
+
+
+def seed_for(config: int, family: str | int) -> int:
+    """Seed of a (workload number, family) pair: 0x75C50000 + 16*config + family."""
+    f = FAMILIES.index(family) if isinstance(family, str) else int(family)
+    return BASE_SEED + 16 * int(config) + f
+
+
+def _mix(z: np.ndarray) -> np.ndarray:
+    z = (z ^ (z >> np.uint64(30))) * M1
+    z = (z ^ (z >> np.uint64(27))) * M2
+    return z ^ (z >> np.uint64(31))
+
+
+def splitmix64(seed: int, count: int, start: int = 0) -> np.ndarray:
+    """x_i for i in [start, start + count) as uint64."""
+    out = np.empty(count, dtype=np.uint64)
+    s = np.uint64(seed & 0xFFFFFFFFFFFFFFFF)
+    with np.errstate(over="ignore"):
+        for c0 in range(0, count, CHUNK):
+            c1 = min(count, c0 + CHUNK)
+            i = np.arange(start + c0 + 1, start + c1 + 1, dtype=np.uint64)
+            out[c0:c1] = _mix(s + i * GOLDEN)
+    return out
+
+
+def _index_family(family: str, n: int, seed: int) -> np.ndarray:
+    """Integer-valued families as int64 values (before the cast to a dtype)."""
+    i = np.arange(n, dtype=np.int64)
+    if family == "sorted":
+        return i
+    if family == "reversed":
+        return n - 1 - i
+    if family == "nearly_sorted":
+        k = i.copy()
+        nsw = n // 200
+        if nsw and n > 1:
+            x = splitmix64(seed, 2 * nsw)
+            a = (x[0::2] % np.uint64(n)).astype(np.int64)
+            b = (x[1::2] % np.uint64(n)).astype(np.int64)
+            for p, q in zip(a.tolist(), b.tolist()):
+                k[p], k[q] = k[q], k[p]
+        return k
+    if family == "many_equals":
+        return (splitmix64(seed, n) % np.uint64(100)).astype(np.int64)
+    if family == "stair_steps":
+        return i // 1000
+    if family == "organ_pipe":
+        h = n // 2
+        return np.where(i < h, i + 1, n - i)
+    raise KeyError(family)
+
+
+def normal_float32(seed: int, n: int) -> np.ndarray:
+    """N(0,1) by Box-Muller from one 64-bit draw per element."""
+    x = splitmix64(seed, n)
+    u1 = ((x >> np.uint64(40)).astype(np.float64) + 1.0) * 2.0 ** -24
+    u2 = (x & np.uint64(0xFFFFFF)).astype(np.float64) * 2.0 ** -24
+    return (np.sqrt(-2.0 * np.log(u1)) * np.cos(2.0 * np.pi * u2)).astype(np.float32)
+
+
+SPECIAL_F32_BITS = [0x80000000, 0x00000000, 0x7F800000, 0xFF800000, 0x7FC00000]
+
+
+def special_float32(seed: int, n: int) -> np.ndarray:
+    """N(0,1) salted with 0.1% each of -0.0, +0.0, +inf, -inf, NaN (0x7FC00000)."""
+    v = normal_float32(seed, n).view(np.uint32)
+    sel = splitmix64(seed + 1, n) % np.uint64(1000)
+    for j, bits in enumerate(SPECIAL_F32_BITS):
+        v[sel == np.uint64(j)] = np.uint32(bits)
+    return v.view(np.float32)
+
+
+def distinct10_u64(seed: int, n: int) -> np.ndarray:
+    """uint64 keys drawn from a pool of max(1, n // 10) random values."""
+    pool_n = max(1, n // 10)
+    pool = splitmix64(seed + 1, pool_n)
+    idx = splitmix64(seed, n) % np.uint64(pool_n)
+    return pool[idx.astype(np.int64)]
+
+
+def family(name: str, n: int, dtype="int32", seed: int | None = None,
+           config: int = 2) -> np.ndarray:
+    """Keys of one family at size n and dtype (a numpy array on the host)."""
+    dt = np.dtype(DTYPES[dtype] if isinstance(dtype, str) else dtype)
+    if seed is None:
+        seed = seed_for(config, name)
+    if name == "uniform":
+        if dt == np.float32:
+            return special_float32(seed, n)
+        x = splitmix64(seed, n)
+        if dt.itemsize == 4:
+            return (x & np.uint64(0xFFFFFFFF)).astype(np.uint32).view(dt)
+        return x.view(dt)
+    v = _index_family(name, n, seed)
+    if dt == np.float32:
+        return v.astype(np.float32)
+    return v.astype(dt)
+
+
+def batch_sizes(seed: int, count: int, lo_log2: int = 4, hi_log2: int = 20) -> np.ndarray:
+    """Sizes floor(2^lo * 2^((hi-lo)*u)), u uniform in [0,1): log-uniform on [2^lo, 2^hi]."""
+    x = splitmix64(seed, count)
+    u = (x >> np.uint64(11)).astype(np.float64) * 2.0 ** -53
+    return np.floor(2.0 ** lo_log2 * 2.0 ** ((hi_log2 - lo_log2) * u)).astype(np.int64)
+
+
+def batch_families(seed: int, count: int) -> list:
+    x = splitmix64(seed + 7, count)
+    return [FAMILIES[int(v % np.uint64(len(FAMILIES)))] for v in x]
+
+
+def batch(seed: int, count: int, lo_log2: int = 4, hi_log2: int = 20, dtype="int32",
+          max_total: int | None = None):
+    """Concatenated keys of ``count`` independent arrays with log-uniform sizes,
+    each of a family drawn uniformly from the seven; array j uses sub-seed
+    ``seed + 0x100000 + j`` so it can be regenerated alone.
+
+    Returns (keys, offsets[count+1] uint64, families).  With ``max_total`` the
+    arrays are drawn until the total would exceed it."""
+    sizes = batch_sizes(seed, count, lo_log2, hi_log2)
+    fams = batch_families(seed, count)
+    if max_total is not None:
+        cs = np.cumsum(sizes)
+        keep = int(np.searchsorted(cs, max_total, side="right"))
+        sizes, fams = sizes[:keep], fams[:keep]
+    offs = np.zeros(len(sizes) + 1, dtype=np.uint64)
+    offs[1:] = np.cumsum(sizes)
+    dt = np.dtype(DTYPES[dtype] if isinstance(dtype, str) else dtype)
+    keys = np.empty(int(offs[-1]), dtype=dt)
+    for j, (s, f) in enumerate(zip(sizes.tolist(), fams)):
+        keys[int(offs[j]):int(offs[j + 1])] = family(f, s, dt, seed=seed + 0x100000 + j)
+    return keys, offs, fams
