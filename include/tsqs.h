@@ -1,0 +1,135 @@
+/*
+ * tsqs.h -- C ABI of libtsqs, a three-way partition sort for AMD MI355X (gfx950).
+ *
+ * The operation is the one of Triple State QuickSort (Muqaddas, arXiv
+ * 1505.00558): sort nmemb elements in ascending order, in place, qsort-style
+ * (abstract and SVII of the paper), by recursive partitioning around a sampled
+ * pivot where every key equal to the pivot is put in a middle band and never
+ * compared again (SIII, the "equals partition").  Here the elements are
+ * fixed-width keys resident in device memory, optionally carrying a uint32
+ * payload; the order is compiled in:
+ *   int32 / int64 / uint32 / uint64  the usual integer order;
+ *   float32                          IEEE 754-2008 totalOrder on the bits:
+ *       -NaN < -inf < -finite < -0.0 < +0.0 < +finite < +inf < +NaN,
+ *       NaNs ordered by payload; two keys are equal iff their bits are equal.
+ * Output keys are therefore unique (the sorted arrangement of the input
+ * multiset).  Payload order among equal keys is unspecified (the sort is not
+ * stable), but every payload stays with its key.
+ *
+ * Ownership.  The caller owns the key / payload buffers (device memory, e.g.
+ * a hipMalloc'd pointer or a torch tensor's data_ptr()).  The library owns a
+ * per-device workspace (a scratch copy of the keys and payloads plus small
+ * tables) that grows to the largest request seen and is kept between calls,
+ * as the paper keeps its temporary buffer (SIII.G); tsqs_free_storage()
+ * releases it (the paper's FreeTripleStateQuickSortStorage()).
+ *
+ * Streams and synchronisation.  All work is enqueued on `stream` (a
+ * hipStream_t; NULL = the default stream).  The call returns after that work
+ * has completed (it synchronises `stream` to learn how many partition levels
+ * were needed and to collect error flags and statistics), so the buffers may
+ * be used as soon as it returns.  Calls are serialised by a library mutex.
+ *
+ * Errors.  Argument errors are returned before any HIP call is made.  A HIP
+ * runtime failure returns TSQS_EDEVICE; a workspace allocation failure
+ * TSQS_ENOMEM; an internal capacity or level-limit violation TSQS_EINTERNAL.
+ * In every error case the contents of the caller's buffers are unspecified.
+ */
+#ifndef TSQS_H
+#define TSQS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  TSQS_INT32 = 0,
+  TSQS_UINT32 = 1,
+  TSQS_INT64 = 2,
+  TSQS_UINT64 = 3,
+  TSQS_FLOAT32 = 4
+} tsqs_dtype_t;
+
+enum {
+  TSQS_OK = 0,
+  TSQS_EINVAL = -1,        /* bad pointer, size or offsets */
+  TSQS_ENOMEM = -2,        /* workspace could not be allocated */
+  TSQS_EDEVICE = -3,       /* HIP runtime error */
+  TSQS_EUNSUPPORTED = -4,  /* unknown dtype or option */
+  TSQS_EINTERNAL = -5      /* capacity / level limit exceeded (a bug) */
+};
+
+/* Option keys for tsqs_set_option / tsqs_get_option. */
+enum {
+  TSQS_OPT_SMALL_MAX = 1,    /* parts of at most this many keys are finished by
+                                one workgroup in LDS (paper SIV's cutoff role);
+                                16..8192 (4096 for 64-bit keys with payload) */
+  TSQS_OPT_SAMPLES = 2,      /* pivot samples per part, odd, 3..63 (SIII.H) */
+  TSQS_OPT_DEPTH_FACTOR = 3, /* depth limit = factor * ceil(log2 n); a part at the
+                                limit gets the exact median (introsort idea, SV.C) */
+  TSQS_OPT_PIVOT_MODE = 4,   /* 0 = median of samples; 1 = exact minimum (test
+                                knob that forces the depth-limit fallback) */
+  TSQS_OPT_SEED = 5,         /* seed of the per-call sample jitter (SV.C) */
+  TSQS_OPT_TIMING = 6,       /* 1 = time every partition launch with HIP events */
+  TSQS_OPT_PART_GRID = 7,    /* workgroups of the partition kernel (0 = auto) */
+  TSQS_OPT_FINISH_GRID = 8   /* workgroups of the finish kernel (0 = auto) */
+};
+
+#define TSQS_MAX_LEVELS 192
+
+typedef struct {
+  uint32_t levels;               /* partition levels launched */
+  uint32_t max_depth;            /* deepest partitioned part */
+  uint64_t n;                    /* keys sorted */
+  uint32_t key_bytes;            /* 4 or 8 */
+  uint32_t payload_bytes;        /* 0 or 4 */
+  uint64_t fallback_parts;       /* parts that got the exact median */
+  uint64_t small_parts;          /* parts finished in LDS */
+  uint64_t small_keys;           /* keys finished in LDS */
+  uint64_t band_keys;            /* keys placed by an equal band */
+  uint64_t level_keys[TSQS_MAX_LEVELS];     /* keys partitioned at each level */
+  uint32_t level_parts[TSQS_MAX_LEVELS];    /* parts partitioned at each level */
+  float level_ms[TSQS_MAX_LEVELS];          /* partition kernel time (TIMING) */
+  double partition_ms;           /* sum of level_ms */
+  uint64_t partition_bytes;      /* algorithmic bytes: 2 * keys * (key+payload bytes) */
+  uint32_t partition_launches;   /* launches with at least one tile */
+  uint32_t reserved;
+} tsqs_stats_t;
+
+/* Sort nmemb keys of type dt at device pointer d_keys, in place.
+ * nmemb <= 1 is a no-op.  nmemb must be < 2^32.
+ * Returns TSQS_OK or an error code. */
+int tsqs_sort(void *d_keys, size_t nmemb, int dt, void *stream);
+
+/* As tsqs_sort, moving the uint32 payload d_vals[i] with key d_keys[i]. */
+int tsqs_sort_pairs(void *d_keys, uint32_t *d_vals, size_t nmemb, int dt, void *stream);
+
+/* Sort nseg independent arrays stored back to back in d_keys: array j is
+ * d_keys[h_offsets[j] .. h_offsets[j+1]).  h_offsets is a host array of nseg+1
+ * non-decreasing values starting at 0; every array must have < 2^32 keys (the
+ * total may exceed that).  d_vals may be NULL (keys only) or a payload array
+ * of the same layout.  All arrays are sorted by one schedule of launches. */
+int tsqs_sort_batch(void *d_keys, uint32_t *d_vals, const uint64_t *h_offsets, size_t nseg,
+                    int dt, void *stream);
+
+/* Release the workspace of every device (SIII.G's manual release). */
+void tsqs_free_storage(void);
+
+int tsqs_set_option(int key, int64_t value);
+/* Returns the option's value, or INT64_MIN for an unknown key. */
+int64_t tsqs_get_option(int key);
+
+/* Statistics of the last successful call. */
+int tsqs_get_stats(tsqs_stats_t *out);
+
+const char *tsqs_strerror(int code);
+
+/* ABI version (increments when this header changes incompatibly). */
+int tsqs_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,199 @@
+"""Three-way partition sort for AMD MI355X (gfx950).
+
+Thin ctypes binding of ``libtsqs.so`` (C ABI in ``include/tsqs.h``).  Every step
+of the sort runs in the library's HIP kernels; this module only marshals torch
+tensors (device memory) and the current HIP stream.  There is no CPU fallback:
+if the library is missing or no GPU is present the calls raise.
+
+The method is Triple State QuickSort's (Muqaddas, arXiv 1505.00558, SIII):
+recursive partitioning around a sampled pivot into < / == / > parts, the == part
+being final and never compared again.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libtsqs.so")
+
+INT32, UINT32, INT64, UINT64, FLOAT32 = 0, 1, 2, 3, 4
+OK, EINVAL, ENOMEM, EDEVICE, EUNSUPPORTED, EINTERNAL = 0, -1, -2, -3, -4, -5
+OPT_SMALL_MAX, OPT_SAMPLES, OPT_DEPTH_FACTOR, OPT_PIVOT_MODE = 1, 2, 3, 4
+OPT_SEED, OPT_TIMING, OPT_PART_GRID, OPT_FINISH_GRID = 5, 6, 7, 8
+MAX_LEVELS = 192
+
+SYMBOLS = ["tsqs_sort", "tsqs_sort_pairs", "tsqs_sort_batch", "tsqs_free_storage",
+           "tsqs_set_option", "tsqs_get_option", "tsqs_get_stats", "tsqs_strerror",
+           "tsqs_version"]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [
+        ("levels", ctypes.c_uint32),
+        ("max_depth", ctypes.c_uint32),
+        ("n", ctypes.c_uint64),
+        ("key_bytes", ctypes.c_uint32),
+        ("payload_bytes", ctypes.c_uint32),
+        ("fallback_parts", ctypes.c_uint64),
+        ("small_parts", ctypes.c_uint64),
+        ("small_keys", ctypes.c_uint64),
+        ("band_keys", ctypes.c_uint64),
+        ("level_keys", ctypes.c_uint64 * MAX_LEVELS),
+        ("level_parts", ctypes.c_uint32 * MAX_LEVELS),
+        ("level_ms", ctypes.c_float * MAX_LEVELS),
+        ("partition_ms", ctypes.c_double),
+        ("partition_bytes", ctypes.c_uint64),
+        ("partition_launches", ctypes.c_uint32),
+        ("reserved", ctypes.c_uint32),
+    ]
+
+    def as_dict(self) -> dict:
+        lv = int(self.levels)
+        return {
+            "levels": lv, "max_depth": int(self.max_depth), "n": int(self.n),
+            "key_bytes": int(self.key_bytes), "payload_bytes": int(self.payload_bytes),
+            "fallback_parts": int(self.fallback_parts), "small_parts": int(self.small_parts),
+            "small_keys": int(self.small_keys), "band_keys": int(self.band_keys),
+            "level_keys": [int(x) for x in self.level_keys[:lv]],
+            "level_parts": [int(x) for x in self.level_parts[:lv]],
+            "level_ms": [float(x) for x in self.level_ms[:lv]],
+            "partition_ms": float(self.partition_ms),
+            "partition_bytes": int(self.partition_bytes),
+            "partition_launches": int(self.partition_launches),
+        }
+
+
+class TsqsError(RuntimeError):
+    pass
+
+
+_lib = None
+
+
+def load_library():
+    """Load libtsqs.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError("libtsqs.so is not built; run paper_1505_00558_amd.build.build()")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, sz = ctypes.c_void_p, ctypes.c_size_t
+    lib.tsqs_sort.argtypes = [vp, sz, ctypes.c_int, vp]
+    lib.tsqs_sort.restype = ctypes.c_int
+    lib.tsqs_sort_pairs.argtypes = [vp, vp, sz, ctypes.c_int, vp]
+    lib.tsqs_sort_pairs.restype = ctypes.c_int
+    lib.tsqs_sort_batch.argtypes = [vp, vp, vp, sz, ctypes.c_int, vp]
+    lib.tsqs_sort_batch.restype = ctypes.c_int
+    lib.tsqs_free_storage.argtypes = []
+    lib.tsqs_free_storage.restype = None
+    lib.tsqs_set_option.argtypes = [ctypes.c_int, ctypes.c_int64]
+    lib.tsqs_set_option.restype = ctypes.c_int
+    lib.tsqs_get_option.argtypes = [ctypes.c_int]
+    lib.tsqs_get_option.restype = ctypes.c_int64
+    lib.tsqs_get_stats.argtypes = [ctypes.POINTER(Stats)]
+    lib.tsqs_get_stats.restype = ctypes.c_int
+    lib.tsqs_strerror.argtypes = [ctypes.c_int]
+    lib.tsqs_strerror.restype = ctypes.c_char_p
+    lib.tsqs_version.argtypes = []
+    lib.tsqs_version.restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def strerror(code: int) -> str:
+    return load_library().tsqs_strerror(int(code)).decode()
+
+
+def _check(rc: int) -> None:
+    if rc != OK:
+        raise TsqsError("tsqs error %d: %s" % (rc, strerror(rc)))
+
+
+def _dtype_code(t) -> int:
+    import torch
+    m = {torch.int32: INT32, torch.int64: INT64, torch.float32: FLOAT32}
+    if hasattr(torch, "uint32"):
+        m[torch.uint32] = UINT32
+    if hasattr(torch, "uint64"):
+        m[torch.uint64] = UINT64
+    if t.dtype not in m:
+        raise TypeError("unsupported key dtype %s" % t.dtype)
+    return m[t.dtype]
+
+
+def _stream_handle():
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _check_tensor(t, name):
+    if not t.is_cuda:
+        raise ValueError("%s must be a device tensor" % name)
+    if not t.is_contiguous():
+        raise ValueError("%s must be contiguous" % name)
+
+
+def sort(keys, dtype_code: int | None = None):
+    """Sort a 1-D device tensor of keys in place (ascending; float32 by totalOrder)."""
+    _check_tensor(keys, "keys")
+    dt = _dtype_code(keys) if dtype_code is None else dtype_code
+    _check(load_library().tsqs_sort(ctypes.c_void_p(keys.data_ptr()), keys.numel(), dt,
+                                    _stream_handle()))
+    return keys
+
+
+def sort_pairs(keys, vals, dtype_code: int | None = None):
+    """Sort keys in place, moving the uint32 payload ``vals`` (int32 or uint32 tensor) along."""
+    _check_tensor(keys, "keys")
+    _check_tensor(vals, "vals")
+    if vals.numel() != keys.numel() or vals.element_size() != 4:
+        raise ValueError("vals must hold one 4-byte payload per key")
+    dt = _dtype_code(keys) if dtype_code is None else dtype_code
+    _check(load_library().tsqs_sort_pairs(ctypes.c_void_p(keys.data_ptr()),
+                                          ctypes.c_void_p(vals.data_ptr()), keys.numel(), dt,
+                                          _stream_handle()))
+    return keys, vals
+
+
+def sort_batch(keys, offsets, vals=None, dtype_code: int | None = None):
+    """Sort len(offsets)-1 arrays stored back to back in ``keys``.
+
+    ``offsets`` is a host sequence / numpy array of nseg+1 non-decreasing uint64
+    values starting at 0."""
+    import numpy as np
+    _check_tensor(keys, "keys")
+    offs = np.ascontiguousarray(np.asarray(offsets, dtype=np.uint64))
+    nseg = offs.size - 1
+    if nseg < 0:
+        raise ValueError("offsets needs at least one value")
+    vp = None
+    if vals is not None:
+        _check_tensor(vals, "vals")
+        if vals.numel() != keys.numel() or vals.element_size() != 4:
+            raise ValueError("vals must hold one 4-byte payload per key")
+        vp = ctypes.c_void_p(vals.data_ptr())
+    dt = _dtype_code(keys) if dtype_code is None else dtype_code
+    _check(load_library().tsqs_sort_batch(ctypes.c_void_p(keys.data_ptr()), vp,
+                                          offs.ctypes.data_as(ctypes.c_void_p), nseg, dt,
+                                          _stream_handle()))
+    return keys
+
+
+def free_storage() -> None:
+    load_library().tsqs_free_storage()
+
+
+def set_option(key: int, value: int) -> None:
+    _check(load_library().tsqs_set_option(int(key), int(value)))
+
+
+def get_option(key: int) -> int:
+    return int(load_library().tsqs_get_option(int(key)))
+
+
+def get_stats() -> dict:
+    s = Stats()
+    _check(load_library().tsqs_get_stats(ctypes.byref(s)))
+    return s.as_dict()

@@ -1,0 +1,380 @@
+// tsqs_host.hip -- host driver and C ABI of libtsqs (see include/tsqs.h).
+//
+// One call = one schedule on the caller's stream:
+//   k_reset, [upload of batch offsets], k_init (roots: pivot or small item),
+//   then per level d: k_partition(d), k_plan(d), k_finish(d),
+// launched without host synchronisation for the number of levels a median
+// split needs (ceil(log2(n / small_max)) + 2); the stream is then synchronised
+// once, and only if parts remain (bad pivots, the depth-limit path) more levels
+// are launched, eight at a time.
+#include "tsqs.h"
+#include "tsqs_kernels.hpp"
+
+#include <hip/hip_runtime.h>
+
+#include <climits>
+#include <cstring>
+#include <mutex>
+#include <vector>
+
+using namespace tsqs;
+
+namespace {
+
+struct Options {
+  int64_t small_max = 8192;
+  int64_t samples = 63;
+  int64_t depth_factor = 2;
+  int64_t pivot_mode = 0;
+  int64_t seed = 0x5EED1505;
+  int64_t timing = 0;
+  int64_t part_grid = 0;
+  int64_t finish_grid = 0;
+};
+
+struct Workspace {
+  bool init = false;
+  int cus = 0;
+  size_t s_bytes = 0;
+  void *S = nullptr;
+  size_t v_cap = 0;
+  uint32_t *VS = nullptr, *VE = nullptr;
+  size_t seg_cap = 0;
+  Seg *seg[2] = {nullptr, nullptr};
+  unsigned long long *ctr[2] = {nullptr, nullptr};
+  unsigned int *ectr[2] = {nullptr, nullptr};
+  size_t fin_cap = 0;
+  FinItem *fin = nullptr;
+  LevelCtl *lvl = nullptr;
+  DevStats *st = nullptr;
+  size_t off_cap = 0;
+  uint64_t *offs = nullptr;
+  LevelCtl *h_lvl = nullptr;   // pinned
+  DevStats *h_st = nullptr;    // pinned
+  hipEvent_t ev[2 * kMaxLevels];
+  bool ev_ok = false;
+};
+
+std::mutex g_mu;
+Options g_opt;
+std::vector<Workspace> g_ws;
+tsqs_stats_t g_stats;
+bool g_have_stats = false;
+uint64_t g_calls = 0;
+
+#define HIPCHK(expr)                                   \
+  do {                                                 \
+    hipError_t e_ = (expr);                            \
+    if (e_ != hipSuccess) return TSQS_EDEVICE;         \
+  } while (0)
+
+template <typename T>
+int grow(T **p, size_t *cap, size_t need, size_t elem = sizeof(T)) {
+  if (*cap >= need) return TSQS_OK;
+  if (*p) { (void)hipFree(*p); *p = nullptr; *cap = 0; }
+  void *q = nullptr;
+  if (hipMalloc(&q, need * elem) != hipSuccess) { (void)hipGetLastError(); return TSQS_ENOMEM; }
+  *p = static_cast<T *>(q);
+  *cap = need;
+  return TSQS_OK;
+}
+
+void free_ws(Workspace &w) {
+  (void)hipFree(w.S); (void)hipFree(w.VS); (void)hipFree(w.VE);
+  for (int i = 0; i < 2; i++) { (void)hipFree(w.seg[i]); (void)hipFree(w.ctr[i]); (void)hipFree(w.ectr[i]); }
+  (void)hipFree(w.fin); (void)hipFree(w.lvl); (void)hipFree(w.st); (void)hipFree(w.offs);
+  (void)hipHostFree(w.h_lvl); (void)hipHostFree(w.h_st);
+  if (w.ev_ok) for (int i = 0; i < 2 * kMaxLevels; i++) (void)hipEventDestroy(w.ev[i]);
+  w = Workspace();
+}
+
+int ensure_static(Workspace &w, int dev) {
+  if (w.init) return TSQS_OK;
+  hipDeviceProp_t prop;
+  HIPCHK(hipGetDeviceProperties(&prop, dev));
+  w.cus = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
+  if (hipMalloc(&w.lvl, sizeof(LevelCtl) * kMaxLevels) != hipSuccess) return TSQS_ENOMEM;
+  if (hipMalloc(&w.st, sizeof(DevStats)) != hipSuccess) return TSQS_ENOMEM;
+  if (hipHostMalloc(&w.h_lvl, sizeof(LevelCtl) * kMaxLevels, hipHostMallocDefault) != hipSuccess) return TSQS_ENOMEM;
+  if (hipHostMalloc(&w.h_st, sizeof(DevStats), hipHostMallocDefault) != hipSuccess) return TSQS_ENOMEM;
+  w.init = true;
+  return TSQS_OK;
+}
+
+uint32_t small_max_limit(size_t kb, bool hasv) { return (kb == 8 && hasv) ? 4096u : 8192u; }
+
+uint32_t ceil_log2(uint64_t x) {
+  uint32_t l = 0;
+  while (l < 64 && (1ull << l) < x) l++;
+  return l;
+}
+
+uint32_t mix32(uint64_t z) {
+  z += 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return (uint32_t)(z ^ (z >> 31));
+}
+
+template <int DT, bool HASV>
+int run_t(Workspace &w, void *keys, uint32_t *vals, const uint64_t *h_offs, size_t nroots,
+          uint64_t n, uint64_t max_root, hipStream_t s) {
+  using B = typename Codec<DT>::B;
+  const size_t kb = sizeof(B);
+  uint32_t small_max = (uint32_t)g_opt.small_max;
+  const uint32_t lim = small_max_limit(kb, HASV);
+  if (small_max > lim) small_max = lim;
+  if (small_max < 16) small_max = 16;
+
+  // workspace sizes
+  const size_t seg_cap = (size_t)(n / (small_max + 1)) + 2;
+  const size_t fin_cap = 3 * seg_cap + (size_t)(n / kBandChunk) + nroots + 16;
+  int rc;
+  {
+    size_t cap_bytes = w.s_bytes;
+    void *S = w.S;
+    if ((rc = grow<unsigned char>((unsigned char **)&S, &cap_bytes, (size_t)n * kb)) != TSQS_OK) return rc;
+    w.S = S; w.s_bytes = cap_bytes;
+  }
+  if (HASV) {
+    size_t c1 = w.v_cap, c2 = w.v_cap;
+    if ((rc = grow(&w.VS, &c1, (size_t)n)) != TSQS_OK) return rc;
+    if ((rc = grow(&w.VE, &c2, (size_t)n)) != TSQS_OK) return rc;
+    w.v_cap = c1 < c2 ? c1 : c2;
+  }
+  if (w.seg_cap < seg_cap) {
+    for (int i = 0; i < 2; i++) {
+      size_t a = w.seg_cap, b = w.seg_cap, c = w.seg_cap;
+      if ((rc = grow(&w.seg[i], &a, seg_cap)) != TSQS_OK) return rc;
+      if ((rc = grow(&w.ctr[i], &b, seg_cap)) != TSQS_OK) return rc;
+      if ((rc = grow(&w.ectr[i], &c, seg_cap)) != TSQS_OK) return rc;
+    }
+    w.seg_cap = seg_cap;
+  }
+  if ((rc = grow(&w.fin, &w.fin_cap, fin_cap)) != TSQS_OK) return rc;
+  if (h_offs) {
+    if ((rc = grow(&w.offs, &w.off_cap, nroots + 1)) != TSQS_OK) return rc;
+    HIPCHK(hipMemcpyAsync(w.offs, h_offs, (nroots + 1) * sizeof(uint64_t), hipMemcpyHostToDevice, s));
+  }
+  if (g_opt.timing && !w.ev_ok) {
+    for (int i = 0; i < 2 * kMaxLevels; i++) HIPCHK(hipEventCreate(&w.ev[i]));
+    w.ev_ok = true;
+  }
+
+  Ctx c;
+  c.K = keys; c.S = w.S;
+  c.V = vals; c.VS = w.VS; c.VE = w.VE;
+  c.seg0 = w.seg[0]; c.seg1 = w.seg[1];
+  c.ctr0 = w.ctr[0]; c.ctr1 = w.ctr[1];
+  c.ectr0 = w.ectr[0]; c.ectr1 = w.ectr[1];
+  c.fin = w.fin; c.lvl = w.lvl; c.st = w.st;
+  c.roots = h_offs ? w.offs : nullptr;
+  c.n = n;
+  c.nroots = (uint32_t)nroots;
+  c.small_max = small_max;
+  c.samples = (uint32_t)g_opt.samples;
+  c.depth_factor = (uint32_t)g_opt.depth_factor;
+  c.pivot_mode = (uint32_t)g_opt.pivot_mode;
+  c.jitter = mix32((uint64_t)g_opt.seed + (g_calls++));
+  c.seg_cap = (uint32_t)seg_cap;
+  c.fin_cap = (uint32_t)fin_cap;
+
+  const int part_grid = g_opt.part_grid > 0 ? (int)g_opt.part_grid : 8 * w.cus;
+  const int fin_grid = g_opt.finish_grid > 0 ? (int)g_opt.finish_grid : 4 * w.cus;
+  int plan_grid = 4 * w.cus;
+  uint32_t P = 1;
+  while (P < small_max) P <<= 1;
+  const size_t fin_lds = (size_t)P * sizeof(typename Rec<B, HASV>::T);
+  int init_grid = (int)(nroots < (size_t)(8 * w.cus) ? nroots : (size_t)(8 * w.cus));
+  if (init_grid < 1) init_grid = 1;
+
+  hipLaunchKernelGGL(k_reset, dim3(1), dim3(256), 0, s, c);
+  hipLaunchKernelGGL((k_init<DT, HASV>), dim3(init_grid), dim3(kPlanWG), 0, s, c);
+  HIPCHK(hipGetLastError());
+
+  uint32_t expected = ceil_log2((max_root + small_max - 1) / small_max) + 2;
+  int d = 0, target = (int)expected;
+  if (target > kMaxLevels - 1) target = kMaxLevels - 1;
+  for (;;) {
+    for (; d < target; d++) {
+      if (g_opt.timing) HIPCHK(hipEventRecord(w.ev[2 * d], s));
+      hipLaunchKernelGGL((k_partition<DT, HASV>), dim3(part_grid), dim3(kPartWG), 0, s, c, d);
+      if (g_opt.timing) HIPCHK(hipEventRecord(w.ev[2 * d + 1], s));
+      hipLaunchKernelGGL((k_plan<DT, HASV>), dim3(plan_grid), dim3(kPlanWG), 0, s, c, d);
+      hipLaunchKernelGGL((k_finish<DT, HASV>), dim3(fin_grid), dim3(kFinWG), fin_lds, s, c, d);
+      HIPCHK(hipGetLastError());
+    }
+    HIPCHK(hipMemcpyAsync(w.h_lvl, w.lvl, sizeof(LevelCtl) * (size_t)(d + 1), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(w.h_st, w.st, sizeof(DevStats), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (w.h_st->err) return TSQS_EINTERNAL;
+    if ((w.h_lvl[d].packed >> 40) == 0) break;
+    if (d >= kMaxLevels - 1) return TSQS_EINTERNAL;
+    target = d + 8 < kMaxLevels - 1 ? d + 8 : kMaxLevels - 1;
+  }
+
+  tsqs_stats_t &st = g_stats;
+  std::memset(&st, 0, sizeof st);
+  st.levels = (uint32_t)d;
+  st.max_depth = w.h_st->max_depth;
+  st.n = n;
+  st.key_bytes = (uint32_t)kb;
+  st.payload_bytes = HASV ? 4u : 0u;
+  st.fallback_parts = w.h_st->fallback_parts;
+  st.small_parts = w.h_st->small_parts;
+  st.small_keys = w.h_st->small_keys;
+  st.band_keys = w.h_st->band_keys;
+  for (int i = 0; i < d && i < TSQS_MAX_LEVELS; i++) {
+    st.level_keys[i] = w.h_lvl[i].keys;
+    st.level_parts[i] = (uint32_t)(w.h_lvl[i].packed >> 40);
+    st.partition_bytes += 2ull * w.h_lvl[i].keys * (kb + (HASV ? 4 : 0));
+    if (w.h_lvl[i].keys) st.partition_launches++;
+    if (g_opt.timing) {
+      float ms = 0.f;
+      HIPCHK(hipEventElapsedTime(&ms, w.ev[2 * i], w.ev[2 * i + 1]));
+      st.level_ms[i] = ms;
+      st.partition_ms += ms;
+    }
+  }
+  g_have_stats = true;
+  return TSQS_OK;
+}
+
+int dispatch(void *keys, uint32_t *vals, const uint64_t *h_offs, size_t nroots, uint64_t n,
+             uint64_t max_root, int dt, hipStream_t s) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  if (dev < 0) return TSQS_EDEVICE;
+  if ((size_t)dev >= g_ws.size()) g_ws.resize((size_t)dev + 1);
+  Workspace &w = g_ws[(size_t)dev];
+  int rc = ensure_static(w, dev);
+  if (rc != TSQS_OK) return rc;
+  g_have_stats = false;
+  const bool hv = vals != nullptr;
+  switch (dt) {
+    case TSQS_INT32: return hv ? run_t<0, true>(w, keys, vals, h_offs, nroots, n, max_root, s)
+                               : run_t<0, false>(w, keys, vals, h_offs, nroots, n, max_root, s);
+    case TSQS_UINT32: return hv ? run_t<1, true>(w, keys, vals, h_offs, nroots, n, max_root, s)
+                                : run_t<1, false>(w, keys, vals, h_offs, nroots, n, max_root, s);
+    case TSQS_INT64: return hv ? run_t<2, true>(w, keys, vals, h_offs, nroots, n, max_root, s)
+                               : run_t<2, false>(w, keys, vals, h_offs, nroots, n, max_root, s);
+    case TSQS_UINT64: return hv ? run_t<3, true>(w, keys, vals, h_offs, nroots, n, max_root, s)
+                                : run_t<3, false>(w, keys, vals, h_offs, nroots, n, max_root, s);
+    case TSQS_FLOAT32: return hv ? run_t<4, true>(w, keys, vals, h_offs, nroots, n, max_root, s)
+                                 : run_t<4, false>(w, keys, vals, h_offs, nroots, n, max_root, s);
+    default: return TSQS_EUNSUPPORTED;
+  }
+}
+
+bool dtype_ok(int dt) { return dt >= TSQS_INT32 && dt <= TSQS_FLOAT32; }
+
+}  // namespace
+
+extern "C" {
+
+int tsqs_sort(void *d_keys, size_t nmemb, int dt, void *stream) {
+  if (!dtype_ok(dt)) return TSQS_EUNSUPPORTED;
+  if (nmemb <= 1) return TSQS_OK;
+  if (!d_keys) return TSQS_EINVAL;
+  if (nmemb > 0xFFFFFFFFull) return TSQS_EINVAL;
+  return dispatch(d_keys, nullptr, nullptr, 1, (uint64_t)nmemb, (uint64_t)nmemb, dt,
+                  (hipStream_t)stream);
+}
+
+int tsqs_sort_pairs(void *d_keys, uint32_t *d_vals, size_t nmemb, int dt, void *stream) {
+  if (!dtype_ok(dt)) return TSQS_EUNSUPPORTED;
+  if (nmemb <= 1) return TSQS_OK;
+  if (!d_keys || !d_vals) return TSQS_EINVAL;
+  if (nmemb > 0xFFFFFFFFull) return TSQS_EINVAL;
+  return dispatch(d_keys, d_vals, nullptr, 1, (uint64_t)nmemb, (uint64_t)nmemb, dt,
+                  (hipStream_t)stream);
+}
+
+int tsqs_sort_batch(void *d_keys, uint32_t *d_vals, const uint64_t *h_offsets, size_t nseg,
+                    int dt, void *stream) {
+  if (!dtype_ok(dt)) return TSQS_EUNSUPPORTED;
+  if (nseg == 0) return TSQS_OK;
+  if (!h_offsets) return TSQS_EINVAL;
+  if (nseg >= (1ull << 24)) return TSQS_EINVAL;
+  if (h_offsets[0] != 0) return TSQS_EINVAL;
+  uint64_t max_root = 0;
+  for (size_t j = 0; j < nseg; j++) {
+    if (h_offsets[j + 1] < h_offsets[j]) return TSQS_EINVAL;
+    uint64_t len = h_offsets[j + 1] - h_offsets[j];
+    if (len > 0xFFFFFFFFull) return TSQS_EINVAL;
+    if (len > max_root) max_root = len;
+  }
+  const uint64_t total = h_offsets[nseg];
+  if (max_root <= 1) return TSQS_OK;
+  if (!d_keys) return TSQS_EINVAL;
+  return dispatch(d_keys, d_vals, h_offsets, nseg, total, max_root, dt, (hipStream_t)stream);
+}
+
+void tsqs_free_storage(void) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  int cur = 0;
+  if (hipGetDevice(&cur) != hipSuccess) cur = -1;
+  for (size_t i = 0; i < g_ws.size(); i++) {
+    if (!g_ws[i].init) continue;
+    if (hipSetDevice((int)i) != hipSuccess) continue;
+    (void)hipDeviceSynchronize();
+    free_ws(g_ws[i]);
+  }
+  if (cur >= 0) (void)hipSetDevice(cur);
+  g_ws.clear();
+}
+
+int tsqs_set_option(int key, int64_t v) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  switch (key) {
+    case TSQS_OPT_SMALL_MAX: if (v < 16 || v > 8192) return TSQS_EINVAL; g_opt.small_max = v; return TSQS_OK;
+    case TSQS_OPT_SAMPLES: if (v < 3 || v > 63 || !(v & 1)) return TSQS_EINVAL; g_opt.samples = v; return TSQS_OK;
+    case TSQS_OPT_DEPTH_FACTOR: if (v < 1 || v > 4) return TSQS_EINVAL; g_opt.depth_factor = v; return TSQS_OK;
+    case TSQS_OPT_PIVOT_MODE: if (v < 0 || v > 1) return TSQS_EINVAL; g_opt.pivot_mode = v; return TSQS_OK;
+    case TSQS_OPT_SEED: g_opt.seed = v; return TSQS_OK;
+    case TSQS_OPT_TIMING: g_opt.timing = v ? 1 : 0; return TSQS_OK;
+    case TSQS_OPT_PART_GRID: if (v < 0 || v > 65536) return TSQS_EINVAL; g_opt.part_grid = v; return TSQS_OK;
+    case TSQS_OPT_FINISH_GRID: if (v < 0 || v > 65536) return TSQS_EINVAL; g_opt.finish_grid = v; return TSQS_OK;
+    default: return TSQS_EUNSUPPORTED;
+  }
+}
+
+int64_t tsqs_get_option(int key) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  switch (key) {
+    case TSQS_OPT_SMALL_MAX: return g_opt.small_max;
+    case TSQS_OPT_SAMPLES: return g_opt.samples;
+    case TSQS_OPT_DEPTH_FACTOR: return g_opt.depth_factor;
+    case TSQS_OPT_PIVOT_MODE: return g_opt.pivot_mode;
+    case TSQS_OPT_SEED: return g_opt.seed;
+    case TSQS_OPT_TIMING: return g_opt.timing;
+    case TSQS_OPT_PART_GRID: return g_opt.part_grid;
+    case TSQS_OPT_FINISH_GRID: return g_opt.finish_grid;
+    default: return INT64_MIN;
+  }
+}
+
+int tsqs_get_stats(tsqs_stats_t *out) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  if (!out) return TSQS_EINVAL;
+  if (!g_have_stats) return TSQS_EINVAL;
+  *out = g_stats;
+  return TSQS_OK;
+}
+
+const char *tsqs_strerror(int code) {
+  switch (code) {
+    case TSQS_OK: return "success";
+    case TSQS_EINVAL: return "invalid argument";
+    case TSQS_ENOMEM: return "device workspace allocation failed";
+    case TSQS_EDEVICE: return "HIP runtime error";
+    case TSQS_EUNSUPPORTED: return "unsupported dtype or option";
+    case TSQS_EINTERNAL: return "internal capacity or level limit exceeded";
+    default: return "unknown error code";
+  }
+}
+
+int tsqs_version(void) { return 1; }
+
+}  // extern "C"

@@ -1,0 +1,118 @@
+"""The C ABI library loads, exports every function include/tsqs.h declares, and
+rejects bad arguments before making any HIP call (so this runs without a GPU)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    import paper_1505_00558_amd as tsqs
+    if not os.path.exists(tsqs.LIB_PATH):
+        from paper_1505_00558_amd import build
+        build.build()
+    return tsqs.load_library()
+
+
+def _declared():
+    with open(os.path.join(ROOT, "include", "tsqs.h")) as f:
+        txt = f.read()
+    return sorted(set(re.findall(r"\b(tsqs_[a-z_]+)\s*\(", txt)))
+
+
+def test_header_declares_the_api():
+    names = _declared()
+    for n in ("tsqs_sort", "tsqs_sort_pairs", "tsqs_sort_batch", "tsqs_free_storage",
+              "tsqs_set_option", "tsqs_get_option", "tsqs_get_stats", "tsqs_strerror"):
+        assert n in names
+
+
+def test_exports_every_declared_symbol(lib):
+    import paper_1505_00558_amd as tsqs
+    for n in _declared():
+        assert hasattr(lib, n), n
+    assert sorted(tsqs.SYMBOLS) == _declared()
+
+
+def test_version_and_strerror(lib):
+    assert lib.tsqs_version() == 1
+    import paper_1505_00558_amd as tsqs
+    for code in (0, -1, -2, -3, -4, -5):
+        assert tsqs.strerror(code) and tsqs.strerror(code) != "unknown error code"
+    assert tsqs.strerror(-99) == "unknown error code"
+
+
+def test_sort_argument_errors(lib):
+    fake = ctypes.c_void_p(0x1000)
+    assert lib.tsqs_sort(None, 5, 0, None) == -1
+    assert lib.tsqs_sort(None, 0, 0, None) == 0
+    assert lib.tsqs_sort(None, 1, 0, None) == 0
+    assert lib.tsqs_sort(fake, 5, 9, None) == -4
+    assert lib.tsqs_sort(fake, 5, -1, None) == -4
+    assert lib.tsqs_sort(fake, 1 << 32, 0, None) == -1
+    assert lib.tsqs_sort_pairs(fake, None, 5, 0, None) == -1
+    assert lib.tsqs_sort_pairs(None, fake, 5, 0, None) == -1
+    assert lib.tsqs_sort_pairs(fake, fake, 1 << 32, 2, None) == -1
+    assert lib.tsqs_sort_pairs(None, None, 1, 4, None) == 0
+
+
+def _offs(vals):
+    arr = (ctypes.c_uint64 * len(vals))(*vals)
+    return ctypes.cast(arr, ctypes.c_void_p), arr
+
+
+def test_batch_argument_errors(lib):
+    fake = ctypes.c_void_p(0x1000)
+    p, keep = _offs([1, 5])
+    assert lib.tsqs_sort_batch(fake, None, p, 1, 0, None) == -1        # offsets[0] != 0
+    p, keep = _offs([0, 5, 3])
+    assert lib.tsqs_sort_batch(fake, None, p, 2, 0, None) == -1        # decreasing
+    p, keep = _offs([0, 1 << 32])
+    assert lib.tsqs_sort_batch(fake, None, p, 1, 0, None) == -1        # array too long
+    assert lib.tsqs_sort_batch(fake, None, None, 3, 0, None) == -1     # no offsets
+    p, keep = _offs([0, 1, 2, 2])
+    assert lib.tsqs_sort_batch(None, None, p, 3, 0, None) == 0         # all arrays <= 1
+    assert lib.tsqs_sort_batch(fake, None, None, 0, 0, None) == 0      # no arrays
+    p, keep = _offs([0, 5])
+    assert lib.tsqs_sort_batch(None, None, p, 1, 0, None) == -1        # null keys
+    assert lib.tsqs_sort_batch(fake, None, p, 1, 7, None) == -4
+
+
+def test_options(lib):
+    import paper_1505_00558_amd as tsqs
+    old = tsqs.get_option(tsqs.OPT_SMALL_MAX)
+    try:
+        assert lib.tsqs_set_option(tsqs.OPT_SMALL_MAX, 8) == -1
+        assert lib.tsqs_set_option(tsqs.OPT_SMALL_MAX, 1 << 20) == -1
+        assert lib.tsqs_set_option(tsqs.OPT_SMALL_MAX, 1024) == 0
+        assert tsqs.get_option(tsqs.OPT_SMALL_MAX) == 1024
+        assert lib.tsqs_set_option(tsqs.OPT_SAMPLES, 4) == -1          # must be odd
+        assert lib.tsqs_set_option(tsqs.OPT_SAMPLES, 65) == -1
+        assert lib.tsqs_set_option(tsqs.OPT_PIVOT_MODE, 2) == -1
+        assert lib.tsqs_set_option(999, 1) == -4
+        assert tsqs.get_option(999) == -(1 << 63)
+    finally:
+        tsqs.set_option(tsqs.OPT_SMALL_MAX, old)
+
+
+def test_stats_before_any_sort(lib):
+    import paper_1505_00558_amd as tsqs
+    s = tsqs.Stats()
+    assert lib.tsqs_get_stats(None) == -1
+    # no successful call yet in this process: nothing to report
+    assert lib.tsqs_get_stats(ctypes.byref(s)) in (0, -1)
+
+
+def test_product_path_has_no_oracle_import():
+    """The library package neither imports the oracle nor carries a CPU sort."""
+    pkg = os.path.join(ROOT, "paper_1505_00558_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for fn in files:
+            if fn.endswith((".py", ".hip", ".hpp", ".cpp", ".h")):
+                with open(os.path.join(dirpath, fn)) as f:
+                    txt = f.read()
+                assert "oracle" not in txt, fn
