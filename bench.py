@@ -1,0 +1,265 @@
+"""Benchmark of the three-way partition sort on one MI355X.
+
+Default workload (one JSON line on stdout): 2^28 int32 keys in each of seven
+seeded families (uniform, sorted, reversed, nearly sorted, many equals, stair
+steps, organ pipe).  One step = for each family, restore the pristine keys
+(device-to-device copy) and sort them in place with ``tsqs_sort``.  ``value`` is
+keys sorted per second over the timed steps (restores included, inputs already
+resident in HBM).
+
+``roofline`` covers the dominant kernel, the partition pass: its algorithmic
+bytes (2 x keys partitioned x bytes per key, summed over every partition launch
+of the timed steps) over its summed duration, measured by the library with HIP
+events on the sorting stream (``TSQS_OPT_TIMING``), against the 8 TB/s HBM peak.
+``traffic`` is the measured HBM bytes per launch from the committed rocprofv3
+counter summary when it was taken on the current kernel source, else null.
+
+``cpu_baseline`` times the CPU oracle (single-threaded Triple State QuickSort)
+on a bounded sample of the same workload.
+
+Other workloads (``--workload``): plain1m, pairs64, float32, batch, serve; each
+prints its own JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "sorted keys/sec + HBM roofline fraction (2^28 int32); batched p50/p99 latency"
+PEAK_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "partition_traffic.json")
+KERNEL_SRC = os.path.join(ROOT, "paper_1505_00558_amd", "csrc", "tsqs_kernels.hpp")
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_hash() -> str:
+    with open(KERNEL_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def measured_traffic(workload: str):
+    """Per-launch HBM bytes of the partition kernel from the committed counter
+    summary, only if it was taken on this kernel source and workload."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_sha") != kernel_hash() or t.get("workload") != workload:
+        return None
+    return t.get("bytes_per_launch")
+
+
+def cpu_baseline(families, n_sample: int, dtype="int32"):
+    """The oracle (single-threaded) on n_sample keys of each family."""
+    import oracle
+    oracle.build(force=not os.path.exists(oracle.LIB_PATH))
+    import tsqs_inputs as ti
+    tot_keys, tot_s = 0, 0.0
+    for fam in families:
+        k = ti.family(fam, n_sample, dtype, seed=ti.seed_for(2, fam))
+        t0 = time.perf_counter()
+        oracle.sort(k)
+        tot_s += time.perf_counter() - t0
+        tot_keys += n_sample
+    return {"value": tot_keys / tot_s, "unit": "keys/s", "cores": 1, "kind": "oracle",
+            "sample": "%d families x %d %s keys, one single-threaded oracle sort each "
+                      "(%.1f s of CPU work)" % (len(families), n_sample, dtype, tot_s)}
+
+
+def to_dev(a):
+    import torch
+    sig = {4: np.int32, 8: np.int64}[a.dtype.itemsize] if a.dtype != np.float32 else np.float32
+    return torch.from_numpy(np.ascontiguousarray(a).view(sig)).to("cuda:0")
+
+
+CODES = {"int32": 0, "uint32": 1, "int64": 2, "uint64": 3, "float32": 4}
+
+
+def run_single_arrays(args, workload, arrays, dtype, with_vals, config):
+    """Time steps of sorting each array once (restore + sort per array)."""
+    import torch
+    import paper_1505_00558_amd as tsqs
+    tsqs.load_library()
+    dt = CODES[dtype]
+    pristine = [to_dev(a) for a in arrays]
+    n_max = max(a.size for a in arrays)
+    work = torch.empty(n_max, dtype=pristine[0].dtype, device="cuda:0")
+    vals0 = vals = None
+    if with_vals:
+        vals0 = torch.arange(n_max, dtype=torch.int32, device="cuda:0")
+        vals = torch.empty_like(vals0)
+    torch.cuda.synchronize()
+
+    def one_step(timing_acc=None):
+        for i, p in enumerate(pristine):
+            w = work[:p.numel()]
+            w.copy_(p)
+            if with_vals:
+                v = vals[:p.numel()]
+                v.copy_(vals0[:p.numel()])
+            ev0 = torch.cuda.Event(enable_timing=True)
+            ev1 = torch.cuda.Event(enable_timing=True)
+            ev0.record()
+            if with_vals:
+                tsqs.sort_pairs(w, v, dt)
+            else:
+                tsqs.sort(w, dt)
+            ev1.record()
+            if timing_acc is not None:
+                st = tsqs.get_stats()
+                timing_acc.append((i, ev0, ev1, st))
+
+    for _ in range(args.warmup):
+        one_step()
+    tsqs.set_option(tsqs.OPT_TIMING, 1)
+    acc = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        one_step(acc)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    tsqs.set_option(tsqs.OPT_TIMING, 0)
+
+    total_keys = args.steps * sum(a.size for a in arrays)
+    per = {}
+    part_ms = part_bytes = 0.0
+    launches = 0
+    sort_ms_total = 0.0
+    levels = []
+    for i, e0, e1, st in acc:
+        ms = e0.elapsed_time(e1)
+        sort_ms_total += ms
+        name = config["families"][i] if "families" in config else str(i)
+        d = per.setdefault(name, {"sort_ms": [], "levels": st["levels"],
+                                  "fallback_parts": st["fallback_parts"]})
+        d["sort_ms"].append(ms)
+        part_ms += st["partition_ms"]
+        part_bytes += st["partition_bytes"]
+        launches += st["partition_launches"]
+        levels.append(st["levels"])
+    for name, d in per.items():
+        ms = float(np.median(d["sort_ms"]))
+        n = arrays[config["families"].index(name)].size if "families" in config else arrays[int(name)].size
+        d["sort_ms"] = round(ms, 3)
+        d["keys_per_s"] = n / (ms / 1e3)
+    achieved = (part_bytes / (part_ms / 1e3)) / 1e9 if part_ms > 0 else None
+    roofline = {"bound": "hbm", "achieved": achieved, "peak": PEAK_GBS, "unit": "GB/s",
+                "frac": (achieved / PEAK_GBS) if achieved else None,
+                "traffic": measured_traffic(workload),
+                "kernel": "tsqs::k_partition",
+                "launches": launches,
+                "avg_launch_ms": part_ms / max(launches, 1),
+                "algorithmic_bytes_per_launch": part_bytes / max(launches, 1)}
+    out = {
+        "metric": METRIC,
+        "value": total_keys / wall,
+        "unit": "keys/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": dtype,
+        "data": "synthetic",
+        "config": config,
+        "roofline": roofline,
+        "sort_only_keys_per_s": total_keys / (sort_ms_total / 1e3),
+        "per_family": per,
+    }
+    return out
+
+
+def workload_large(args):
+    import tsqs_inputs as ti
+    n = 1 << args.log2n
+    fams = ti.FAMILIES if args.families == "all" else args.families.split(",")
+    log("generating %d families x %d int32 keys" % (len(fams), n))
+    arrays = [ti.family(f, n, "int32", seed=ti.seed_for(2, f)) for f in fams]
+    config = {"workload": "large single sort: 2^%d int32 keys in each of %d families, one "
+                          "in-place sort per family per step" % (args.log2n, len(fams)),
+              "n": n, "families": fams, "key": "int32", "payload": None}
+    out = run_single_arrays(args, "large_2^%d_int32" % args.log2n, arrays, "int32", False, config)
+    if not args.no_cpu_baseline:
+        log("cpu baseline")
+        out["cpu_baseline"] = cpu_baseline(fams, 1 << args.cpu_log2n)
+    return out
+
+
+def workload_plain1m(args):
+    import tsqs_inputs as ti
+    k = ti.family("uniform", 1000000, "int32", seed=ti.seed_for(1, "uniform"))
+    config = {"workload": "plain single array: 1,000,000 uniform int32 keys", "n": 1000000,
+              "families": ["uniform"], "key": "int32", "payload": None}
+    out = run_single_arrays(args, "plain1m", [k], "int32", False, config)
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(["uniform"], 1000000)
+    return out
+
+
+def workload_pairs64(args):
+    import tsqs_inputs as ti
+    n = 1 << 27
+    arrays = [ti.family("uniform", n, "uint64", seed=ti.seed_for(3, 0)),
+              ti.distinct10_u64(ti.seed_for(3, 1), n)]
+    config = {"workload": "2^27 uint64 keys + uint32 payload (index): uniform and 10%-distinct",
+              "n": n, "families": ["uniform", "distinct10"], "key": "uint64", "payload": "uint32"}
+    return run_single_arrays(args, "pairs64", arrays, "uint64", True, config)
+
+
+def workload_float32(args):
+    import tsqs_inputs as ti
+    n = 1 << 27
+    arrays = [ti.special_float32(ti.seed_for(3, 2), n)]
+    config = {"workload": "2^27 float32 N(0,1) keys with 0.1% each of -0.0, +0.0, +inf, -inf, NaN",
+              "n": n, "families": ["normal_specials"], "key": "float32", "payload": None}
+    return run_single_arrays(args, "float32", arrays, "float32", False, config)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="large",
+                    choices=["large", "plain1m", "pairs64", "float32", "batch", "serve"])
+    ap.add_argument("--log2n", type=int, default=28)
+    ap.add_argument("--families", default="all")
+    ap.add_argument("--cpu-log2n", type=int, default=23)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py: this build runs on one GPU only; --gpus %d is not supported "
+              "(run with --gpus 1)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+    import torch
+    if not torch.cuda.is_available():
+        print("bench.py: no GPU", file=sys.stderr)
+        sys.exit(1)
+    fn = {"large": workload_large, "plain1m": workload_plain1m, "pairs64": workload_pairs64,
+          "float32": workload_float32}.get(args.workload)
+    if fn is None:
+        import bench_batch
+        fn = {"batch": bench_batch.workload_batch, "serve": bench_batch.workload_serve}[args.workload]
+    out = fn(args)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

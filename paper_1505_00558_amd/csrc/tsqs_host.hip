@@ -39,18 +39,18 @@ struct Workspace {
   void *S = nullptr;
   size_t v_cap = 0;
   uint32_t *VS = nullptr, *VE = nullptr;
+  size_t lds_budget = 0;
   size_t seg_cap = 0;
   Seg *seg[2] = {nullptr, nullptr};
   unsigned long long *ctr[2] = {nullptr, nullptr};
-  unsigned int *ectr[2] = {nullptr, nullptr};
-  size_t fin_cap = 0;
-  FinItem *fin = nullptr;
+  size_t slot_cap = 0, band_cap = 0, big_cap = 0;
+  FinItem *fin = nullptr, *finw = nullptr, *band = nullptr, *big = nullptr;
   LevelCtl *lvl = nullptr;
-  DevStats *st = nullptr;
+  unsigned long long *stats = nullptr;   // kStripes x kStatWords, then one word of error flags
   size_t off_cap = 0;
   uint64_t *offs = nullptr;
-  LevelCtl *h_lvl = nullptr;   // pinned
-  DevStats *h_st = nullptr;    // pinned
+  LevelCtl *h_lvl = nullptr;             // pinned
+  unsigned long long *h_stats = nullptr; // pinned
   hipEvent_t ev[2 * kMaxLevels];
   bool ev_ok = false;
 };
@@ -81,9 +81,10 @@ int grow(T **p, size_t *cap, size_t need, size_t elem = sizeof(T)) {
 
 void free_ws(Workspace &w) {
   (void)hipFree(w.S); (void)hipFree(w.VS); (void)hipFree(w.VE);
-  for (int i = 0; i < 2; i++) { (void)hipFree(w.seg[i]); (void)hipFree(w.ctr[i]); (void)hipFree(w.ectr[i]); }
-  (void)hipFree(w.fin); (void)hipFree(w.lvl); (void)hipFree(w.st); (void)hipFree(w.offs);
-  (void)hipHostFree(w.h_lvl); (void)hipHostFree(w.h_st);
+  for (int i = 0; i < 2; i++) { (void)hipFree(w.seg[i]); (void)hipFree(w.ctr[i]); }
+  (void)hipFree(w.fin); (void)hipFree(w.finw); (void)hipFree(w.band); (void)hipFree(w.big);
+  (void)hipFree(w.lvl); (void)hipFree(w.stats); (void)hipFree(w.offs);
+  (void)hipHostFree(w.h_lvl); (void)hipHostFree(w.h_stats);
   if (w.ev_ok) for (int i = 0; i < 2 * kMaxLevels; i++) (void)hipEventDestroy(w.ev[i]);
   w = Workspace();
 }
@@ -93,15 +94,17 @@ int ensure_static(Workspace &w, int dev) {
   hipDeviceProp_t prop;
   HIPCHK(hipGetDeviceProperties(&prop, dev));
   w.cus = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
+  w.lds_budget = prop.sharedMemPerBlock > 0 ? (size_t)prop.sharedMemPerBlock : 65536;
   if (hipMalloc(&w.lvl, sizeof(LevelCtl) * kMaxLevels) != hipSuccess) return TSQS_ENOMEM;
-  if (hipMalloc(&w.st, sizeof(DevStats)) != hipSuccess) return TSQS_ENOMEM;
+  const size_t stat_bytes = sizeof(unsigned long long) * (kStripes * kStatWords + 16);
+  if (hipMalloc(&w.stats, stat_bytes) != hipSuccess) return TSQS_ENOMEM;
   if (hipHostMalloc(&w.h_lvl, sizeof(LevelCtl) * kMaxLevels, hipHostMallocDefault) != hipSuccess) return TSQS_ENOMEM;
-  if (hipHostMalloc(&w.h_st, sizeof(DevStats), hipHostMallocDefault) != hipSuccess) return TSQS_ENOMEM;
+  if (hipHostMalloc(&w.h_stats, stat_bytes, hipHostMallocDefault) != hipSuccess) return TSQS_ENOMEM;
   w.init = true;
   return TSQS_OK;
 }
 
-uint32_t small_max_limit(size_t kb, bool hasv) { return (kb == 8 && hasv) ? 4096u : 8192u; }
+size_t lds_pad_host(size_t x) { return x + (x >> 5); }
 
 uint32_t ceil_log2(uint64_t x) {
   uint32_t l = 0;
@@ -120,15 +123,22 @@ template <int DT, bool HASV>
 int run_t(Workspace &w, void *keys, uint32_t *vals, const uint64_t *h_offs, size_t nroots,
           uint64_t n, uint64_t max_root, hipStream_t s) {
   using B = typename Codec<DT>::B;
+  using RT = typename Rec<B, HASV>::T;
   const size_t kb = sizeof(B);
+  if (((uintptr_t)keys % kb) != 0 || ((uintptr_t)vals % 4) != 0) return TSQS_EINVAL;
+  // small parts: one wave up to wave_max keys, the workgroup up to 8192, within LDS
+  uint32_t wave_max = 1024;
+  while (wave_max > 64 && kFinNW * lds_pad_host(wave_max) * sizeof(RT) > w.lds_budget) wave_max >>= 1;
+  uint32_t wg_max = 8192;
+  while (wg_max > wave_max && lds_pad_host(wg_max) * sizeof(RT) > w.lds_budget) wg_max >>= 1;
   uint32_t small_max = (uint32_t)g_opt.small_max;
-  const uint32_t lim = small_max_limit(kb, HASV);
-  if (small_max > lim) small_max = lim;
+  if (small_max > wg_max) small_max = wg_max;
   if (small_max < 16) small_max = 16;
 
   // workspace sizes
   const size_t seg_cap = (size_t)(n / (small_max + 1)) + 2;
-  const size_t fin_cap = 3 * seg_cap + (size_t)(n / kBandChunk) + nroots + 16;
+  const size_t slot_cap = 2 * seg_cap + nroots;
+  const size_t big_cap = 2 * (size_t)(n / kBandChunk) + 16;
   int rc;
   {
     size_t cap_bytes = w.s_bytes;
@@ -144,14 +154,20 @@ int run_t(Workspace &w, void *keys, uint32_t *vals, const uint64_t *h_offs, size
   }
   if (w.seg_cap < seg_cap) {
     for (int i = 0; i < 2; i++) {
-      size_t a = w.seg_cap, b = w.seg_cap, c = w.seg_cap;
+      size_t a = w.seg_cap, b = w.seg_cap * kCtrStride;
       if ((rc = grow(&w.seg[i], &a, seg_cap)) != TSQS_OK) return rc;
-      if ((rc = grow(&w.ctr[i], &b, seg_cap)) != TSQS_OK) return rc;
-      if ((rc = grow(&w.ectr[i], &c, seg_cap)) != TSQS_OK) return rc;
+      if ((rc = grow(&w.ctr[i], &b, seg_cap * kCtrStride)) != TSQS_OK) return rc;
     }
     w.seg_cap = seg_cap;
   }
-  if ((rc = grow(&w.fin, &w.fin_cap, fin_cap)) != TSQS_OK) return rc;
+  if (w.slot_cap < slot_cap) {
+    size_t a = w.slot_cap, b = w.slot_cap;
+    if ((rc = grow(&w.fin, &a, slot_cap)) != TSQS_OK) return rc;
+    if ((rc = grow(&w.finw, &b, slot_cap)) != TSQS_OK) return rc;
+    w.slot_cap = slot_cap;
+  }
+  if ((rc = grow(&w.band, &w.band_cap, seg_cap)) != TSQS_OK) return rc;
+  if ((rc = grow(&w.big, &w.big_cap, big_cap)) != TSQS_OK) return rc;
   if (h_offs) {
     if ((rc = grow(&w.offs, &w.off_cap, nroots + 1)) != TSQS_OK) return rc;
     HIPCHK(hipMemcpyAsync(w.offs, h_offs, (nroots + 1) * sizeof(uint64_t), hipMemcpyHostToDevice, s));
@@ -166,48 +182,61 @@ int run_t(Workspace &w, void *keys, uint32_t *vals, const uint64_t *h_offs, size
   c.V = vals; c.VS = w.VS; c.VE = w.VE;
   c.seg0 = w.seg[0]; c.seg1 = w.seg[1];
   c.ctr0 = w.ctr[0]; c.ctr1 = w.ctr[1];
-  c.ectr0 = w.ectr[0]; c.ectr1 = w.ectr[1];
-  c.fin = w.fin; c.lvl = w.lvl; c.st = w.st;
+  c.fin = w.fin; c.finw = w.finw; c.band = w.band; c.big = w.big; c.lvl = w.lvl;
+  c.stats = w.stats;
+  c.err = (unsigned int *)(w.stats + kStripes * kStatWords);
   c.roots = h_offs ? w.offs : nullptr;
   c.n = n;
   c.nroots = (uint32_t)nroots;
   c.small_max = small_max;
+  c.wave_max = wave_max;
+  c.pad0 = 0;
   c.samples = (uint32_t)g_opt.samples;
   c.depth_factor = (uint32_t)g_opt.depth_factor;
   c.pivot_mode = (uint32_t)g_opt.pivot_mode;
   c.jitter = mix32((uint64_t)g_opt.seed + (g_calls++));
   c.seg_cap = (uint32_t)seg_cap;
-  c.fin_cap = (uint32_t)fin_cap;
+  c.big_cap = (uint32_t)big_cap;
 
-  const int part_grid = g_opt.part_grid > 0 ? (int)g_opt.part_grid : 8 * w.cus;
+  const int part_grid = g_opt.part_grid > 0 ? (int)g_opt.part_grid : 4 * w.cus;
   const int fin_grid = g_opt.finish_grid > 0 ? (int)g_opt.finish_grid : 4 * w.cus;
-  int plan_grid = 4 * w.cus;
+  const int plan_grid = 4 * w.cus;
   uint32_t P = 1;
   while (P < small_max) P <<= 1;
-  const size_t fin_lds = (size_t)P * sizeof(typename Rec<B, HASV>::T);
-  int init_grid = (int)(nroots < (size_t)(8 * w.cus) ? nroots : (size_t)(8 * w.cus));
+  size_t fin_lds = lds_pad_host(P) * sizeof(RT);
+  if (kFinNW * lds_pad_host(wave_max) * sizeof(RT) > fin_lds) fin_lds = kFinNW * lds_pad_host(wave_max) * sizeof(RT);
+  if (fin_lds > 65536) {
+    HIPCHK(hipFuncSetAttribute((const void *)k_finish<DT, HASV>,
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)fin_lds));
+  }
+  const size_t waves_init = (nroots + kPlanNW - 1) / kPlanNW;
+  int init_grid = (int)(waves_init < (size_t)(4 * w.cus) ? waves_init : (size_t)(4 * w.cus));
   if (init_grid < 1) init_grid = 1;
 
   hipLaunchKernelGGL(k_reset, dim3(1), dim3(256), 0, s, c);
-  hipLaunchKernelGGL((k_init<DT, HASV>), dim3(init_grid), dim3(kPlanWG), 0, s, c);
+  hipLaunchKernelGGL((k_init<DT, HASV>), dim3(init_grid), dim3(kPlanNT), 0, s, c);
   HIPCHK(hipGetLastError());
 
-  uint32_t expected = ceil_log2((max_root + small_max - 1) / small_max) + 2;
+  // median-of-63 splits stay within about 45/55: allow 20% more levels than a
+  // perfect halving, plus two
+  const uint32_t lv = ceil_log2((max_root + small_max - 1) / small_max);
+  uint32_t expected = lv + (lv + 4) / 5 + 2;
   int d = 0, target = (int)expected;
   if (target > kMaxLevels - 1) target = kMaxLevels - 1;
   for (;;) {
     for (; d < target; d++) {
       if (g_opt.timing) HIPCHK(hipEventRecord(w.ev[2 * d], s));
-      hipLaunchKernelGGL((k_partition<DT, HASV>), dim3(part_grid), dim3(kPartWG), 0, s, c, d);
+      hipLaunchKernelGGL((k_partition<DT, HASV>), dim3(part_grid), dim3(kPartNT), 0, s, c, d);
       if (g_opt.timing) HIPCHK(hipEventRecord(w.ev[2 * d + 1], s));
-      hipLaunchKernelGGL((k_plan<DT, HASV>), dim3(plan_grid), dim3(kPlanWG), 0, s, c, d);
-      hipLaunchKernelGGL((k_finish<DT, HASV>), dim3(fin_grid), dim3(kFinWG), fin_lds, s, c, d);
+      hipLaunchKernelGGL((k_plan<DT, HASV>), dim3(plan_grid), dim3(kPlanNT), 0, s, c, d);
+      hipLaunchKernelGGL((k_finish<DT, HASV>), dim3(fin_grid), dim3(kFinNT), fin_lds, s, c, d);
       HIPCHK(hipGetLastError());
     }
     HIPCHK(hipMemcpyAsync(w.h_lvl, w.lvl, sizeof(LevelCtl) * (size_t)(d + 1), hipMemcpyDeviceToHost, s));
-    HIPCHK(hipMemcpyAsync(w.h_st, w.st, sizeof(DevStats), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(w.h_stats, w.stats, sizeof(unsigned long long) * (kStripes * kStatWords + 1),
+                          hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
-    if (w.h_st->err) return TSQS_EINTERNAL;
+    if (*(unsigned int *)(w.h_stats + kStripes * kStatWords)) return TSQS_EINTERNAL;
     if ((w.h_lvl[d].packed >> 40) == 0) break;
     if (d >= kMaxLevels - 1) return TSQS_EINTERNAL;
     target = d + 8 < kMaxLevels - 1 ? d + 8 : kMaxLevels - 1;
@@ -216,14 +245,18 @@ int run_t(Workspace &w, void *keys, uint32_t *vals, const uint64_t *h_offs, size
   tsqs_stats_t &st = g_stats;
   std::memset(&st, 0, sizeof st);
   st.levels = (uint32_t)d;
-  st.max_depth = w.h_st->max_depth;
   st.n = n;
   st.key_bytes = (uint32_t)kb;
   st.payload_bytes = HASV ? 4u : 0u;
-  st.fallback_parts = w.h_st->fallback_parts;
-  st.small_parts = w.h_st->small_parts;
-  st.small_keys = w.h_st->small_keys;
-  st.band_keys = w.h_st->band_keys;
+  for (int i = 0; i < kStripes; i++) {
+    const unsigned long long *sp = w.h_stats + (size_t)i * kStatWords;
+    st.fallback_parts += sp[kStFallback];
+    st.small_parts += sp[kStSmallParts];
+    st.small_keys += sp[kStSmallKeys];
+    st.band_keys += sp[kStBandKeys];
+  }
+  for (int i = 0; i < d; i++)
+    if (w.h_lvl[i].packed >> 40) st.max_depth = (uint32_t)i;
   for (int i = 0; i < d && i < TSQS_MAX_LEVELS; i++) {
     st.level_keys[i] = w.h_lvl[i].keys;
     st.level_parts[i] = (uint32_t)(w.h_lvl[i].packed >> 40);

@@ -7,20 +7,30 @@
 // hole-juggling scan (SIII.A-F) is not used; on the GPU one level of the
 // recursion is one data-parallel pass over every active part:
 //
-//   k_partition  every 4096-key tile of every part at this level: coalesced
-//                loads, two compares per key on an order-preserving unsigned
-//                code, ranks from 64-lane ballots + mbcnt, an LDS prefix over
-//                (item, wave), ONE packed 64-bit atomic per tile reserving
-//                [left cursor, right cursor] in the part, and stores of the
-//                < and > keys into the other buffer (ping-pong K <-> S).
-//   k_plan       one workgroup per part just partitioned: reads the final
-//                cursors, emits the equal band, and for each child either a
-//                small-part item or a part of the next level with a pivot
-//                (median of up to 63 samples sorted inside one wave; the exact
-//                median by radix select once the depth limit is reached).
-//   k_finish     one workgroup per item: small parts are sorted in LDS by a
-//                bitonic network and written to K; band chunks write the pivot
-//                value (equality means identical bits) and the staged payloads.
+//   k_partition  every chunk of every part at this level.  A chunk is an
+//                address-aligned window of 16384 keys (8192 / 4096 for wider
+//                elements) read with 16-byte loads by a 512-thread workgroup;
+//                two compares per key on an order-preserving unsigned code;
+//                ranks from 64-lane ballots + mbcnt; an LDS prefix over
+//                (item, wave); ONE packed 64-bit atomic per chunk reserves
+//                [left cursor, right cursor] in the part (counters of
+//                different parts sit in different 128-byte lines); the < and >
+//                keys are stored into the other buffer (ping-pong K <-> S).
+//                Each workgroup takes a contiguous run of chunks, so the part
+//                of the next chunk is found by advancing, not by searching.
+//   k_plan       one wave per part just partitioned: reads the final cursors,
+//                writes the equal band and the small children into fixed slots
+//                (slot = 2 * part + side, no list atomics), and for large
+//                children picks a pivot (median of up to 63 samples sorted
+//                inside the wave; the exact median by radix select once the
+//                depth limit is reached); the workgroup then reserves all its
+//                next-level parts with one atomic.
+//   k_finish     small parts are sorted by a bitonic network held in registers
+//                (blocked layout, partner exchange by lane permutes inside a
+//                wave and through LDS across waves): one wave per part up to
+//                1024 keys, the 512-thread workgroup above; bands write the
+//                pivot value (equality means identical bits) and the staged
+//                payloads.
 //
 // Buffers: a part at depth d lives in K when d is even, in S when d is odd.
 #pragma once
@@ -31,16 +41,19 @@
 namespace tsqs {
 
 constexpr int kWave = 64;
-constexpr int kPartWG = 256;
-constexpr int kPartWaves = kPartWG / kWave;
-constexpr int kIPT = 16;                        // keys per thread per tile
-constexpr uint32_t kTile = kPartWG * kIPT;      // 4096 keys per tile
-static_assert(kIPT * kPartWaves == kWave, "one wave scans the (item, wave) counts");
-constexpr int kPlanWG = 256;
-constexpr int kFinWG = 256;
+constexpr int kPartNT = 512;
+constexpr int kPartNW = kPartNT / kWave;
+constexpr int kPlanNT = 256;
+constexpr int kPlanNW = kPlanNT / kWave;
+constexpr int kFinNT = 512;
+constexpr int kFinNW = kFinNT / kWave;
 constexpr uint32_t kBandChunk = 1u << 16;
 constexpr int kMaxLevels = 192;
 constexpr unsigned long long kTileMask = (1ull << 40) - 1;
+constexpr int kCtrStride = 16;   // u64 words between part counters: one 128-byte line each
+constexpr int kStripes = 64;     // statistics counters are spread over this many lines
+constexpr int kStatWords = 16;
+enum { kStFallback = 0, kStSmallParts = 1, kStSmallKeys = 2, kStBandKeys = 3 };
 constexpr uint32_t kErrSegCap = 1, kErrFinCap = 2, kErrLevel = 4;
 
 // ---- order-preserving codes (compares are done on these, never on floats) --
@@ -76,62 +89,76 @@ template <> struct Codec<4> {  // float32 bits, IEEE totalOrder: negatives rever
   }
 };
 
+// Geometry of the partition pass per element type.
+template <int DT, bool HASV> struct PartCfg {
+  using B = typename Codec<DT>::B;
+  static constexpr int KB = (int)sizeof(B);
+  static constexpr int VEC = 16 / KB;                                   // keys per 16-byte load
+  static constexpr int KPT = KB == 4 ? (HASV ? 16 : 32) : (HASV ? 8 : 16);  // keys per thread
+  static constexpr int NLOAD = KPT / VEC;
+  static constexpr uint64_t CH = (uint64_t)kPartNT * KPT;               // keys per chunk
+  static constexpr int NENT = KPT * kPartNW;                            // (item, wave) entries
+  static_assert(NENT % kWave == 0 && KPT <= 32, "layout");
+};
+
+
 // ---- device tables -----------------------------------------------------------
 
 struct Seg {                 // one part of a level
   uint64_t off;              // first key
   uint64_t pivot;            // encoded pivot
   uint32_t len;
-  uint32_t tile_begin;       // first tile of this part in the level's tile space
+  uint32_t chunk_begin;      // first chunk of this part in the level's chunk space
   uint32_t depth;
   uint32_t dmax;             // depth limit of the array it came from
 };
 
-struct FinItem {             // work of the finish kernel
-  uint64_t off;              // small part: first key; band chunk: first band slot
-  uint64_t src;              // band chunk: first staged payload in VE
-  uint64_t pivot;            // band chunk: encoded key of the band
+struct FinItem {             // work of the finish kernel (len 0 = empty slot)
+  uint64_t off;              // small part: first key; band: first band slot
+  uint64_t src;              // band: first staged payload in VE
+  uint64_t pivot;            // band: encoded key of the band
   uint32_t len;
-  uint32_t kind;             // bit 0: band chunk; bit 1: small part lives in S
+  uint32_t kind;             // bit 1: small part lives in S
 };
 
 struct LevelCtl {
-  unsigned long long packed; // parts << 40 | tiles of this level
+  unsigned long long packed; // parts << 40 | chunks of this level
   unsigned long long keys;   // keys in the parts of this level
-  unsigned int nfin;         // finish items emitted at this level
+  unsigned int nbig;         // chunks of bands longer than kBandChunk
   unsigned int pad0;
   unsigned long long pad1;
-};
-
-struct DevStats {
-  unsigned long long fallback_parts, small_parts, small_keys, band_keys;
-  unsigned int max_depth, err;
 };
 
 struct Ctx {
   void *K, *S;
   uint32_t *V, *VS, *VE;
   Seg *seg0, *seg1;
-  unsigned long long *ctr0, *ctr1;   // packed (left count | right count << 32)
-  unsigned int *ectr0, *ectr1;       // equal-key count (payload staging)
-  FinItem *fin;
+  unsigned long long *ctr0, *ctr1;   // per part, stride kCtrStride: [0] = L | G << 32, [1] = E
+  FinItem *fin, *finw;               // small-part slots: workgroup / wave sized
+  FinItem *band;                     // band slot per part
+  FinItem *big;                      // chunks of long bands (appended)
   LevelCtl *lvl;
-  DevStats *st;
+  unsigned long long *stats;         // kStripes x kStatWords
+  unsigned int *err;
   const uint64_t *roots;             // nroots+1 offsets, or null: one root [0, n)
   uint64_t n;
   uint32_t nroots;
   uint32_t small_max;
+  uint32_t wave_max;                 // small parts up to this padded size go to one wave
   uint32_t samples;
   uint32_t depth_factor;
   uint32_t pivot_mode;               // 0 sampled median, 1 exact minimum
   uint32_t jitter;                   // per-call sample shift
-  uint32_t seg_cap;
-  uint32_t fin_cap;
+  uint32_t seg_cap;                  // part records per level; child slots are 2 * seg_cap
+  uint32_t big_cap;
+  uint32_t pad0;
 };
 
 // ---- wave helpers ------------------------------------------------------------
 
-__device__ inline uint32_t lane_id() { return __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u)); }
+__device__ inline uint32_t lane_id() {
+  return __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
+}
 
 // number of set bits of m in lanes below this one
 __device__ inline uint32_t mbcnt(unsigned long long m) {
@@ -151,6 +178,13 @@ __device__ inline uint64_t shfl_u64(uint64_t v, int src) {
 template <typename U> __device__ inline U shfl_xor_any(U v, int m);
 template <> __device__ inline uint32_t shfl_xor_any<uint32_t>(uint32_t v, int m) { return shfl_xor_u32(v, m); }
 template <> __device__ inline uint64_t shfl_xor_any<uint64_t>(uint64_t v, int m) { return shfl_xor_u64(v, m); }
+
+// LDS ordering between the lanes of one wave (a wave-scope barrier).
+__device__ inline void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
 
 // ascending bitonic sort of one value per lane across the 64 lanes
 template <typename U>
@@ -178,12 +212,12 @@ __device__ inline uint32_t wave_incl_scan(uint32_t x) {
   return x;
 }
 
-// ---- pivot choice ----------------------------------------------------------------
+// ---- pivot choice (one wave) ---------------------------------------------------
 
 // Median of S samples (S odd, <= 63) at evenly spaced positions of Y[off, off+len);
 // interior samples (not the first, middle or last) are shifted toward the middle
 // or away from it by a per-call amount of at most a quarter spacing (the paper's
-// sample jitter against crafted inputs, SV.C).  Run by one whole wave.
+// sample jitter against crafted inputs, SV.C).
 template <int DT>
 __device__ inline typename Codec<DT>::B wave_sample_pivot(const typename Codec<DT>::B *Y,
                                                           uint64_t off, uint32_t len,
@@ -208,293 +242,456 @@ __device__ inline typename Codec<DT>::B wave_sample_pivot(const typename Codec<D
 }
 
 // Exact k-th smallest code of Y[off, off+len) by most-significant-digit radix
-// select (8-bit digits, 256-bin LDS histograms).  Whole workgroup, read-only.
-template <int DT, int NT>
-__device__ typename Codec<DT>::B wg_select(const typename Codec<DT>::B *Y, uint64_t off,
-                                           uint32_t len, uint32_t k, uint32_t *hist,
-                                           unsigned long long *bcast) {
+// select (8-bit digits, a 256-bin LDS histogram per wave).  Read-only.
+template <int DT>
+__device__ typename Codec<DT>::B wave_select(const typename Codec<DT>::B *Y, uint64_t off,
+                                             uint32_t len, uint32_t k, uint32_t *hist) {
   using B = typename Codec<DT>::B;
   constexpr int BITS = (int)sizeof(B) * 8;
+  const uint32_t lane = lane_id();
   B prefix = 0, mask = 0;
   uint32_t krem = k;
   for (int shift = BITS - 8; shift >= 0; shift -= 8) {
-    for (int i = threadIdx.x; i < 256; i += NT) hist[i] = 0;
-    __syncthreads();
-    for (uint32_t i = threadIdx.x; i < len; i += NT) {
-      B u = Codec<DT>::enc(Y[off + i]);
+    for (int i = 0; i < 4; i++) hist[lane * 4 + i] = 0;
+    wave_lds_sync();
+    for (uint32_t i = lane; i < len; i += kWave) {
+      const B u = Codec<DT>::enc(Y[off + i]);
       if ((u & mask) == prefix) atomicAdd(&hist[(uint32_t)(u >> shift) & 255u], 1u);
     }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      uint32_t acc = 0, sel = 255;
-      for (uint32_t dgt = 0; dgt < 256; dgt++) {
-        if (acc + hist[dgt] > krem) { sel = dgt; break; }
-        acc += hist[dgt];
+    wave_lds_sync();
+    uint32_t h[4], s = 0;
+    for (int i = 0; i < 4; i++) { h[i] = hist[lane * 4 + i]; s += h[i]; }
+    const uint32_t incl = wave_incl_scan(s);
+    const uint32_t excl = incl - s;
+    const bool mine = excl <= krem && krem < incl;
+    const unsigned long long bm = __ballot(mine);
+    const int src = bm ? (int)__builtin_ctzll(bm) : 63;
+    uint32_t dig = lane * 4 + 3, below = excl;
+    {
+      uint32_t acc = excl;
+      for (int i = 0; i < 4; i++) {
+        if (krem < acc + h[i]) { dig = lane * 4 + i; below = acc; break; }
+        acc += h[i];
       }
-      bcast[0] = (unsigned long long)(prefix | ((B)sel << shift));
-      bcast[1] = krem - acc;
     }
-    __syncthreads();
-    prefix = (B)bcast[0];
-    krem = (uint32_t)bcast[1];
+    dig = shfl_u32(dig, src);
+    below = shfl_u32(below, src);
+    krem -= below;
+    prefix |= (B)dig << shift;
     mask |= (B)255 << shift;
-    __syncthreads();
+    wave_lds_sync();
   }
   return prefix;
 }
 
-// Pivot of a part, computed by the whole workgroup (result in every thread).
-template <int DT>
-__device__ typename Codec<DT>::B choose_pivot(const Ctx &c, const typename Codec<DT>::B *Y,
-                                              uint64_t off, uint32_t len, uint32_t depth,
-                                              uint32_t dmax, uint32_t *hist,
-                                              unsigned long long *bcast) {
-  using B = typename Codec<DT>::B;
-  if (c.pivot_mode == 1 || depth >= dmax) {
-    uint32_t k = (c.pivot_mode == 1 && depth < dmax) ? 0u : len / 2;
-    if (threadIdx.x == 0 && depth >= dmax) atomicAdd(&c.st->fallback_parts, 1ull);
-    return wg_select<DT, kPlanWG>(Y, off, len, k, hist, bcast);
-  }
-  if (threadIdx.x < kWave) {
-    uint32_t S = c.samples;
-    if (S > len) S = (len & 1) ? len : len - 1;
-    B p = wave_sample_pivot<DT>(Y, off, len, S, c.jitter);
-    if (threadIdx.x == 0) bcast[2] = (unsigned long long)p;
-  }
-  __syncthreads();
-  B p = (B)bcast[2];
-  __syncthreads();
+
+// ---- emission ---------------------------------------------------------------------
+
+__device__ inline uint32_t next_pow2(uint32_t x) {
+  uint32_t p = 1;
+  while (p < x) p <<= 1;
   return p;
 }
 
-// ---- emission (single thread) ---------------------------------------------------
-
-template <bool HASV>
-__device__ inline void emit_part(const Ctx &c, int lvl_next, uint64_t off, uint32_t len,
-                                 uint64_t pivot, uint32_t depth, uint32_t dmax) {
-  if (lvl_next >= kMaxLevels) { atomicOr(&c.st->err, kErrLevel); return; }
-  const uint32_t tiles = (len + kTile - 1) / kTile;
-  unsigned long long old = atomicAdd(&c.lvl[lvl_next].packed, (1ull << 40) | (unsigned long long)tiles);
-  const uint32_t idx = (uint32_t)(old >> 40);
-  if (idx >= c.seg_cap) { atomicOr(&c.st->err, kErrSegCap); return; }
-  Seg s;
-  s.off = off; s.pivot = pivot; s.len = len; s.tile_begin = (uint32_t)(old & kTileMask);
-  s.depth = depth; s.dmax = dmax;
-  Seg *segs = (lvl_next & 1) ? c.seg1 : c.seg0;
-  segs[idx] = s;
-  ((lvl_next & 1) ? c.ctr1 : c.ctr0)[idx] = 0ull;
-  if (HASV) ((lvl_next & 1) ? c.ectr1 : c.ectr0)[idx] = 0u;
-  atomicAdd(&c.lvl[lvl_next].keys, (unsigned long long)len);
-  atomicMax(&c.st->max_depth, depth);
-}
-
-__device__ inline void emit_small(const Ctx &c, int level, uint64_t off, uint32_t len, bool in_s) {
-  uint32_t i = atomicAdd(&c.lvl[level].nfin, 1u);
-  if (i >= c.fin_cap) { atomicOr(&c.st->err, kErrFinCap); return; }
-  FinItem it;
-  it.off = off; it.src = 0; it.pivot = 0; it.len = len; it.kind = in_s ? 2u : 0u;
-  c.fin[i] = it;
-  atomicAdd(&c.st->small_parts, 1ull);
-  atomicAdd(&c.st->small_keys, (unsigned long long)len);
-}
-
-__device__ inline void emit_band(const Ctx &c, int level, uint64_t off, uint64_t src,
-                                 uint32_t len, uint64_t pivot) {
-  const uint32_t nch = (len + kBandChunk - 1) / kBandChunk;
-  uint32_t i0 = atomicAdd(&c.lvl[level].nfin, nch);
-  if (i0 + nch > c.fin_cap) { atomicOr(&c.st->err, kErrFinCap); return; }
-  for (uint32_t q = 0; q < nch; q++) {
-    FinItem it;
-    uint32_t base = q * kBandChunk;
-    it.off = off + base; it.src = src + base; it.pivot = pivot;
-    it.len = (len - base < kBandChunk) ? (len - base) : kBandChunk;
-    it.kind = 1u;
-    c.fin[i0 + q] = it;
-  }
-  atomicAdd(&c.st->band_keys, (unsigned long long)len);
-}
-
-// A child part of depth `depth` living in the buffer of that depth's parity:
-// small -> finish item of level `fin_level`; large -> part of level
-// `part_level` with its pivot.
+// Number of chunks of a part [off, off+len) of a buffer: chunks are aligned to
+// CH keys in the absolute (address / key size) coordinate.
 template <int DT, bool HASV>
-__device__ void handle_child(const Ctx &c, int fin_level, int part_level, uint64_t off,
-                             uint32_t len, uint32_t depth, uint32_t dmax, uint32_t *hist,
-                             unsigned long long *bcast) {
+__device__ inline uint32_t part_chunks(const void *buf, uint64_t off, uint32_t len) {
+  using Cfg = PartCfg<DT, HASV>;
+  const uint64_t a0 = (uint64_t)(uintptr_t)buf / Cfg::KB + off;
+  return (uint32_t)((a0 + len - 1) / Cfg::CH - a0 / Cfg::CH + 1);
+}
+
+
+__device__ inline void stat_add(const Ctx &c, int which, unsigned long long v) {
+  if (v) atomicAdd(&c.stats[(size_t)(blockIdx.x % kStripes) * kStatWords + which], v);
+}
+
+// Writes the small-part item of a child into its fixed slot of the wave or the
+// workgroup array and an empty item into the other (one lane).
+__device__ inline void put_small(const Ctx &c, uint32_t slot, uint64_t off, uint32_t len, bool in_s) {
+  const bool real = len > 1 || (len == 1 && in_s);
+  const bool wave = next_pow2(len) <= c.wave_max;
+  FinItem it;
+  it.off = off; it.src = 0; it.pivot = 0; it.kind = in_s ? 2u : 0u;
+  it.len = (real && wave) ? len : 0u;
+  c.finw[slot] = it;
+  it.len = (real && !wave) ? len : 0u;
+  c.fin[slot] = it;
+}
+
+// Band of a part: short bands go to the part's band slot, long ones are cut
+// into kBandChunk pieces appended to the long-band list (one lane).
+__device__ inline void put_band(const Ctx &c, int level, uint32_t si, uint64_t off, uint64_t src,
+                                uint32_t len, uint64_t pivot) {
+  FinItem it;
+  it.off = off; it.src = src; it.pivot = pivot; it.len = len <= kBandChunk ? len : 0u; it.kind = 0;
+  c.band[si] = it;
+  if (len <= kBandChunk) return;
+  const uint32_t nch = (len + kBandChunk - 1) / kBandChunk;
+  const uint32_t i0 = atomicAdd(&c.lvl[level].nbig, nch);
+  if (i0 + nch > c.big_cap) { atomicOr(c.err, kErrFinCap); return; }
+  for (uint32_t q = 0; q < nch; q++) {
+    const uint32_t base = q * kBandChunk;
+    it.off = off + base; it.src = src + base;
+    it.len = (len - base < kBandChunk) ? (len - base) : kBandChunk;
+    c.big[i0 + q] = it;
+  }
+}
+
+// Pivot of a large child (whole wave): median of samples, or the exact k-th
+// code by radix select (the depth-limit fallback, or the minimum in the test
+// mode that forces it).
+template <int DT>
+__device__ inline typename Codec<DT>::B child_pivot(const Ctx &c, uint64_t off, uint32_t len,
+                                                    uint32_t depth, uint32_t dmax, uint32_t *hist) {
   using B = typename Codec<DT>::B;
+  const B *Y = (const B *)((depth & 1) ? c.S : c.K);
+  if (c.pivot_mode == 1 || depth >= dmax) {
+    const uint32_t k = (c.pivot_mode == 1 && depth < dmax) ? 0u : len / 2;
+    if (lane_id() == 0 && depth >= dmax) stat_add(c, kStFallback, 1ull);
+    return wave_select<DT>(Y, off, len, k, hist);
+  }
+  uint32_t S = c.samples;
+  if (S > len) S = (len & 1) ? len : len - 1;
+  return wave_sample_pivot<DT>(Y, off, len, S, c.jitter);
+}
+
+// Large children found by the waves of a workgroup in one iteration, reserved
+// in the next level with a single atomic (records keep the wave order, so
+// chunk_begin stays increasing with the record index).
+struct Pending {
+  uint64_t off0, off1, pivot0, pivot1;
+  uint32_t len0, len1, chunks0, chunks1;
+  uint32_t n;
+};
+
+template <int DT, bool HASV>
+__device__ inline void flush_parts(const Ctx &c, int lvl_next, const Pending &pd, uint32_t depth,
+                                   uint32_t dmax, uint32_t *sh_n, uint32_t *sh_ch,
+                                   unsigned long long *sh_keys, unsigned long long *sh_old) {
+  const uint32_t wv = threadIdx.x / kWave, lane = threadIdx.x & 63u;
+  if (lane == 0) {
+    sh_n[wv] = pd.n;
+    sh_ch[wv] = (pd.n > 0 ? pd.chunks0 : 0u) + (pd.n > 1 ? pd.chunks1 : 0u);
+    sh_keys[wv] = (pd.n > 0 ? (unsigned long long)pd.len0 : 0ull) + (pd.n > 1 ? (unsigned long long)pd.len1 : 0ull);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t tp = 0, tc = 0;
+    unsigned long long tk = 0;
+    for (int i = 0; i < kPlanNW; i++) { tp += sh_n[i]; tc += sh_ch[i]; tk += sh_keys[i]; }
+    *sh_old = 0;
+    if (tp > 0) {
+      if (lvl_next >= kMaxLevels) {
+        atomicOr(c.err, kErrLevel);
+        *sh_old = ~0ull;
+      } else {
+        *sh_old = atomicAdd(&c.lvl[lvl_next].packed, ((unsigned long long)tp << 40) | tc);
+        atomicAdd(&c.lvl[lvl_next].keys, tk);
+      }
+    }
+  }
+  __syncthreads();
+  if (lane == 0 && pd.n > 0 && *sh_old != ~0ull) {
+    uint32_t idx = (uint32_t)(*sh_old >> 40), cb = (uint32_t)(*sh_old & kTileMask);
+    for (uint32_t i = 0; i < wv; i++) { idx += sh_n[i]; cb += sh_ch[i]; }
+    Seg *segs = (lvl_next & 1) ? c.seg1 : c.seg0;
+    unsigned long long *ctr = (lvl_next & 1) ? c.ctr1 : c.ctr0;
+#pragma unroll
+    for (uint32_t q = 0; q < 2; q++, idx++) {
+      if (q >= pd.n) break;
+      if (idx >= c.seg_cap) { atomicOr(c.err, kErrSegCap); break; }
+      Seg s;
+      s.off = q ? pd.off1 : pd.off0; s.pivot = q ? pd.pivot1 : pd.pivot0;
+      s.len = q ? pd.len1 : pd.len0; s.chunk_begin = cb;
+      s.depth = depth; s.dmax = dmax;
+      segs[idx] = s;
+      ctr[(size_t)idx * kCtrStride] = 0ull;
+      if (HASV) ctr[(size_t)idx * kCtrStride + 1] = 0ull;
+      cb += q ? pd.chunks1 : pd.chunks0;
+    }
+  }
+  __syncthreads();
+}
+
+// A child of depth `depth`: small -> slot item; large -> pivot + pending part.
+template <int DT, bool HASV>
+__device__ inline void child(const Ctx &c, uint32_t slot, uint64_t off, uint32_t len, uint32_t depth,
+                             uint32_t dmax, uint32_t *hist, Pending &pd,
+                             unsigned long long &small_parts, unsigned long long &small_keys) {
   const bool in_s = (depth & 1) != 0;
-  if (len == 0) return;
+  const uint32_t lane = lane_id();
   if (len <= c.small_max) {
-    if (threadIdx.x == 0 && (len > 1 || in_s)) emit_small(c, fin_level, off, len, in_s);
+    if (lane == 0) {
+      put_small(c, slot, off, len, in_s);
+      if (len > 1 || (len == 1 && in_s)) { small_parts++; small_keys += len; }
+    }
     return;
   }
-  const B *Y = (const B *)(in_s ? c.S : c.K);
-  B p = choose_pivot<DT>(c, Y, off, len, depth, dmax, hist, bcast);
-  if (threadIdx.x == 0) emit_part<HASV>(c, part_level, off, len, (uint64_t)p, depth, dmax);
+  const typename Codec<DT>::B p = child_pivot<DT>(c, off, len, depth, dmax, hist);
+  if (lane == 0) {
+    put_small(c, slot, 0, 0, false);
+    const uint32_t ch = part_chunks<DT, HASV>((depth & 1) ? c.S : c.K, off, len);
+    if (pd.n == 0) { pd.off0 = off; pd.pivot0 = (uint64_t)p; pd.len0 = len; pd.chunks0 = ch; }
+    else { pd.off1 = off; pd.pivot1 = (uint64_t)p; pd.len1 = len; pd.chunks1 = ch; }
+    pd.n++;
+  }
 }
 
 // ---- kernels ------------------------------------------------------------------------
 
 __global__ void k_reset(Ctx c) {
   for (int i = threadIdx.x; i < kMaxLevels; i += blockDim.x) {
-    c.lvl[i].packed = 0ull; c.lvl[i].keys = 0ull; c.lvl[i].nfin = 0u;
+    c.lvl[i].packed = 0ull; c.lvl[i].keys = 0ull; c.lvl[i].nbig = 0u;
   }
-  if (threadIdx.x == 0) {
-    c.st->fallback_parts = 0; c.st->small_parts = 0; c.st->small_keys = 0;
-    c.st->band_keys = 0; c.st->max_depth = 0; c.st->err = 0;
+  for (int i = threadIdx.x; i < kStripes * kStatWords; i += blockDim.x) c.stats[i] = 0ull;
+  if (threadIdx.x == 0) *c.err = 0u;
+}
+
+// Roots: one wave per array (workgroup-uniform iterations).  A root is depth 0,
+// lives in K, and its small-part slot is 2 * seg_cap + root index.
+template <int DT, bool HASV>
+__global__ __launch_bounds__(kPlanNT) void k_init(Ctx c) {
+  __shared__ uint32_t hist[kPlanNW][256];
+  __shared__ uint32_t sh_n[kPlanNW], sh_ch[kPlanNW];
+  __shared__ unsigned long long sh_keys[kPlanNW], sh_old;
+  const uint32_t wv = threadIdx.x / kWave;
+  unsigned long long small_parts = 0, small_keys = 0;
+  for (uint32_t base = blockIdx.x * kPlanNW; base < c.nroots; base += gridDim.x * kPlanNW) {
+    const uint32_t j = base + wv;
+    Pending pd = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    uint32_t dmax = 0;
+    if (j < c.nroots) {
+      const uint64_t off = c.roots ? c.roots[j] : 0ull;
+      const uint64_t end = c.roots ? c.roots[j + 1] : c.n;
+      const uint32_t len = (uint32_t)(end - off);
+      uint32_t lg = 0;
+      while (lg < 32 && (1ull << lg) < (unsigned long long)len) lg++;
+      dmax = c.depth_factor * lg;
+      child<DT, HASV>(c, 2 * c.seg_cap + j, off, len, 0u, dmax, hist[wv], pd, small_parts, small_keys);
+    }
+    flush_parts<DT, HASV>(c, 0, pd, 0u, dmax, sh_n, sh_ch, sh_keys, &sh_old);
+  }
+  if ((threadIdx.x & 63u) == 0) {
+    stat_add(c, kStSmallParts, small_parts);
+    stat_add(c, kStSmallKeys, small_keys);
   }
 }
 
-// Roots: one workgroup per array.  A root is depth 0 and lives in K.
+// One partition level: every chunk of every part of level d.
 template <int DT, bool HASV>
-__global__ __launch_bounds__(kPlanWG) void k_init(Ctx c) {
-  __shared__ uint32_t hist[256];
-  __shared__ unsigned long long bcast[4];
-  for (uint32_t j = blockIdx.x; j < c.nroots; j += gridDim.x) {
-    const uint64_t off = c.roots ? c.roots[j] : 0ull;
-    const uint64_t end = c.roots ? c.roots[j + 1] : c.n;
-    const uint32_t len = (uint32_t)(end - off);
-    uint32_t lg = 0;
-    while (lg < 32 && (1ull << lg) < (unsigned long long)len) lg++;
-    const uint32_t dmax = c.depth_factor * lg;
-    handle_child<DT, HASV>(c, 0, 0, off, len, 0u, dmax, hist, bcast);
-  }
-}
-
-// One partition level: every tile of every part of level d.
-template <int DT, bool HASV>
-__global__ __launch_bounds__(kPartWG) void k_partition(Ctx c, int d) {
-  using B = typename Codec<DT>::B;
-  __shared__ uint32_t cntL[kWave], cntG[kWave], cntE[kWave];
-  __shared__ uint32_t sh_seg;
-  __shared__ unsigned long long sh_base;
-  __shared__ uint32_t sh_baseE, sh_totG;
+__global__ __launch_bounds__(kPartNT) void k_partition(Ctx c, int d) {
+  using Cfg = PartCfg<DT, HASV>;
+  using B = typename Cfg::B;
+  constexpr int NT = kPartNT, NW = kPartNW, VEC = Cfg::VEC, KPT = Cfg::KPT;
+  constexpr int NLOAD = Cfg::NLOAD, NENT = Cfg::NENT, PER = NENT / kWave, KB = Cfg::KB;
+  constexpr uint64_t CH = Cfg::CH;
+  constexpr int NCLS = HASV ? 3 : 2;
+  __shared__ uint32_t cnt[2][NCLS][NENT];
+  __shared__ unsigned long long sh_base[2];
+  __shared__ uint32_t sh_totG[2], sh_baseE[2];
+  __shared__ uint32_t sh_part;
 
   const unsigned long long packed = c.lvl[d].packed;
   const uint32_t nseg = (uint32_t)(packed >> 40);
-  const uint32_t ntiles = (uint32_t)(packed & kTileMask);
+  const uint32_t nch = (uint32_t)(packed & kTileMask);
   // a failed capacity check leaves the count above the records written: stop
-  if (ntiles == 0 || nseg > c.seg_cap) return;
+  if (nch == 0 || nseg == 0 || nseg > c.seg_cap) return;
+  const uint32_t per = (nch + gridDim.x - 1) / gridDim.x;
+  const uint32_t t0 = blockIdx.x * per;
+  if (t0 >= nch) return;
+  const uint32_t t1 = (nch - t0 < per) ? nch : t0 + per;
+
   const Seg *segs = (d & 1) ? c.seg1 : c.seg0;
   unsigned long long *ctr = (d & 1) ? c.ctr1 : c.ctr0;
-  unsigned int *ectr = (d & 1) ? c.ectr1 : c.ectr0;
   const B *X = (const B *)((d & 1) ? c.S : c.K);
   B *Y = (B *)((d & 1) ? c.K : c.S);
   const uint32_t *VX = (d & 1) ? c.VS : c.V;
   uint32_t *VY = (d & 1) ? c.V : c.VS;
-
   const uint32_t tid = threadIdx.x, lane = tid & 63u, w = tid >> 6;
+  const uint64_t xabs0 = (uint64_t)(uintptr_t)X / KB;
 
-  for (uint32_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
-    if (tid == 0) {
-      uint32_t lo = 0, hi = nseg;
-      while (hi - lo > 1) {
-        uint32_t mid = (lo + hi) >> 1;
-        if (segs[mid].tile_begin <= t) lo = mid; else hi = mid;
-      }
-      sh_seg = lo;
+  // part containing chunk t0: 64-ary search by wave 0
+  if (w == 0) {
+    uint32_t lo = 0, hi = nseg;
+    while (hi - lo > 1) {
+      const uint32_t step = (hi - lo + 63) / 64;
+      const uint32_t probe = lo + lane * step;
+      const bool ok = probe < hi && segs[probe].chunk_begin <= t0;
+      const unsigned long long m = __ballot(ok);
+      const uint32_t best = 63u - (uint32_t)__clzll((long long)m);
+      const uint32_t nlo = lo + best * step;
+      hi = (hi - nlo < step) ? hi : nlo + step;
+      lo = nlo;
     }
-    __syncthreads();
-    const Seg s = segs[sh_seg];
-    const uint64_t tstart = s.off + (uint64_t)(t - s.tile_begin) * kTile;
-    const uint64_t segend = s.off + s.len;
-    const uint32_t cnt = (uint32_t)((segend - tstart) < kTile ? (segend - tstart) : kTile);
+    if (lane == 0) sh_part = lo;
+  }
+  __syncthreads();
+  uint32_t pi = __builtin_amdgcn_readfirstlane(sh_part);
+  Seg s = segs[pi];
+  uint32_t nxt_begin = (pi + 1 < nseg) ? segs[pi + 1].chunk_begin : 0xFFFFFFFFu;
+
+  for (uint32_t t = t0; t < t1; t++) {
+    const int bf = (int)((t - t0) & 1u);
+    while (nxt_begin <= t) {
+      pi++;
+      s = segs[pi];
+      nxt_begin = (pi + 1 < nseg) ? segs[pi + 1].chunk_begin : 0xFFFFFFFFu;
+    }
+    const uint64_t A0 = xabs0 + s.off, A1 = A0 + s.len;
+    const uint64_t W = (A0 / CH + (uint64_t)(t - s.chunk_begin)) * CH;
+    // window start as an offset from X (it may begin before X[0]; only 16-byte
+    // blocks that hold keys of this part are loaded)
+    const uint4 *win = (const uint4 *)(X + (int64_t)(W - xabs0));
     const B pv = (B)s.pivot;
 
-    B key[kIPT];
-    uint32_t val[kIPT];
+    B key[KPT];
+    uint32_t val[HASV ? KPT : 1];
     uint32_t ltm = 0, gtm = 0, eqm = 0;
 #pragma unroll
-    for (int j = 0; j < kIPT; j++) {
-      const uint32_t idx = (uint32_t)j * kPartWG + tid;
-      const bool valid = idx < cnt;
-      key[j] = valid ? X[tstart + idx] : (B)0;
-      if (HASV) val[j] = valid ? VX[tstart + idx] : 0u;
-      const B u = Codec<DT>::enc(key[j]);
-      const bool lt = valid && (u < pv);
-      const bool gt = valid && (u > pv);
-      ltm |= (uint32_t)lt << j;
-      gtm |= (uint32_t)gt << j;
-      if (HASV) eqm |= (uint32_t)(valid && !lt && !gt) << j;
-      const unsigned long long bl = __ballot(lt);
-      const unsigned long long bg = __ballot(gt);
-      if (lane == 0) {
-        cntL[j * kPartWaves + w] = (uint32_t)__popcll(bl);
-        cntG[j * kPartWaves + w] = (uint32_t)__popcll(bg);
+    for (int j = 0; j < NLOAD; j++) {
+      const uint64_t e0 = W + (uint64_t)(j * NT + tid) * VEC;
+      uint4 v = make_uint4(0u, 0u, 0u, 0u);
+      if (e0 + VEC > A0 && e0 < A1) v = win[j * NT + tid];
+      B comp[VEC];
+      if constexpr (KB == 4) {
+        comp[0] = v.x; comp[1] = v.y; comp[2] = v.z; comp[3] = v.w;
+      } else {
+        comp[0] = (uint64_t)v.x | ((uint64_t)v.y << 32);
+        comp[1] = (uint64_t)v.z | ((uint64_t)v.w << 32);
       }
-      if (HASV) {
-        const unsigned long long be = __ballot(valid && !lt && !gt);
-        if (lane == 0) cntE[j * kPartWaves + w] = (uint32_t)__popcll(be);
+#pragma unroll
+      for (int q = 0; q < VEC; q++) {
+        const int it = j * VEC + q;
+        const uint64_t e = e0 + q;
+        const bool valid = e >= A0 && e < A1;
+        key[it] = comp[q];
+        const B u = Codec<DT>::enc(comp[q]);
+        const bool lt = valid && (u < pv);
+        const bool gt = valid && (u > pv);
+        ltm |= (uint32_t)lt << it;
+        gtm |= (uint32_t)gt << it;
+        if constexpr (HASV) {
+          eqm |= (uint32_t)(valid && !lt && !gt) << it;
+          val[it] = VX[valid ? (e - xabs0) : s.off];   // unconditional: loads stay in flight together
+        }
+      }
+    }
+#pragma unroll
+    for (int it = 0; it < KPT; it++) {
+      const unsigned long long bl = __ballot((ltm >> it) & 1u);
+      const unsigned long long bg = __ballot((gtm >> it) & 1u);
+      if (lane == 0) {
+        cnt[bf][0][it * NW + w] = (uint32_t)__popcll(bl);
+        cnt[bf][1][it * NW + w] = (uint32_t)__popcll(bg);
+      }
+      if constexpr (HASV) {
+        const unsigned long long be = __ballot((eqm >> it) & 1u);
+        if (lane == 0) cnt[bf][2][it * NW + w] = (uint32_t)__popcll(be);
       }
     }
     __syncthreads();
     if (w == 0) {
-      const uint32_t a = cntL[lane], b = cntG[lane];
-      const uint32_t ia = wave_incl_scan(a), ib = wave_incl_scan(b);
-      uint32_t e = 0, ie = 0;
-      if (HASV) { e = cntE[lane]; ie = wave_incl_scan(e); }
-      if (lane == 63) {
-        unsigned long long old = atomicAdd(&ctr[sh_seg], ((unsigned long long)ib << 32) | ia);
-        sh_base = old;
-        sh_totG = ib;
-        if (HASV) sh_baseE = atomicAdd(&ectr[sh_seg], ie);
+      uint32_t a[PER], b[PER], e[PER], sa = 0, sb = 0, se = 0;
+#pragma unroll
+      for (int p = 0; p < PER; p++) {
+        a[p] = cnt[bf][0][lane * PER + p]; sa += a[p];
+        b[p] = cnt[bf][1][lane * PER + p]; sb += b[p];
+        if constexpr (HASV) { e[p] = cnt[bf][2][lane * PER + p]; se += e[p]; }
       }
-      cntL[lane] = ia - a;
-      cntG[lane] = ib - b;
-      if (HASV) cntE[lane] = ie - e;
+      const uint32_t ia = wave_incl_scan(sa), ib = wave_incl_scan(sb);
+      uint32_t ie = 0;
+      if constexpr (HASV) ie = wave_incl_scan(se);
+      uint32_t xa = ia - sa, xb = ib - sb, xe = ie - se;
+#pragma unroll
+      for (int p = 0; p < PER; p++) {
+        cnt[bf][0][lane * PER + p] = xa; xa += a[p];
+        cnt[bf][1][lane * PER + p] = xb; xb += b[p];
+        if constexpr (HASV) { cnt[bf][2][lane * PER + p] = xe; xe += e[p]; }
+      }
+      if (lane == 63) {
+        unsigned long long *cp = ctr + (size_t)pi * kCtrStride;
+        sh_base[bf] = atomicAdd(cp, ((unsigned long long)ib << 32) | ia);
+        sh_totG[bf] = ib;
+        if constexpr (HASV) sh_baseE[bf] = (uint32_t)atomicAdd(cp + 1, (unsigned long long)ie);
+      }
     }
     __syncthreads();
-    const uint32_t baseL = (uint32_t)sh_base;
-    const uint32_t baseG = (uint32_t)(sh_base >> 32);
-    const uint64_t leftBase = s.off + baseL;
-    const uint64_t rightBase = segend - baseG - sh_totG;
+    const unsigned long long base = sh_base[bf];
+    const uint64_t leftBase = s.off + (uint32_t)base;
+    const uint64_t rightBase = s.off + s.len - (uint32_t)(base >> 32) - sh_totG[bf];
+    uint64_t eqBase = 0;
+    if constexpr (HASV) eqBase = s.off + sh_baseE[bf];
 #pragma unroll
-    for (int j = 0; j < kIPT; j++) {
-      const bool lt = (ltm >> j) & 1u, gt = (gtm >> j) & 1u;
+    for (int it = 0; it < KPT; it++) {
+      const bool lt = (ltm >> it) & 1u, gt = (gtm >> it) & 1u;
       const unsigned long long bl = __ballot(lt);
       const unsigned long long bg = __ballot(gt);
       if (lt) {
-        const uint64_t pos = leftBase + cntL[j * kPartWaves + w] + mbcnt(bl);
-        Y[pos] = key[j];
-        if (HASV) VY[pos] = val[j];
+        const uint64_t pos = leftBase + cnt[bf][0][it * NW + w] + mbcnt(bl);
+        Y[pos] = key[it];
+        if constexpr (HASV) VY[pos] = val[it];
       }
       if (gt) {
-        const uint64_t pos = rightBase + cntG[j * kPartWaves + w] + mbcnt(bg);
-        Y[pos] = key[j];
-        if (HASV) VY[pos] = val[j];
+        const uint64_t pos = rightBase + cnt[bf][1][it * NW + w] + mbcnt(bg);
+        Y[pos] = key[it];
+        if constexpr (HASV) VY[pos] = val[it];
       }
-      if (HASV) {
-        const bool eq = (eqm >> j) & 1u;
+      if constexpr (HASV) {
+        const bool eq = (eqm >> it) & 1u;
         const unsigned long long be = __ballot(eq);
-        if (eq) c.VE[s.off + sh_baseE + cntE[j * kPartWaves + w] + mbcnt(be)] = val[j];
+        if (eq) c.VE[eqBase + cnt[bf][2][it * NW + w] + mbcnt(be)] = val[it];
       }
     }
-    __syncthreads();
   }
 }
 
-// After level d: bands, small children, next-level parts with pivots.
+
+// After level d: bands, small children, next-level parts with pivots (a wave per
+// part, workgroup-uniform iterations so the workgroup can reserve together).
 template <int DT, bool HASV>
-__global__ __launch_bounds__(kPlanWG) void k_plan(Ctx c, int d) {
-  __shared__ uint32_t hist[256];
-  __shared__ unsigned long long bcast[4];
+__global__ __launch_bounds__(kPlanNT) void k_plan(Ctx c, int d) {
+  __shared__ uint32_t hist[kPlanNW][256];
+  __shared__ uint32_t sh_n[kPlanNW], sh_ch[kPlanNW];
+  __shared__ unsigned long long sh_keys[kPlanNW], sh_old;
   const unsigned long long packed = c.lvl[d].packed;
   const uint32_t nseg = (uint32_t)(packed >> 40);
   if (nseg > c.seg_cap) return;
   const Seg *segs = (d & 1) ? c.seg1 : c.seg0;
   const unsigned long long *ctr = (d & 1) ? c.ctr1 : c.ctr0;
-  for (uint32_t si = blockIdx.x; si < nseg; si += gridDim.x) {
-    const Seg s = segs[si];
-    const unsigned long long cv = ctr[si];
-    const uint32_t L = (uint32_t)cv, G = (uint32_t)(cv >> 32);
-    const uint32_t E = s.len - L - G;
-    if (threadIdx.x == 0 && E > 0) emit_band(c, d, s.off + L, s.off, E, s.pivot);
-    handle_child<DT, HASV>(c, d, d + 1, s.off, L, s.depth + 1, s.dmax, hist, bcast);
-    handle_child<DT, HASV>(c, d, d + 1, s.off + s.len - G, G, s.depth + 1, s.dmax, hist, bcast);
+  const uint32_t wv = threadIdx.x / kWave, lane = threadIdx.x & 63u;
+  unsigned long long small_parts = 0, small_keys = 0, band_keys = 0;
+  for (uint32_t base = blockIdx.x * kPlanNW; base < nseg; base += gridDim.x * kPlanNW) {
+    const uint32_t si = base + wv;
+    Pending pd = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    uint32_t dmax = 0;
+    if (si < nseg) {
+      const Seg s = segs[si];
+      const unsigned long long cv = ctr[(size_t)si * kCtrStride];
+      const uint32_t L = (uint32_t)cv, G = (uint32_t)(cv >> 32);
+      const uint32_t E = s.len - L - G;
+      dmax = s.dmax;
+      if (lane == 0) {
+        put_band(c, d, si, s.off + L, s.off, E, s.pivot);
+        band_keys += E;
+      }
+      child<DT, HASV>(c, 2 * si, s.off, L, s.depth + 1, dmax, hist[wv], pd, small_parts, small_keys);
+      child<DT, HASV>(c, 2 * si + 1, s.off + s.len - G, G, s.depth + 1, dmax, hist[wv], pd,
+                      small_parts, small_keys);
+    }
+    flush_parts<DT, HASV>(c, d + 1, pd, (uint32_t)d + 1, dmax, sh_n, sh_ch, sh_keys, &sh_old);
+  }
+  if (lane == 0) {
+    stat_add(c, kStSmallParts, small_parts);
+    stat_add(c, kStSmallKeys, small_keys);
+    stat_add(c, kStBandKeys, band_keys);
   }
 }
 
-// LDS records of the small-part sort: the code, plus (with payloads) the local
+// ---- small-part sort: bitonic network in registers ------------------------------
+
+// Records of the small-part sort: the code, plus (with payloads) the local
 // index, so that padding sorts after every real key and payloads can follow.
 template <typename B, bool HASV> struct Rec;
 template <typename B> struct Rec<B, false> {
@@ -502,6 +699,7 @@ template <typename B> struct Rec<B, false> {
   __device__ static inline T make(B code, uint32_t) { return code; }
   __device__ static inline T pad() { return ~(B)0; }
   __device__ static inline B code(T r) { return r; }
+  __device__ static inline uint32_t idx(T) { return 0; }
   __device__ static inline bool less(T a, T b) { return a < b; }
 };
 template <> struct Rec<uint32_t, true> {
@@ -510,79 +708,254 @@ template <> struct Rec<uint32_t, true> {
   __device__ static inline T pad() { return ~0ull; }
   __device__ static inline uint32_t code(T r) { return (uint32_t)(r >> 32); }
   __device__ static inline uint32_t idx(T r) { return (uint32_t)r; }
-  __device__ static inline T with_idx(T r, uint32_t v) { return (r & 0xFFFFFFFF00000000ull) | v; }
   __device__ static inline bool less(T a, T b) { return a < b; }
 };
-struct R64 { uint64_t k; uint64_t i; };
+struct R64 { uint64_t k; uint32_t i; uint32_t pad; };
 template <> struct Rec<uint64_t, true> {
   using T = R64;
-  __device__ static inline T make(uint64_t code, uint32_t i) { T r; r.k = code; r.i = i; return r; }
-  __device__ static inline T pad() { T r; r.k = ~0ull; r.i = ~0ull; return r; }
+  __device__ static inline T make(uint64_t code, uint32_t i) { T r; r.k = code; r.i = i; r.pad = 0; return r; }
+  __device__ static inline T pad() { T r; r.k = ~0ull; r.i = ~0u; r.pad = 0; return r; }
   __device__ static inline uint64_t code(T r) { return r.k; }
-  __device__ static inline uint32_t idx(T r) { return (uint32_t)r.i; }
-  __device__ static inline T with_idx(T r, uint32_t v) { r.i = v; return r; }
+  __device__ static inline uint32_t idx(T r) { return r.i; }
   __device__ static inline bool less(T a, T b) { return a.k < b.k || (a.k == b.k && a.i < b.i); }
 };
 
+// value of lane (addr / 4) of this wave (ds_bpermute)
+__device__ inline uint32_t bperm(uint32_t v, int addr) {
+  return (uint32_t)__builtin_amdgcn_ds_bpermute(addr, (int)v);
+}
+__device__ inline uint64_t bperm(uint64_t v, int addr) {
+  const uint32_t lo = bperm((uint32_t)v, addr), hi = bperm((uint32_t)(v >> 32), addr);
+  return ((uint64_t)hi << 32) | lo;
+}
+__device__ inline R64 bperm(R64 v, int addr) {
+  R64 r;
+  r.k = bperm(v.k, addr);
+  r.i = bperm(v.i, addr);
+  r.pad = 0;
+  return r;
+}
+
 template <typename R>
-__device__ void bitonic_lds(typename R::T *a, uint32_t P) {
-  using T = typename R::T;
-  for (uint32_t k = 2; k <= P; k <<= 1) {
-    for (uint32_t j = k >> 1; j > 0; j >>= 1) {
-      for (uint32_t i = threadIdx.x; i < P / 2; i += blockDim.x) {
-        const uint32_t lo = ((i & ~(j - 1)) << 1) | (i & (j - 1));
-        const uint32_t hi = lo + j;
-        const bool up = (lo & k) == 0;
-        T x = a[lo], y = a[hi];
-        if (R::less(y, x) == up) { a[lo] = y; a[hi] = x; }
+__device__ inline void cas_asc(typename R::T &a, typename R::T &b) {
+  const bool sw = R::less(b, a);
+  const typename R::T lo = sw ? b : a, hi = sw ? a : b;
+  a = lo; b = hi;
+}
+
+// full ascending bitonic sort of the E registers of one thread
+template <typename R, int E>
+__device__ inline void sort_regs_asc(typename R::T (&v)[E]) {
+#pragma unroll
+  for (int k = 2; k <= E; k <<= 1) {
+#pragma unroll
+    for (int j = k >> 1; j > 0; j >>= 1) {
+#pragma unroll
+      for (int i = 0; i < E; i++) {
+        const int p = i ^ j;
+        if (p > i) {
+          if ((i & k) == 0) cas_asc<R>(v[i], v[p]);
+          else cas_asc<R>(v[p], v[i]);
+        }
       }
-      __syncthreads();
     }
   }
 }
 
+// ascending merge of a bitonic sequence held in the E registers
+template <typename R, int E>
+__device__ inline void merge_regs_asc(typename R::T (&v)[E]) {
+#pragma unroll
+  for (int j = E >> 1; j > 0; j >>= 1) {
+#pragma unroll
+    for (int i = 0; i < E; i++)
+      if ((i & j) == 0) cas_asc<R>(v[i], v[i + j]);
+  }
+}
+
+template <typename R, int E>
+__device__ inline void reverse_if(typename R::T (&v)[E], bool cond) {
+#pragma unroll
+  for (int i = 0; i < E / 2; i++) {
+    const typename R::T a = v[i], b = v[E - 1 - i];
+    v[i] = cond ? b : a;
+    v[E - 1 - i] = cond ? a : b;
+  }
+}
+
+__device__ inline uint32_t lds_pad(uint32_t x) { return x + (x >> 5); }
+
+template <int NT>
+__device__ inline void group_sync() {
+  if constexpr (NT == kWave) wave_lds_sync();
+  else __syncthreads();
+}
+
+// Sort one small part of len <= NT*E keys with NT threads (one wave or the whole
+// workgroup), E consecutive elements per thread, and write it to K (and V).
+template <int DT, bool HASV, int NT, int E>
+__device__ void sort_group(const Ctx &c, const FinItem &it,
+                           typename Rec<typename Codec<DT>::B, HASV>::T *lds, uint32_t t) {
+  using B = typename Codec<DT>::B;
+  using R = Rec<B, HASV>;
+  using T = typename R::T;
+  constexpr uint32_t P = (uint32_t)NT * E;
+  constexpr int GB = E < 8 ? E : 8;     // permutes issued back to back
+  const bool in_s = (it.kind & 2u) != 0;
+  const B *src = (const B *)(in_s ? c.S : c.K);
+  const uint32_t *srcV = in_s ? c.VS : c.V;
+  B *K = (B *)c.K;
+  const uint32_t len = it.len;
+  const uint64_t off = it.off;
+  const uint32_t lane = t & 63u;
+  // coalesced load into LDS, then the blocked layout into registers; the loads
+  // are unconditional (index clamped into the part) so that all of them are in
+  // flight together
+  B kin[E];
+#pragma unroll
+  for (int i = 0; i < E; i++) {
+    const uint32_t x = (uint32_t)i * NT + t;
+    kin[i] = src[off + (x < len ? x : len - 1)];
+  }
+#pragma unroll
+  for (int i = 0; i < E; i++) {
+    const uint32_t x = (uint32_t)i * NT + t;
+    lds[lds_pad(x)] = x < len ? R::make(Codec<DT>::enc(kin[i]), x) : R::pad();
+  }
+  group_sync<NT>();
+  T v[E];
+#pragma unroll
+  for (int i = 0; i < E; i++) v[i] = lds[lds_pad(t * E + i)];
+  group_sync<NT>();
+  sort_regs_asc<R, E>(v);
+  reverse_if<R, E>(v, (t & 1u) != 0);
+  for (uint32_t k = 2 * E; k <= P; k <<= 1) {
+    const bool asc = ((t * E) & k) == 0;
+    for (uint32_t j = k >> 1; j >= (uint32_t)E; j >>= 1) {
+      const uint32_t dd = j / E;
+      const bool take_min = ((t & dd) == 0) == asc;
+      if (NT == kWave || dd < (uint32_t)kWave) {
+        const int addr = (int)((lane ^ dd) << 2);
+#pragma unroll
+        for (int i0 = 0; i0 < E; i0 += GB) {
+          T o[GB];
+#pragma unroll
+          for (int g = 0; g < GB; g++) o[g] = bperm(v[i0 + g], addr);
+#pragma unroll
+          for (int g = 0; g < GB; g++) {
+            const bool ol = R::less(o[g], v[i0 + g]);
+            const T mn = ol ? o[g] : v[i0 + g], mx = ol ? v[i0 + g] : o[g];
+            v[i0 + g] = take_min ? mn : mx;
+          }
+        }
+      } else {
+#pragma unroll
+        for (int i = 0; i < E; i++) lds[lds_pad((uint32_t)i * NT + t)] = v[i];
+        group_sync<NT>();
+#pragma unroll
+        for (int i = 0; i < E; i++) {
+          const T o = lds[lds_pad((uint32_t)i * NT + (t ^ dd))];
+          const bool ol = R::less(o, v[i]);
+          const T mn = ol ? o : v[i], mx = ol ? v[i] : o;
+          v[i] = take_min ? mn : mx;
+        }
+        group_sync<NT>();
+      }
+    }
+    merge_regs_asc<R, E>(v);
+    reverse_if<R, E>(v, !asc);
+  }
+#pragma unroll
+  for (int i = 0; i < E; i++) lds[lds_pad(t * E + i)] = v[i];
+  group_sync<NT>();
+  if constexpr (HASV) {
+    uint32_t pv[E];
+#pragma unroll
+    for (int i = 0; i < E; i++) {
+      const uint32_t x = (uint32_t)i * NT + t;
+      const uint32_t li = x < len ? R::idx(lds[lds_pad(x)]) : 0u;
+      pv[i] = srcV[off + li];
+    }
+    group_sync<NT>();   // every payload is read before any is overwritten (in-place parts)
+#pragma unroll
+    for (int i = 0; i < E; i++) {
+      const uint32_t x = (uint32_t)i * NT + t;
+      if (x < len) {
+        K[off + x] = Codec<DT>::dec(R::code(lds[lds_pad(x)]));
+        c.V[off + x] = pv[i];
+      }
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < E; i++) {
+      const uint32_t x = (uint32_t)i * NT + t;
+      if (x < len) K[off + x] = Codec<DT>::dec(R::code(lds[lds_pad(x)]));
+    }
+  }
+  group_sync<NT>();
+}
+
 template <int DT, bool HASV>
-__global__ __launch_bounds__(kFinWG) void k_finish(Ctx c, int d) {
+__device__ inline void fill_band(const Ctx &c, const FinItem &it, uint32_t t, uint32_t nt) {
+  using B = typename Codec<DT>::B;
+  B *K = (B *)c.K;
+  const B kv = Codec<DT>::dec((B)it.pivot);
+  for (uint32_t q = t; q < it.len; q += nt) {
+    K[it.off + q] = kv;
+    if constexpr (HASV) c.V[it.off + q] = c.VE[it.src + q];
+  }
+}
+
+// Level d's finishing work: long-band chunks and workgroup-sized small parts
+// (workgroup each), then wave-sized small parts and short bands (wave each).
+// Child slots are [0, 2 * parts of level d); at level 0 also the root slots.
+template <int DT, bool HASV>
+__global__ __launch_bounds__(kFinNT) void k_finish(Ctx c, int d) {
   using B = typename Codec<DT>::B;
   using R = Rec<B, HASV>;
   using T = typename R::T;
   extern __shared__ unsigned char smem[];
-  T *rec = reinterpret_cast<T *>(smem);
-  const uint32_t nfin = c.lvl[d].nfin;
-  if (nfin > c.fin_cap) return;
-  B *K = (B *)c.K;
-  for (uint32_t ii = blockIdx.x; ii < nfin; ii += gridDim.x) {
-    const FinItem it = c.fin[ii];
-    if (it.kind & 1u) {
-      const B kv = Codec<DT>::dec((B)it.pivot);
-      for (uint32_t q = threadIdx.x; q < it.len; q += kFinWG) {
-        K[it.off + q] = kv;
-        if (HASV) c.V[it.off + q] = c.VE[it.src + q];
-      }
-      continue;   // no LDS use, no barrier needed
+  T *lds = reinterpret_cast<T *>(smem);
+  const uint32_t nseg = (uint32_t)(c.lvl[d].packed >> 40);
+  const uint32_t nbig = c.lvl[d].nbig;
+  if (nseg > c.seg_cap || nbig > c.big_cap) return;
+  const uint32_t nchild = 2 * nseg;
+  const uint32_t nslots = nchild + (d == 0 ? c.nroots : 0u);
+  const uint32_t tid = threadIdx.x;
+  for (uint32_t ii = blockIdx.x; ii < nbig + nslots; ii += gridDim.x) {
+    if (ii < nbig) {
+      fill_band<DT, HASV>(c, c.big[ii], tid, kFinNT);
+      continue;
     }
-    const bool in_s = (it.kind & 2u) != 0;
-    const B *src = in_s ? (const B *)c.S : (const B *)c.K;
-    const uint32_t *srcV = in_s ? c.VS : c.V;
-    uint32_t P = 1;
-    while (P < it.len) P <<= 1;
-    for (uint32_t q = threadIdx.x; q < P; q += kFinWG)
-      rec[q] = q < it.len ? R::make(Codec<DT>::enc(src[it.off + q]), q) : R::pad();
-    __syncthreads();
-    bitonic_lds<R>(rec, P);
-    if constexpr (HASV) {
-      for (uint32_t q = threadIdx.x; q < it.len; q += kFinWG)
-        rec[q] = R::with_idx(rec[q], srcV[it.off + R::idx(rec[q])]);
-      __syncthreads();
-      for (uint32_t q = threadIdx.x; q < it.len; q += kFinWG) {
-        K[it.off + q] = Codec<DT>::dec(R::code(rec[q]));
-        c.V[it.off + q] = R::idx(rec[q]);
-      }
-    } else {
-      for (uint32_t q = threadIdx.x; q < it.len; q += kFinWG)
-        K[it.off + q] = Codec<DT>::dec(R::code(rec[q]));
+    const uint32_t q = ii - nbig;
+    const uint32_t slot = q < nchild ? q : 2 * c.seg_cap + (q - nchild);
+    const FinItem it = c.fin[slot];
+    if (it.len == 0) continue;
+    const uint32_t P = next_pow2(it.len);
+    if (P <= 512) sort_group<DT, HASV, kFinNT, 1>(c, it, lds, tid);
+    else if (P <= 1024) sort_group<DT, HASV, kFinNT, 2>(c, it, lds, tid);
+    else if (P <= 2048) sort_group<DT, HASV, kFinNT, 4>(c, it, lds, tid);
+    else if (P <= 4096) sort_group<DT, HASV, kFinNT, 8>(c, it, lds, tid);
+    else sort_group<DT, HASV, kFinNT, 16>(c, it, lds, tid);
+  }
+  const uint32_t wv = tid / kWave, lane = tid & 63u;
+  T *wl = lds + (size_t)wv * lds_pad(c.wave_max);
+  const uint32_t gw = blockIdx.x * kFinNW + wv, nw = gridDim.x * kFinNW;
+  for (uint32_t q = gw; q < nslots + nseg; q += nw) {
+    if (q >= nslots) {
+      const FinItem bd = c.band[q - nslots];
+      if (bd.len) fill_band<DT, HASV>(c, bd, lane, kWave);
+      continue;
     }
-    __syncthreads();
+    const uint32_t slot = q < nchild ? q : 2 * c.seg_cap + (q - nchild);
+    const FinItem it = c.finw[slot];
+    if (it.len == 0) continue;
+    const uint32_t P = next_pow2(it.len);
+    if (P <= 64) sort_group<DT, HASV, kWave, 1>(c, it, wl, lane);
+    else if (P <= 128) sort_group<DT, HASV, kWave, 2>(c, it, wl, lane);
+    else if (P <= 256) sort_group<DT, HASV, kWave, 4>(c, it, wl, lane);
+    else if (P <= 512) sort_group<DT, HASV, kWave, 8>(c, it, wl, lane);
+    else sort_group<DT, HASV, kWave, 16>(c, it, wl, lane);
   }
 }
 
