@@ -261,7 +261,7 @@ int run_t(Workspace &w, void *keys, uint32_t *vals, const uint64_t *h_offs, size
     st.level_keys[i] = w.h_lvl[i].keys;
     st.level_parts[i] = (uint32_t)(w.h_lvl[i].packed >> 40);
     st.partition_bytes += 2ull * w.h_lvl[i].keys * (kb + (HASV ? 4 : 0));
-    if (w.h_lvl[i].keys) st.partition_launches++;
+    st.partition_launches++;
     if (g_opt.timing) {
       float ms = 0.f;
       HIPCHK(hipEventElapsedTime(&ms, w.ev[2 * i], w.ev[2 * i + 1]));
