@@ -127,9 +127,10 @@ int run_t(Workspace &w, void *keys, uint32_t *vals, const uint64_t *h_offs, size
   const size_t kb = sizeof(B);
   if (((uintptr_t)keys % kb) != 0 || ((uintptr_t)vals % 4) != 0) return TSQS_EINVAL;
   // small parts: one wave up to wave_max keys, the workgroup up to 8192, within LDS
-  uint32_t wave_max = 1024;
+  const uint32_t me = (uint32_t)max_e<RT>();
+  uint32_t wave_max = 64 * me;
   while (wave_max > 64 && kFinNW * lds_pad_host(wave_max) * sizeof(RT) > w.lds_budget) wave_max >>= 1;
-  uint32_t wg_max = 8192;
+  uint32_t wg_max = kFinNT * me;
   while (wg_max > wave_max && lds_pad_host(wg_max) * sizeof(RT) > w.lds_budget) wg_max >>= 1;
   uint32_t small_max = (uint32_t)g_opt.small_max;
   if (small_max > wg_max) small_max = wg_max;

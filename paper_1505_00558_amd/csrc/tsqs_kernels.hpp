@@ -28,7 +28,7 @@
 //   k_finish     small parts are sorted by a bitonic network held in registers
 //                (blocked layout, partner exchange by lane permutes inside a
 //                wave and through LDS across waves): one wave per part up to
-//                1024 keys, the 512-thread workgroup above; bands write the
+//                2048 keys, the 256-thread workgroup above; bands write the
 //                pivot value (equality means identical bits) and the staged
 //                payloads.
 //
@@ -45,7 +45,7 @@ constexpr int kPartNT = 512;
 constexpr int kPartNW = kPartNT / kWave;
 constexpr int kPlanNT = 256;
 constexpr int kPlanNW = kPlanNT / kWave;
-constexpr int kFinNT = 512;
+constexpr int kFinNT = 256;
 constexpr int kFinNW = kFinNT / kWave;
 constexpr uint32_t kBandChunk = 1u << 16;
 constexpr int kMaxLevels = 192;
@@ -720,21 +720,38 @@ template <> struct Rec<uint64_t, true> {
   __device__ static inline bool less(T a, T b) { return a.k < b.k || (a.k == b.k && a.i < b.i); }
 };
 
-// value of lane (addr / 4) of this wave (ds_bpermute)
-__device__ inline uint32_t bperm(uint32_t v, int addr) {
-  return (uint32_t)__builtin_amdgcn_ds_bpermute(addr, (int)v);
+// Partner exchange inside a wave: the value of lane (lane ^ DD).  Distances
+// 1, 2, 4 and 8 use DPP moves (quad_perm, row_mirror, row_half_mirror: VALU
+// only, no LDS traffic); larger ones ds_bpermute with the byte address `addr`.
+template <int CTRL>
+__device__ inline uint32_t dpp32(uint32_t v) {
+  return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, CTRL, 0xF, 0xF, false);
 }
-__device__ inline uint64_t bperm(uint64_t v, int addr) {
-  const uint32_t lo = bperm((uint32_t)v, addr), hi = bperm((uint32_t)(v >> 32), addr);
+template <int DD>
+__device__ inline uint32_t xch(uint32_t v, int addr) {
+  if constexpr (DD == 1) return dpp32<0xB1>(v);                 // quad_perm(1,0,3,2)
+  else if constexpr (DD == 2) return dpp32<0x4E>(v);            // quad_perm(2,3,0,1)
+  else if constexpr (DD == 4) return dpp32<0x1B>(dpp32<0x141>(v));  // half_mirror, quad_perm(3,2,1,0)
+  else if constexpr (DD == 8) return dpp32<0x141>(dpp32<0x140>(v)); // mirror, half_mirror
+  else return (uint32_t)__builtin_amdgcn_ds_bpermute(addr, (int)v);
+}
+template <int DD>
+__device__ inline uint64_t xch(uint64_t v, int addr) {
+  const uint32_t lo = xch<DD>((uint32_t)v, addr), hi = xch<DD>((uint32_t)(v >> 32), addr);
   return ((uint64_t)hi << 32) | lo;
 }
-__device__ inline R64 bperm(R64 v, int addr) {
+template <int DD>
+__device__ inline R64 xch(R64 v, int addr) {
   R64 r;
-  r.k = bperm(v.k, addr);
-  r.i = bperm(v.i, addr);
+  r.k = xch<DD>(v.k, addr);
+  r.i = xch<DD>(v.i, addr);
   r.pad = 0;
   return r;
 }
+
+// keys per lane of the small-part sort, bounded by registers: 32 for 4-byte
+// records, 16 for 8-byte, 8 for 16-byte
+template <typename T> constexpr int max_e() { return sizeof(T) <= 4 ? 32 : (sizeof(T) <= 8 ? 16 : 8); }
 
 template <typename R>
 __device__ inline void cas_asc(typename R::T &a, typename R::T &b) {
@@ -791,6 +808,26 @@ __device__ inline void group_sync() {
   else __syncthreads();
 }
 
+// One compare-exchange stage against the partner lane (lane ^ DD; DD = 0 means
+// "use the permute address"), permutes issued eight at a time.
+template <typename R, int E, int DD>
+__device__ inline void cross_stage(typename R::T (&v)[E], bool take_min, int addr) {
+  using T = typename R::T;
+  constexpr int GB = E < 8 ? E : 8;
+#pragma unroll
+  for (int i0 = 0; i0 < E; i0 += GB) {
+    T o[GB];
+#pragma unroll
+    for (int g = 0; g < GB; g++) o[g] = xch<DD>(v[i0 + g], addr);
+#pragma unroll
+    for (int g = 0; g < GB; g++) {
+      const bool ol = R::less(o[g], v[i0 + g]);
+      const T mn = ol ? o[g] : v[i0 + g], mx = ol ? v[i0 + g] : o[g];
+      v[i0 + g] = take_min ? mn : mx;
+    }
+  }
+}
+
 // Sort one small part of len <= NT*E keys with NT threads (one wave or the whole
 // workgroup), E consecutive elements per thread, and write it to K (and V).
 template <int DT, bool HASV, int NT, int E>
@@ -800,7 +837,6 @@ __device__ void sort_group(const Ctx &c, const FinItem &it,
   using R = Rec<B, HASV>;
   using T = typename R::T;
   constexpr uint32_t P = (uint32_t)NT * E;
-  constexpr int GB = E < 8 ? E : 8;     // permutes issued back to back
   const bool in_s = (it.kind & 2u) != 0;
   const B *src = (const B *)(in_s ? c.S : c.K);
   const uint32_t *srcV = in_s ? c.VS : c.V;
@@ -808,19 +844,23 @@ __device__ void sort_group(const Ctx &c, const FinItem &it,
   const uint32_t len = it.len;
   const uint64_t off = it.off;
   const uint32_t lane = t & 63u;
-  // coalesced load into LDS, then the blocked layout into registers; the loads
-  // are unconditional (index clamped into the part) so that all of them are in
-  // flight together
-  B kin[E];
+  // coalesced load into LDS, then the blocked layout into registers; loads are
+  // unconditional (index clamped into the part) and issued eight at a time so
+  // they are in flight together
+  constexpr int LB = E < 8 ? E : 8;
 #pragma unroll
-  for (int i = 0; i < E; i++) {
-    const uint32_t x = (uint32_t)i * NT + t;
-    kin[i] = src[off + (x < len ? x : len - 1)];
-  }
+  for (int i0 = 0; i0 < E; i0 += LB) {
+    B kin[LB];
 #pragma unroll
-  for (int i = 0; i < E; i++) {
-    const uint32_t x = (uint32_t)i * NT + t;
-    lds[lds_pad(x)] = x < len ? R::make(Codec<DT>::enc(kin[i]), x) : R::pad();
+    for (int g = 0; g < LB; g++) {
+      const uint32_t x = (uint32_t)(i0 + g) * NT + t;
+      kin[g] = src[off + (x < len ? x : len - 1)];
+    }
+#pragma unroll
+    for (int g = 0; g < LB; g++) {
+      const uint32_t x = (uint32_t)(i0 + g) * NT + t;
+      lds[lds_pad(x)] = x < len ? R::make(Codec<DT>::enc(kin[g]), x) : R::pad();
+    }
   }
   group_sync<NT>();
   T v[E];
@@ -836,17 +876,12 @@ __device__ void sort_group(const Ctx &c, const FinItem &it,
       const bool take_min = ((t & dd) == 0) == asc;
       if (NT == kWave || dd < (uint32_t)kWave) {
         const int addr = (int)((lane ^ dd) << 2);
-#pragma unroll
-        for (int i0 = 0; i0 < E; i0 += GB) {
-          T o[GB];
-#pragma unroll
-          for (int g = 0; g < GB; g++) o[g] = bperm(v[i0 + g], addr);
-#pragma unroll
-          for (int g = 0; g < GB; g++) {
-            const bool ol = R::less(o[g], v[i0 + g]);
-            const T mn = ol ? o[g] : v[i0 + g], mx = ol ? v[i0 + g] : o[g];
-            v[i0 + g] = take_min ? mn : mx;
-          }
+        switch (dd) {
+          case 1: cross_stage<R, E, 1>(v, take_min, addr); break;
+          case 2: cross_stage<R, E, 2>(v, take_min, addr); break;
+          case 4: cross_stage<R, E, 4>(v, take_min, addr); break;
+          case 8: cross_stage<R, E, 8>(v, take_min, addr); break;
+          default: cross_stage<R, E, 0>(v, take_min, addr); break;
         }
       } else {
 #pragma unroll
@@ -932,11 +967,13 @@ __global__ __launch_bounds__(kFinNT) void k_finish(Ctx c, int d) {
     const FinItem it = c.fin[slot];
     if (it.len == 0) continue;
     const uint32_t P = next_pow2(it.len);
-    if (P <= 512) sort_group<DT, HASV, kFinNT, 1>(c, it, lds, tid);
-    else if (P <= 1024) sort_group<DT, HASV, kFinNT, 2>(c, it, lds, tid);
-    else if (P <= 2048) sort_group<DT, HASV, kFinNT, 4>(c, it, lds, tid);
-    else if (P <= 4096) sort_group<DT, HASV, kFinNT, 8>(c, it, lds, tid);
-    else sort_group<DT, HASV, kFinNT, 16>(c, it, lds, tid);
+    constexpr int ME = max_e<T>();
+    if (P <= 1024) sort_group<DT, HASV, kFinNT, 4>(c, it, lds, tid);
+    else if (P <= 2048 || ME < 16) sort_group<DT, HASV, kFinNT, 8>(c, it, lds, tid);
+    else if constexpr (ME >= 16) {
+      if (P <= 4096 || ME < 32) sort_group<DT, HASV, kFinNT, 16>(c, it, lds, tid);
+      else if constexpr (ME >= 32) sort_group<DT, HASV, kFinNT, 32>(c, it, lds, tid);
+    }
   }
   const uint32_t wv = tid / kWave, lane = tid & 63u;
   T *wl = lds + (size_t)wv * lds_pad(c.wave_max);
@@ -951,11 +988,15 @@ __global__ __launch_bounds__(kFinNT) void k_finish(Ctx c, int d) {
     const FinItem it = c.finw[slot];
     if (it.len == 0) continue;
     const uint32_t P = next_pow2(it.len);
+    constexpr int ME = max_e<T>();
     if (P <= 64) sort_group<DT, HASV, kWave, 1>(c, it, wl, lane);
     else if (P <= 128) sort_group<DT, HASV, kWave, 2>(c, it, wl, lane);
     else if (P <= 256) sort_group<DT, HASV, kWave, 4>(c, it, wl, lane);
-    else if (P <= 512) sort_group<DT, HASV, kWave, 8>(c, it, wl, lane);
-    else sort_group<DT, HASV, kWave, 16>(c, it, wl, lane);
+    else if (P <= 512 || ME < 16) sort_group<DT, HASV, kWave, 8>(c, it, wl, lane);
+    else if constexpr (ME >= 16) {
+      if (P <= 1024 || ME < 32) sort_group<DT, HASV, kWave, 16>(c, it, wl, lane);
+      else if constexpr (ME >= 32) sort_group<DT, HASV, kWave, 32>(c, it, wl, lane);
+    }
   }
 }
 
