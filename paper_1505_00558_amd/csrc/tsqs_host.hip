@@ -220,6 +220,8 @@ int run_t(Workspace &w, void *keys, uint32_t *vals, const uint64_t *h_offs, size
 
   // median-of-63 splits stay within about 45/55: allow 20% more levels than a
   // perfect halving, plus two
+  // 32-bit byte offsets within a part suffice unless a part reaches 4 GiB
+  const bool wide = (uint64_t)max_root * sizeof(typename Codec<DT>::B) > 0xFFFFFFFFull;
   const uint32_t lv = ceil_log2((max_root + small_max - 1) / small_max);
   uint32_t expected = lv + (lv + 4) / 5 + 2;
   int d = 0, target = (int)expected;
@@ -227,7 +229,10 @@ int run_t(Workspace &w, void *keys, uint32_t *vals, const uint64_t *h_offs, size
   for (;;) {
     for (; d < target; d++) {
       if (g_opt.timing) HIPCHK(hipEventRecord(w.ev[2 * d], s));
-      hipLaunchKernelGGL((k_partition<DT, HASV>), dim3(part_grid), dim3(kPartNT), 0, s, c, d);
+      if (wide)
+        hipLaunchKernelGGL((k_partition<DT, HASV, true>), dim3(part_grid), dim3(kPartNT), 0, s, c, d);
+      else
+        hipLaunchKernelGGL((k_partition<DT, HASV, false>), dim3(part_grid), dim3(kPartNT), 0, s, c, d);
       if (g_opt.timing) HIPCHK(hipEventRecord(w.ev[2 * d + 1], s));
       hipLaunchKernelGGL((k_plan<DT, HASV>), dim3(plan_grid), dim3(kPlanNT), 0, s, c, d);
       hipLaunchKernelGGL((k_finish<DT, HASV>), dim3(fin_grid), dim3(kFinNT), fin_lds, s, c, d);

@@ -37,6 +37,7 @@
 
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+#include <type_traits>
 
 namespace tsqs {
 
@@ -97,8 +98,7 @@ template <int DT, bool HASV> struct PartCfg {
   static constexpr int KPT = KB == 4 ? (HASV ? 16 : 32) : (HASV ? 8 : 16);  // keys per thread
   static constexpr int NLOAD = KPT / VEC;
   static constexpr uint64_t CH = (uint64_t)kPartNT * KPT;               // keys per chunk
-  static constexpr int NENT = KPT * kPartNW;                            // (item, wave) entries
-  static_assert(NENT % kWave == 0 && KPT <= 32, "layout");
+  static_assert(KPT % VEC == 0 && kPartNW <= kWave, "layout");
 };
 
 
@@ -161,6 +161,12 @@ __device__ inline uint32_t lane_id() {
 }
 
 // number of set bits of m in lanes below this one
+// wave mask of a predicate
+__device__ inline unsigned long long wave_ballot(bool p) { return __builtin_amdgcn_ballot_w64(p); }
+// base + number of set bits of m in lanes below this one
+__device__ inline uint32_t mbcnt_from(unsigned long long m, uint32_t base) {
+  return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, base));
+}
 __device__ inline uint32_t mbcnt(unsigned long long m) {
   return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
 }
@@ -479,18 +485,44 @@ __global__ __launch_bounds__(kPlanNT) void k_init(Ctx c) {
   }
 }
 
-// One partition level: every chunk of every part of level d.
-template <int DT, bool HASV>
+// v := x in lane L of v; the other lanes keep their value
+template <int L>
+__device__ inline void lane_put(uint32_t &v, uint32_t x) {
+  asm volatile("v_writelane_b32 %0, %1, %2" : "+v"(v) : "s"(x), "n"(L));
+}
+// f(integral_constant<int, I>) for I = B .. E-1, expanded at compile time
+template <int B, int E, typename F>
+__device__ inline void static_for(F &&f) {
+  if constexpr (B < E) {
+    f(std::integral_constant<int, B>{});
+    static_for<B + 1, E>(f);
+  }
+}
+// hide a value's origin from the optimiser (no instruction is emitted)
+template <typename T>
+__device__ inline void opaque_v(T &x) { asm volatile("" : "+v"(x)); }
+template <typename T>
+__device__ inline void opaque_s(T &x) { asm volatile("" : "+s"(x)); }
+
+// &base[i]; unless WIDE, i * sizeof(T) must fit in 32 bits (the address is
+// then formed as a uniform base plus a 32-bit lane offset)
+template <bool WIDE, typename T>
+__device__ inline T *at(T *base, uint32_t i) {
+  if constexpr (WIDE) return base + i;
+  else return (T *)((char *)base + (uint32_t)(i * (uint32_t)sizeof(T)));
+}
+
+// One partition level: every chunk of every part of level d.  WIDE: some part
+// may span 4 GiB or more of keys or payloads.
+template <int DT, bool HASV, bool WIDE>
 __global__ __launch_bounds__(kPartNT) void k_partition(Ctx c, int d) {
   using Cfg = PartCfg<DT, HASV>;
   using B = typename Cfg::B;
   constexpr int NT = kPartNT, NW = kPartNW, VEC = Cfg::VEC, KPT = Cfg::KPT;
-  constexpr int NLOAD = Cfg::NLOAD, NENT = Cfg::NENT, PER = NENT / kWave, KB = Cfg::KB;
+  constexpr int NLOAD = Cfg::NLOAD, KB = Cfg::KB;
   constexpr uint64_t CH = Cfg::CH;
   constexpr int NCLS = HASV ? 3 : 2;
-  __shared__ uint32_t cnt[2][NCLS][NENT];
-  __shared__ unsigned long long sh_base[2];
-  __shared__ uint32_t sh_totG[2], sh_baseE[2];
+  __shared__ uint32_t cnt[2][NCLS][NW];
   __shared__ uint32_t sh_part;
 
   const unsigned long long packed = c.lvl[d].packed;
@@ -539,114 +571,156 @@ __global__ __launch_bounds__(kPartNT) void k_partition(Ctx c, int d) {
       s = segs[pi];
       nxt_begin = (pi + 1 < nseg) ? segs[pi + 1].chunk_begin : 0xFFFFFFFFu;
     }
+    // chunk window [W, W + CH) in absolute key coordinates; the keys of this
+    // part occupy window indices [lo, hi)
     const uint64_t A0 = xabs0 + s.off, A1 = A0 + s.len;
     const uint64_t W = (A0 / CH + (uint64_t)(t - s.chunk_begin)) * CH;
+    const uint32_t lo = A0 > W ? (uint32_t)(A0 - W) : 0u;
+    const uint32_t hi = A1 < W + CH ? (uint32_t)(A1 - W) : (uint32_t)CH;
     // window start as an offset from X (it may begin before X[0]; only 16-byte
     // blocks that hold keys of this part are loaded)
     const uint4 *win = (const uint4 *)(X + (int64_t)(W - xabs0));
-    const B pv = (B)s.pivot;
+    // payloads from window index lo on (part index max(W - A0, 0) on)
+    const uint32_t *VXp = VX + s.off + (A0 > W ? 0u : (uint32_t)(W - A0));
 
-    B key[KPT];
-    uint32_t val[HASV ? KPT : 1];
-    uint32_t ltm = 0, gtm = 0, eqm = 0;
+    // FULL: every window index holds a key of this part (no range checks)
+    auto body = [&](auto full_tag) {
+      constexpr bool FULL = decltype(full_tag)::value;
+      const uint32_t rel0 = tid * VEC - lo;   // window index - lo, modulo 2^32
+      const uint32_t wlen = hi - lo;
+      B key[KPT];
+      uint32_t val[HASV ? KPT : 1];
 #pragma unroll
-    for (int j = 0; j < NLOAD; j++) {
-      const uint64_t e0 = W + (uint64_t)(j * NT + tid) * VEC;
-      uint4 v = make_uint4(0u, 0u, 0u, 0u);
-      if (e0 + VEC > A0 && e0 < A1) v = win[j * NT + tid];
-      B comp[VEC];
-      if constexpr (KB == 4) {
-        comp[0] = v.x; comp[1] = v.y; comp[2] = v.z; comp[3] = v.w;
-      } else {
-        comp[0] = (uint64_t)v.x | ((uint64_t)v.y << 32);
-        comp[1] = (uint64_t)v.z | ((uint64_t)v.w << 32);
-      }
-#pragma unroll
-      for (int q = 0; q < VEC; q++) {
-        const int it = j * VEC + q;
-        const uint64_t e = e0 + q;
-        const bool valid = e >= A0 && e < A1;
-        key[it] = comp[q];
-        const B u = Codec<DT>::enc(comp[q]);
-        const bool lt = valid && (u < pv);
-        const bool gt = valid && (u > pv);
-        ltm |= (uint32_t)lt << it;
-        gtm |= (uint32_t)gt << it;
+      for (int j = 0; j < NLOAD; j++) {
+        const uint32_t e0 = (uint32_t)(j * NT + tid) * VEC;
+        uint4 v = make_uint4(0u, 0u, 0u, 0u);
+        if (FULL || (e0 + VEC > lo && e0 < hi)) v = win[j * NT + tid];
+        if constexpr (KB == 4) {
+          key[j * VEC + 0] = v.x; key[j * VEC + 1] = v.y; key[j * VEC + 2] = v.z; key[j * VEC + 3] = v.w;
+        } else {
+          key[j * VEC + 0] = (uint64_t)v.x | ((uint64_t)v.y << 32);
+          key[j * VEC + 1] = (uint64_t)v.z | ((uint64_t)v.w << 32);
+        }
         if constexpr (HASV) {
-          eqm |= (uint32_t)(valid && !lt && !gt) << it;
-          val[it] = VX[valid ? (e - xabs0) : s.off];   // unconditional: loads stay in flight together
+#pragma unroll
+          for (int q = 0; q < VEC; q++) {
+            const uint32_t r = rel0 + (uint32_t)(j * NT * VEC + q);
+            // unconditional (index clamped into the part): loads stay in flight together
+            val[j * VEC + q] = *at<false>(VXp, (FULL || r < wlen) ? r : 0u);
+          }
         }
       }
-    }
-#pragma unroll
-    for (int it = 0; it < KPT; it++) {
-      const unsigned long long bl = __ballot((ltm >> it) & 1u);
-      const unsigned long long bg = __ballot((gtm >> it) & 1u);
+      // item it of this lane: ok = holds a key of this part, lt / gt = the key
+      // is below / above the pivot; lm / gm / om are the wave's masks of lt /
+      // gt / ok (each a plain compare ballot, combined on the scalar unit)
+      B pvc = (B)s.pivot;
+      uint32_t relc = rel0;
+      auto classify = [&](int it, bool &lt, bool &gt, unsigned long long &lm,
+                          unsigned long long &gm, unsigned long long &om) {
+        const B u = Codec<DT>::enc(key[it]);
+        lt = u < pvc;
+        gt = u > pvc;
+        lm = wave_ballot(lt);
+        gm = wave_ballot(gt);
+        om = ~0ull;
+        if constexpr (!FULL) {
+          const bool ok = relc + (uint32_t)((it / VEC) * NT * VEC + (it % VEC)) < wlen;
+          om = wave_ballot(ok);
+          lm &= om;
+          gm &= om;
+          lt = lt && ok;
+          gt = gt && ok;
+        }
+      };
+      // pass 1: this wave's class totals (scalar)
+      uint32_t sL = 0, sG = 0, sO = 0;
+      static_for<0, KPT>([&](auto I) {
+        constexpr int it = decltype(I)::value;
+        bool lt, gt;
+        unsigned long long lm, gm, om;
+        classify(it, lt, gt, lm, gm, om);
+        sL += (uint32_t)__popcll(lm);
+        sG += (uint32_t)__popcll(gm);
+        if constexpr (HASV && !FULL) sO += (uint32_t)__popcll(om);
+        // one item at a time: deferring the sums would keep every mask live
+        opaque_s(sL);
+        opaque_s(sG);
+        if constexpr (HASV && !FULL) opaque_s(sO);
+      });
+      if constexpr (HASV && FULL) sO = (uint32_t)(kWave * KPT);
       if (lane == 0) {
-        cnt[bf][0][it * NW + w] = (uint32_t)__popcll(bl);
-        cnt[bf][1][it * NW + w] = (uint32_t)__popcll(bg);
+        cnt[bf][0][w] = sL;
+        cnt[bf][1][w] = sG;
+        if constexpr (HASV) cnt[bf][2][w] = sO - sL - sG;
       }
-      if constexpr (HASV) {
-        const unsigned long long be = __ballot((eqm >> it) & 1u);
-        if (lane == 0) cnt[bf][2][it * NW + w] = (uint32_t)__popcll(be);
+      __syncthreads();
+      // exclusive prefix over the waves of each class; one reservation per chunk
+      if (w == 0) {
+        const uint32_t a = lane < (uint32_t)NW ? cnt[bf][0][lane] : 0u;
+        const uint32_t b = lane < (uint32_t)NW ? cnt[bf][1][lane] : 0u;
+        uint32_t e = 0;
+        if constexpr (HASV) e = lane < (uint32_t)NW ? cnt[bf][2][lane] : 0u;
+        const uint32_t ia = wave_incl_scan(a), ib = wave_incl_scan(b);
+        uint32_t ie = 0;
+        if constexpr (HASV) ie = wave_incl_scan(e);
+        unsigned long long rb = 0;
+        uint32_t re = 0;
+        if (lane == (uint32_t)NW - 1) {
+          unsigned long long *cp = ctr + (size_t)pi * kCtrStride;
+          rb = atomicAdd(cp, ((unsigned long long)ib << 32) | ia);
+          if constexpr (HASV) re = (uint32_t)atomicAdd(cp + 1, (unsigned long long)ie);
+        }
+        // < keys fill from the left cursor, > keys from the right cursor
+        // (the reserved block ends where the previous reservations began)
+        rb = __shfl(rb, NW - 1);
+        const uint32_t totG = __shfl(ib, NW - 1);
+        if constexpr (HASV) re = __shfl(re, NW - 1);
+        if (lane < (uint32_t)NW) {
+          cnt[bf][0][lane] = (uint32_t)rb + ia - a;
+          cnt[bf][1][lane] = s.len - (uint32_t)(rb >> 32) - totG + ib - b;
+          if constexpr (HASV) cnt[bf][2][lane] = re + ie - e;
+        }
       }
-    }
-    __syncthreads();
-    if (w == 0) {
-      uint32_t a[PER], b[PER], e[PER], sa = 0, sb = 0, se = 0;
-#pragma unroll
-      for (int p = 0; p < PER; p++) {
-        a[p] = cnt[bf][0][lane * PER + p]; sa += a[p];
-        b[p] = cnt[bf][1][lane * PER + p]; sb += b[p];
-        if constexpr (HASV) { e[p] = cnt[bf][2][lane * PER + p]; se += e[p]; }
-      }
-      const uint32_t ia = wave_incl_scan(sa), ib = wave_incl_scan(sb);
-      uint32_t ie = 0;
-      if constexpr (HASV) ie = wave_incl_scan(se);
-      uint32_t xa = ia - sa, xb = ib - sb, xe = ie - se;
-#pragma unroll
-      for (int p = 0; p < PER; p++) {
-        cnt[bf][0][lane * PER + p] = xa; xa += a[p];
-        cnt[bf][1][lane * PER + p] = xb; xb += b[p];
-        if constexpr (HASV) { cnt[bf][2][lane * PER + p] = xe; xe += e[p]; }
-      }
-      if (lane == 63) {
-        unsigned long long *cp = ctr + (size_t)pi * kCtrStride;
-        sh_base[bf] = atomicAdd(cp, ((unsigned long long)ib << 32) | ia);
-        sh_totG[bf] = ib;
-        if constexpr (HASV) sh_baseE[bf] = (uint32_t)atomicAdd(cp + 1, (unsigned long long)ie);
-      }
-    }
-    __syncthreads();
-    const unsigned long long base = sh_base[bf];
-    const uint64_t leftBase = s.off + (uint32_t)base;
-    const uint64_t rightBase = s.off + s.len - (uint32_t)(base >> 32) - sh_totG[bf];
-    uint64_t eqBase = 0;
-    if constexpr (HASV) eqBase = s.off + sh_baseE[bf];
-#pragma unroll
-    for (int it = 0; it < KPT; it++) {
-      const bool lt = (ltm >> it) & 1u, gt = (gtm >> it) & 1u;
-      const unsigned long long bl = __ballot(lt);
-      const unsigned long long bg = __ballot(gt);
-      if (lt) {
-        const uint64_t pos = leftBase + cnt[bf][0][it * NW + w] + mbcnt(bl);
-        Y[pos] = key[it];
-        if constexpr (HASV) VY[pos] = val[it];
-      }
-      if (gt) {
-        const uint64_t pos = rightBase + cnt[bf][1][it * NW + w] + mbcnt(bg);
-        Y[pos] = key[it];
-        if constexpr (HASV) VY[pos] = val[it];
-      }
-      if constexpr (HASV) {
-        const bool eq = (eqm >> it) & 1u;
-        const unsigned long long be = __ballot(eq);
-        if (eq) c.VE[eqBase + cnt[bf][2][it * NW + w] + mbcnt(be)] = val[it];
-      }
-    }
+      __syncthreads();
+      uint32_t runL = __builtin_amdgcn_readfirstlane(cnt[bf][0][w]);
+      uint32_t runG = __builtin_amdgcn_readfirstlane(cnt[bf][1][w]);
+      uint32_t runE = 0;
+      if constexpr (HASV) runE = __builtin_amdgcn_readfirstlane(cnt[bf][2][w]);
+      B *Yp = Y + s.off;
+      uint32_t *VYp = VY + s.off;
+      uint32_t *VEp = c.VE + s.off;
+      // pass 2: the comparisons are recomputed rather than kept (2 x KPT wave
+      // masks do not fit in scalar registers); the opaque copies stop the
+      // compiler from keeping them
+      opaque_v(pvc);
+      opaque_v(relc);
+      static_for<0, KPT>([&](auto I) {
+        constexpr int it = decltype(I)::value;
+        bool lt, gt;
+        unsigned long long lm, gm, om;
+        classify(it, lt, gt, lm, gm, om);
+        uint32_t posL = runL + mbcnt(lm), posG = runG + mbcnt(gm);
+        opaque_v(posL);   // select the position, not the masks
+        opaque_v(posG);
+        const uint32_t pos = lt ? posL : posG;
+        runL += (uint32_t)__popcll(lm);
+        runG += (uint32_t)__popcll(gm);
+        if (lt || gt) {
+          *at<WIDE>(Yp, pos) = key[it];
+          if constexpr (HASV) *at<WIDE>(VYp, pos) = val[it];
+        }
+        if constexpr (HASV) {
+          const unsigned long long em = om & ~(lm | gm);
+          if ((em >> lane) & 1ull) *at<WIDE>(VEp, runE + mbcnt(em)) = val[it];
+          runE += (uint32_t)__popcll(em);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+      });
+    };
+    if (lo == 0u && hi == (uint32_t)CH) body(std::true_type{});
+    else body(std::false_type{});
   }
 }
-
 
 // After level d: bands, small children, next-level parts with pivots (a wave per
 // part, workgroup-uniform iterations so the workgroup can reserve together).
