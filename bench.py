@@ -232,6 +232,128 @@ def workload_float32(args):
     return run_single_arrays(args, "float32", arrays, "float32", False, config)
 
 
+def device_sorted_check(keys, offs) -> bool:
+    """Every array [offs[j], offs[j+1]) of the device tensor is non-decreasing
+    (integer keys; checked on the device in slices)."""
+    import torch
+    n = int(offs[-1])
+    if n < 2:
+        return True
+    # positions i where keys[i] > keys[i+1] must all be last elements of an array
+    starts = torch.from_numpy(np.asarray(offs[1:-1], dtype=np.int64)).to(keys.device)
+    bad_total = 0
+    step = 1 << 28
+    for a in range(0, n - 1, step):
+        b = min(n - 1, a + step)
+        desc = torch.nonzero(keys[a:b] > keys[a + 1:b + 1]).flatten() + (a + 1)
+        if desc.numel():
+            ok = torch.isin(desc, starts)
+            bad_total += int((~ok).sum())
+    return bad_total == 0
+
+
+def pct(xs, q):
+    return float(np.percentile(np.asarray(xs, dtype=np.float64), q)) if len(xs) else None
+
+
+def run_batch_case(args, keys0, offs, label):
+    """One batched call over every array vs one plain call per array."""
+    import ctypes
+    import torch
+    import paper_1505_00558_amd as tsqs
+    lib = tsqs.load_library()
+    nseg = offs.size - 1
+    total = int(offs[-1])
+    work = torch.empty_like(keys0)
+    stream = torch.cuda.current_stream()
+
+    # batched: restore (untimed), then one tsqs_sort_batch
+    batch_ms = []
+    for step in range(args.warmup + args.steps):
+        work.copy_(keys0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        tsqs.sort_batch(work, offs)
+        torch.cuda.synchronize()
+        if step >= args.warmup:
+            batch_ms.append((time.perf_counter() - t0) * 1e3)
+    levels = tsqs.get_stats()["levels"]
+    ok_batch = device_sorted_check(work, offs)
+
+    # plain: one tsqs_sort per array, serially on one stream, from one host thread
+    work.copy_(keys0)
+    torch.cuda.synchronize()
+    base = work.data_ptr()
+    esz = work.element_size()
+    dt = tsqs._dtype_code(work)
+    sh = ctypes.c_void_p(stream.cuda_stream)
+    o = offs.astype(np.int64)
+    done_ms = np.empty(nseg)
+    t0 = time.perf_counter()
+    for j in range(nseg):
+        rc = lib.tsqs_sort(ctypes.c_void_p(base + int(o[j]) * esz), int(o[j + 1] - o[j]), dt, sh)
+        if rc != 0:
+            raise RuntimeError("tsqs_sort failed: %d" % rc)
+        done_ms[j] = (time.perf_counter() - t0) * 1e3
+    torch.cuda.synchronize()
+    plain_ms = (time.perf_counter() - t0) * 1e3
+    ok_plain = device_sorted_check(work, offs)
+
+    bm = float(np.median(batch_ms))
+    return {
+        "case": label,
+        "arrays": nseg,
+        "total_keys": total,
+        "batch": {"ms_median": bm, "ms_all": [round(x, 3) for x in batch_ms],
+                  "keys_per_s": total / (bm / 1e3), "levels": levels,
+                  # every array of a batched call completes when the call returns
+                  "latency_ms_p50": bm, "latency_ms_p99": bm, "sorted": ok_batch},
+        "plain": {"ms": plain_ms, "keys_per_s": total / (plain_ms / 1e3),
+                  "latency_ms_p50": pct(done_ms, 50), "latency_ms_p99": pct(done_ms, 99),
+                  "sorted": ok_plain},
+        "speedup": plain_ms / bm,
+    }
+
+
+def workload_batch(args):
+    """Many independent int32 arrays, sizes log-uniform in [16, 2^20], each of a
+    family drawn from the seven; generated on the device from the seeded stream."""
+    import torch
+    import tsqs_inputs as ti
+    seed = ti.seed_for(4, 0)
+    cases = []
+    for label, max_total in (("full", None), ("capped_2^28", 1 << 28)):
+        log("batch %s: generating %d arrays" % (label, args.batch_count))
+        keys0, offs, fams = ti.device_batch(seed, args.batch_count, 4, 20, "int32",
+                                            max_total=max_total)
+        log("batch %s: %d arrays, %d keys" % (label, offs.size - 1, int(offs[-1])))
+        cases.append(run_batch_case(args, keys0, offs, label))
+        del keys0
+        torch.cuda.empty_cache()
+    head = cases[0]
+    out = {
+        "metric": METRIC,
+        "value": head["batch"]["keys_per_s"],
+        "unit": "keys/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": head["batch"]["ms_median"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int32",
+        "data": "synthetic",
+        "config": {"workload": "batched segmented sort: %d int32 arrays, sizes log-uniform in "
+                               "[16, 2^20], family per array drawn from the seven; one "
+                               "tsqs_sort_batch call vs one tsqs_sort call per array"
+                               % args.batch_count,
+                   "arrays": head["arrays"], "total_keys": head["total_keys"]},
+        "cases": cases,
+    }
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -241,7 +363,8 @@ def main():
                     choices=["large", "plain1m", "pairs64", "float32", "batch", "serve"])
     ap.add_argument("--log2n", type=int, default=28)
     ap.add_argument("--families", default="all")
-    ap.add_argument("--cpu-log2n", type=int, default=23)
+    ap.add_argument("--cpu-log2n", type=int, default=26)
+    ap.add_argument("--batch-count", type=int, default=100000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -253,10 +376,10 @@ def main():
         print("bench.py: no GPU", file=sys.stderr)
         sys.exit(1)
     fn = {"large": workload_large, "plain1m": workload_plain1m, "pairs64": workload_pairs64,
-          "float32": workload_float32}.get(args.workload)
+          "float32": workload_float32, "batch": workload_batch}.get(args.workload)
     if fn is None:
-        import bench_batch
-        fn = {"batch": bench_batch.workload_batch, "serve": bench_batch.workload_serve}[args.workload]
+        print("bench.py: workload %s is not available" % args.workload, file=sys.stderr)
+        sys.exit(2)
     out = fn(args)
     print(json.dumps(out), flush=True)
 

@@ -94,7 +94,7 @@ typedef struct {
   float level_ms[TSQS_MAX_LEVELS];          /* partition kernel time (TIMING) */
   double partition_ms;           /* sum of level_ms */
   uint64_t partition_bytes;      /* algorithmic bytes: 2 * keys * (key+payload bytes) */
-  uint32_t partition_launches;   /* partition kernel launches (one per level) */
+  uint32_t partition_launches;   /* partition kernel launches (one per level with parts) */
   uint32_t reserved;
 } tsqs_stats_t;
 

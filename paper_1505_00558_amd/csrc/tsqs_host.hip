@@ -223,18 +223,23 @@ int run_t(Workspace &w, void *keys, uint32_t *vals, const uint64_t *h_offs, size
   // 32-bit byte offsets within a part suffice unless a part reaches 4 GiB
   const bool wide = (uint64_t)max_root * sizeof(typename Codec<DT>::B) > 0xFFFFFFFFull;
   const uint32_t lv = ceil_log2((max_root + small_max - 1) / small_max);
-  uint32_t expected = lv + (lv + 4) / 5 + 2;
+  // every root small: level 0 has no parts, only its finish work
+  const bool roots_small = max_root <= small_max;
+  uint32_t expected = roots_small ? 1u : lv + (lv + 4) / 5 + 2;
   int d = 0, target = (int)expected;
   if (target > kMaxLevels - 1) target = kMaxLevels - 1;
   for (;;) {
     for (; d < target; d++) {
+      const bool idle = d == 0 && roots_small;
       if (g_opt.timing) HIPCHK(hipEventRecord(w.ev[2 * d], s));
-      if (wide)
+      if (idle) {
+      } else if (wide) {
         hipLaunchKernelGGL((k_partition<DT, HASV, true>), dim3(part_grid), dim3(kPartNT), 0, s, c, d);
-      else
+      } else {
         hipLaunchKernelGGL((k_partition<DT, HASV, false>), dim3(part_grid), dim3(kPartNT), 0, s, c, d);
+      }
       if (g_opt.timing) HIPCHK(hipEventRecord(w.ev[2 * d + 1], s));
-      hipLaunchKernelGGL((k_plan<DT, HASV>), dim3(plan_grid), dim3(kPlanNT), 0, s, c, d);
+      if (!idle) hipLaunchKernelGGL((k_plan<DT, HASV>), dim3(plan_grid), dim3(kPlanNT), 0, s, c, d);
       hipLaunchKernelGGL((k_finish<DT, HASV>), dim3(fin_grid), dim3(kFinNT), fin_lds, s, c, d);
       HIPCHK(hipGetLastError());
     }
@@ -267,7 +272,7 @@ int run_t(Workspace &w, void *keys, uint32_t *vals, const uint64_t *h_offs, size
     st.level_keys[i] = w.h_lvl[i].keys;
     st.level_parts[i] = (uint32_t)(w.h_lvl[i].packed >> 40);
     st.partition_bytes += 2ull * w.h_lvl[i].keys * (kb + (HASV ? 4 : 0));
-    st.partition_launches++;
+    if (!(i == 0 && roots_small)) st.partition_launches++;
     if (g_opt.timing) {
       float ms = 0.f;
       HIPCHK(hipEventElapsedTime(&ms, w.ev[2 * i], w.ev[2 * i + 1]));

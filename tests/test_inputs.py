@@ -72,3 +72,27 @@ def test_batch_layout():
     assert np.array_equal(keys[int(offs[j]):int(offs[j + 1])], alone)
     k2, o2, _ = ti.batch(11, 200, lo_log2=4, hi_log2=12, max_total=50000)
     assert int(o2[-1]) <= 50000
+
+
+def test_batch_plan_matches_batch():
+    keys, offs, fams = ti.batch(4242, 50, 4, 12)
+    sizes, poffs, pfams, seeds = ti.batch_plan(4242, 50, 4, 12)
+    assert np.array_equal(offs, poffs) and fams == pfams
+    assert np.array_equal(np.diff(poffs).astype(np.int64), sizes)
+    for j in (0, 17, 49):
+        a, b = int(offs[j]), int(offs[j + 1])
+        assert np.array_equal(keys[a:b], ti.family(fams[j], b - a, "int32", seed=int(seeds[j])))
+    _, coffs, _, _ = ti.batch_plan(4242, 50, 4, 12, max_total=5000)
+    assert int(coffs[-1]) <= 5000
+
+
+def test_device_generator_library_exports():
+    import ctypes
+    path = os.path.join(os.path.dirname(ti.__file__), "libtsqs_inputs.so")
+    if not os.path.exists(path):
+        pytest.skip("libtsqs_inputs.so not built")
+    lib = ctypes.CDLL(path)
+    assert hasattr(lib, "tsqs_inputs_generate")
+    lib.tsqs_inputs_generate.restype = ctypes.c_int
+    # argument errors are reported before any device work
+    assert lib.tsqs_inputs_generate(None, 0, None, None, None, 1, None) == -1

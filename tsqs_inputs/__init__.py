@@ -174,3 +174,84 @@ def batch(seed: int, count: int, lo_log2: int = 4, hi_log2: int = 20, dtype="int
     for j, (s, f) in enumerate(zip(sizes.tolist(), fams)):
         keys[int(offs[j]):int(offs[j + 1])] = family(f, s, dt, seed=seed + 0x100000 + j)
     return keys, offs, fams
+
+
+# ---- device-side generation (same arrays, generated by tsqs_inputs/gen.hip) ----
+
+FAMILY_CODE = {f: i for i, f in enumerate(FAMILIES)}
+DTYPE_CODE = {"int32": 0, "uint32": 1, "int64": 2, "uint64": 3, "float32": 4}
+# device tensors hold unsigned keys in the signed type of the same width
+TORCH_DTYPE = {"int32": "int32", "uint32": "int32", "int64": "int64", "uint64": "int64",
+               "float32": "float32"}
+_gen_lib = None
+
+
+def _load_gen():
+    global _gen_lib
+    if _gen_lib is None:
+        import ctypes
+        import os
+        path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libtsqs_inputs.so")
+        if not os.path.exists(path):
+            raise ImportError("libtsqs_inputs.so is not built (python tsqs_inputs/build.py)")
+        lib = ctypes.CDLL(path)
+        lib.tsqs_inputs_generate.restype = ctypes.c_int
+        lib.tsqs_inputs_generate.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p,
+                                             ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint32,
+                                             ctypes.c_void_p]
+        _gen_lib = lib
+    return _gen_lib
+
+
+def device_generate(out, dtype: str, offsets, fams, seeds) -> None:
+    """Fill the device tensor ``out`` with arrays [offsets[j], offsets[j+1]) of
+    family fams[j] (names) from seeds[j], exactly as ``family`` would on the host."""
+    import torch
+    lib = _load_gen()
+    offs = np.ascontiguousarray(offsets, dtype=np.uint64)
+    fc = np.ascontiguousarray([FAMILY_CODE[f] for f in fams], dtype=np.int32)
+    sd = np.ascontiguousarray(np.asarray(seeds, dtype=np.uint64))
+    count = len(fc)
+    assert offs.size == count + 1 and sd.size == count
+    assert out.is_cuda and out.numel() >= int(offs[-1])
+    stream = torch.cuda.current_stream(out.device).cuda_stream
+    rc = lib.tsqs_inputs_generate(out.data_ptr(), DTYPE_CODE[dtype], offs.ctypes.data,
+                                  fc.ctypes.data, sd.ctypes.data, count, stream)
+    if rc != 0:
+        raise RuntimeError("tsqs_inputs_generate failed (%d)" % rc)
+
+
+def device_family(name: str, n: int, dtype="int32", seed: int | None = None, config: int = 2,
+                  device="cuda:0"):
+    """``family(name, n, dtype, seed)`` generated directly in device memory."""
+    import torch
+    if seed is None:
+        seed = seed_for(config, name)
+    t = torch.empty(n, dtype=getattr(torch, TORCH_DTYPE[dtype]), device=device)
+    device_generate(t, dtype, np.array([0, n], dtype=np.uint64), [name], [seed])
+    return t
+
+
+def batch_plan(seed: int, count: int, lo_log2: int = 4, hi_log2: int = 20,
+               max_total: int | None = None):
+    """Sizes, offsets, families and per-array seeds of ``batch`` (no keys)."""
+    sizes = batch_sizes(seed, count, lo_log2, hi_log2)
+    fams = batch_families(seed, count)
+    if max_total is not None:
+        cs = np.cumsum(sizes)
+        keep = int(np.searchsorted(cs, max_total, side="right"))
+        sizes, fams = sizes[:keep], fams[:keep]
+    offs = np.zeros(len(sizes) + 1, dtype=np.uint64)
+    offs[1:] = np.cumsum(sizes)
+    seeds = np.uint64(seed + 0x100000) + np.arange(len(sizes), dtype=np.uint64)
+    return sizes, offs, fams, seeds
+
+
+def device_batch(seed: int, count: int, lo_log2: int = 4, hi_log2: int = 20, dtype="int32",
+                 max_total: int | None = None, device="cuda:0"):
+    """``batch(...)`` generated directly in device memory: (tensor, offsets, families)."""
+    import torch
+    sizes, offs, fams, seeds = batch_plan(seed, count, lo_log2, hi_log2, max_total)
+    t = torch.empty(int(offs[-1]), dtype=getattr(torch, TORCH_DTYPE[dtype]), device=device)
+    device_generate(t, dtype, offs, fams, seeds)
+    return t, offs, fams
