@@ -18,7 +18,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libtsqs.so")
 
 INT32, UINT32, INT64, UINT64, FLOAT32 = 0, 1, 2, 3, 4
-OK, EINVAL, ENOMEM, EDEVICE, EUNSUPPORTED, EINTERNAL = 0, -1, -2, -3, -4, -5
+OK, EINVAL, ENOMEM, EDEVICE, EUNSUPPORTED, EINTERNAL, EAGAIN = 0, -1, -2, -3, -4, -5, -6
 OPT_SMALL_MAX, OPT_SAMPLES, OPT_DEPTH_FACTOR, OPT_PIVOT_MODE = 1, 2, 3, 4
 OPT_SEED, OPT_TIMING, OPT_PART_GRID, OPT_FINISH_GRID = 5, 6, 7, 8
 MAX_LEVELS = 192
@@ -26,6 +26,9 @@ MAX_LEVELS = 192
 SYMBOLS = ["tsqs_sort", "tsqs_sort_pairs", "tsqs_sort_batch", "tsqs_free_storage",
            "tsqs_set_option", "tsqs_get_option", "tsqs_get_stats", "tsqs_strerror",
            "tsqs_version"]
+QUEUE_SYMBOLS = ["tsqs_queue_open", "tsqs_queue_submit", "tsqs_queue_step", "tsqs_queue_poll",
+                 "tsqs_queue_result", "tsqs_queue_reap", "tsqs_queue_release",
+                 "tsqs_queue_info", "tsqs_queue_close"]
 
 
 class Stats(ctypes.Structure):
@@ -98,6 +101,19 @@ def load_library():
     lib.tsqs_strerror.restype = ctypes.c_char_p
     lib.tsqs_version.argtypes = []
     lib.tsqs_version.restype = ctypes.c_int
+    u64p = ctypes.POINTER(ctypes.c_uint64)
+    lib.tsqs_queue_open.argtypes = [sz, vp, ctypes.POINTER(vp)]
+    lib.tsqs_queue_submit.argtypes = [vp, vp, sz, ctypes.c_int, u64p]
+    lib.tsqs_queue_step.argtypes = [vp]
+    lib.tsqs_queue_poll.argtypes = [vp, ctypes.c_uint64]
+    lib.tsqs_queue_result.argtypes = [vp, ctypes.c_uint64, ctypes.POINTER(vp),
+                                      ctypes.POINTER(sz)]
+    lib.tsqs_queue_reap.argtypes = [vp, vp, sz, ctypes.POINTER(sz)]
+    lib.tsqs_queue_release.argtypes = [vp, ctypes.c_uint64]
+    lib.tsqs_queue_info.argtypes = [vp, u64p, u64p, u64p, u64p, u64p]
+    lib.tsqs_queue_close.argtypes = [vp]
+    for name in QUEUE_SYMBOLS:
+        getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -197,3 +213,90 @@ def get_stats() -> dict:
     s = Stats()
     _check(load_library().tsqs_get_stats(ctypes.byref(s)))
     return s.as_dict()
+
+
+class _DeviceView:
+    """__cuda_array_interface__ of a device buffer the library owns (no copy)."""
+
+    def __init__(self, ptr: int, n: int, typestr: str):
+        self.__cuda_array_interface__ = {"shape": (n,), "typestr": typestr,
+                                         "data": (ptr, False), "version": 2}
+
+
+_TYPESTR = {INT32: "<i4", UINT32: "<i4", INT64: "<i8", UINT64: "<i8", FLOAT32: "<f4"}
+
+
+class Queue:
+    """Serving queue (``include/tsqs_queue.h``): requests are copied into a
+    device arena held within ``budget_bytes`` and sorted by ticks that batch every
+    live request of a key type into the same launches."""
+
+    QUEUED, RUNNING, DONE = 0, 1, 2
+
+    def __init__(self, budget_bytes: int):
+        self._lib = load_library()
+        self._q = ctypes.c_void_p()
+        _check(self._lib.tsqs_queue_open(int(budget_bytes), _stream_handle(),
+                                         ctypes.byref(self._q)))
+        self._keep = {}
+
+    def submit(self, keys, dtype_code: int | None = None) -> int:
+        """Queue a sort of the device tensor ``keys`` (left unchanged; it must stay
+        valid until the request is admitted).  Returns a ticket."""
+        _check_tensor(keys, "keys")
+        dt = _dtype_code(keys) if dtype_code is None else dtype_code
+        t = ctypes.c_uint64()
+        _check(self._lib.tsqs_queue_submit(self._q, ctypes.c_void_p(keys.data_ptr()),
+                                           keys.numel(), dt, ctypes.byref(t)))
+        self._keep[t.value] = (keys, dt)
+        return t.value
+
+    def step(self) -> None:
+        _check(self._lib.tsqs_queue_step(self._q))
+
+    def poll(self, ticket: int) -> int:
+        rc = self._lib.tsqs_queue_poll(self._q, int(ticket))
+        if rc < 0:
+            _check(rc)
+        return rc
+
+    def result(self, ticket: int):
+        """The sorted keys of a done request, as a tensor viewing the arena
+        (valid until ``release``)."""
+        import torch
+        ptr, n = ctypes.c_void_p(), ctypes.c_size_t()
+        _check(self._lib.tsqs_queue_result(self._q, int(ticket), ctypes.byref(ptr),
+                                           ctypes.byref(n)))
+        src, dt = self._keep[int(ticket)]
+        view = torch.as_tensor(_DeviceView(int(ptr.value), int(n.value), _TYPESTR[dt]),
+                               device=src.device)
+        return view
+
+    def reap(self, cap: int = 4096) -> list:
+        """Tickets found done since the previous call."""
+        buf = (ctypes.c_uint64 * cap)()
+        n = ctypes.c_size_t()
+        _check(self._lib.tsqs_queue_reap(self._q, buf, cap, ctypes.byref(n)))
+        return list(buf[:n.value])
+
+    def release(self, ticket: int) -> None:
+        _check(self._lib.tsqs_queue_release(self._q, int(ticket)))
+        self._keep.pop(int(ticket), None)
+
+    def info(self) -> dict:
+        v = [ctypes.c_uint64() for _ in range(5)]
+        _check(self._lib.tsqs_queue_info(self._q, *[ctypes.byref(x) for x in v]))
+        return dict(zip(["queued", "running", "done", "arena_used", "arena_bytes"],
+                        [x.value for x in v]))
+
+    def close(self) -> None:
+        if self._q:
+            _check(self._lib.tsqs_queue_close(self._q))
+            self._q = ctypes.c_void_p()
+            self._keep.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

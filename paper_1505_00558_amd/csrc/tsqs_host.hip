@@ -9,12 +9,18 @@
 // are launched, eight at a time.
 #include "tsqs.h"
 #include "tsqs_kernels.hpp"
+#include "tsqs_queue.h"
 
 #include <hip/hip_runtime.h>
 
 #include <climits>
 #include <cstring>
+#include <deque>
+#include <iterator>
+#include <map>
 #include <mutex>
+#include <new>
+#include <unordered_map>
 #include <vector>
 
 using namespace tsqs;
@@ -119,22 +125,41 @@ uint32_t mix32(uint64_t z) {
   return (uint32_t)(z ^ (z >> 31));
 }
 
+// Small-part geometry of a key type: one wave sorts up to wave_max keys, the
+// workgroup up to small_max (the option, clipped to what registers and LDS
+// hold); fin_lds is the dynamic LDS of the finish kernel.
+struct FinGeom {
+  uint32_t small_max, wave_max;
+  size_t fin_lds;
+};
+
+template <int DT, bool HASV>
+FinGeom fin_geom(size_t lds_budget, int64_t small_opt) {
+  using B = typename Codec<DT>::B;
+  using RT = typename Rec<B, HASV>::T;
+  const uint32_t me = (uint32_t)max_e<RT>();
+  uint32_t wave_max = 64 * me;
+  while (wave_max > 64 && kFinNW * lds_pad_host(wave_max) * sizeof(RT) > lds_budget) wave_max >>= 1;
+  uint32_t wg_max = kFinNT * me;
+  while (wg_max > wave_max && lds_pad_host(wg_max) * sizeof(RT) > lds_budget) wg_max >>= 1;
+  uint32_t small_max = (uint32_t)small_opt;
+  if (small_max > wg_max) small_max = wg_max;
+  if (small_max < 16) small_max = 16;
+  uint32_t P = 1;
+  while (P < small_max) P <<= 1;
+  size_t fin_lds = lds_pad_host(P) * sizeof(RT);
+  if (kFinNW * lds_pad_host(wave_max) * sizeof(RT) > fin_lds) fin_lds = kFinNW * lds_pad_host(wave_max) * sizeof(RT);
+  return FinGeom{small_max, wave_max, fin_lds};
+}
+
 template <int DT, bool HASV>
 int run_t(Workspace &w, void *keys, uint32_t *vals, const uint64_t *h_offs, size_t nroots,
           uint64_t n, uint64_t max_root, hipStream_t s) {
   using B = typename Codec<DT>::B;
-  using RT = typename Rec<B, HASV>::T;
   const size_t kb = sizeof(B);
   if (((uintptr_t)keys % kb) != 0 || ((uintptr_t)vals % 4) != 0) return TSQS_EINVAL;
-  // small parts: one wave up to wave_max keys, the workgroup up to 8192, within LDS
-  const uint32_t me = (uint32_t)max_e<RT>();
-  uint32_t wave_max = 64 * me;
-  while (wave_max > 64 && kFinNW * lds_pad_host(wave_max) * sizeof(RT) > w.lds_budget) wave_max >>= 1;
-  uint32_t wg_max = kFinNT * me;
-  while (wg_max > wave_max && lds_pad_host(wg_max) * sizeof(RT) > w.lds_budget) wg_max >>= 1;
-  uint32_t small_max = (uint32_t)g_opt.small_max;
-  if (small_max > wg_max) small_max = wg_max;
-  if (small_max < 16) small_max = 16;
+  const FinGeom geo = fin_geom<DT, HASV>(w.lds_budget, g_opt.small_max);
+  const uint32_t small_max = geo.small_max, wave_max = geo.wave_max;
 
   // workspace sizes
   const size_t seg_cap = (size_t)(n / (small_max + 1)) + 2;
@@ -187,6 +212,15 @@ int run_t(Workspace &w, void *keys, uint32_t *vals, const uint64_t *h_offs, size
   c.stats = w.stats;
   c.err = (unsigned int *)(w.stats + kStripes * kStatWords);
   c.roots = h_offs ? w.offs : nullptr;
+  c.root_recs = nullptr;
+  c.req_left = nullptr;
+  c.req_flag = nullptr;
+  c.done_ring = nullptr;
+  c.done_pos = nullptr;
+  c.done_cap = 0;
+  c.pad1 = 0;
+  c.root_level = 0;
+  c.ring = 0;
   c.n = n;
   c.nroots = (uint32_t)nroots;
   c.small_max = small_max;
@@ -202,10 +236,7 @@ int run_t(Workspace &w, void *keys, uint32_t *vals, const uint64_t *h_offs, size
   const int part_grid = g_opt.part_grid > 0 ? (int)g_opt.part_grid : 4 * w.cus;
   const int fin_grid = g_opt.finish_grid > 0 ? (int)g_opt.finish_grid : 4 * w.cus;
   const int plan_grid = 4 * w.cus;
-  uint32_t P = 1;
-  while (P < small_max) P <<= 1;
-  size_t fin_lds = lds_pad_host(P) * sizeof(RT);
-  if (kFinNW * lds_pad_host(wave_max) * sizeof(RT) > fin_lds) fin_lds = kFinNW * lds_pad_host(wave_max) * sizeof(RT);
+  const size_t fin_lds = geo.fin_lds;
   if (fin_lds > 65536) {
     HIPCHK(hipFuncSetAttribute((const void *)k_finish<DT, HASV>,
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)fin_lds));
@@ -415,6 +446,7 @@ const char *tsqs_strerror(int code) {
     case TSQS_EDEVICE: return "HIP runtime error";
     case TSQS_EUNSUPPORTED: return "unsupported dtype or option";
     case TSQS_EINTERNAL: return "internal capacity or level limit exceeded";
+    case TSQS_EAGAIN: return "not yet (request not done, or no room yet)";
     default: return "unknown error code";
   }
 }
@@ -422,3 +454,5 @@ const char *tsqs_strerror(int code) {
 int tsqs_version(void) { return 1; }
 
 }  // extern "C"
+
+#include "tsqs_queue_impl.hpp"

@@ -109,8 +109,10 @@ struct Seg {                 // one part of a level
   uint64_t pivot;            // encoded pivot
   uint32_t len;
   uint32_t chunk_begin;      // first chunk of this part in the level's chunk space
-  uint32_t depth;
+  uint32_t depth;            // recursion depth: the part lives in K when even, S when odd
   uint32_t dmax;             // depth limit of the array it came from
+  uint32_t req;              // request (array) the part belongs to
+  uint32_t pad;
 };
 
 struct FinItem {             // work of the finish kernel (len 0 = empty slot)
@@ -118,7 +120,13 @@ struct FinItem {             // work of the finish kernel (len 0 = empty slot)
   uint64_t src;              // band: first staged payload in VE
   uint64_t pivot;            // band: encoded key of the band
   uint32_t len;
-  uint32_t kind;             // bit 1: small part lives in S
+  uint32_t kind;             // bit 1: small part lives in S; bits 2..31: request
+};
+
+struct RootRec {             // an array to sort, given by place instead of by offsets
+  uint64_t off;
+  uint32_t len;
+  uint32_t req;
 };
 
 struct LevelCtl {
@@ -141,6 +149,15 @@ struct Ctx {
   unsigned long long *stats;         // kStripes x kStatWords
   unsigned int *err;
   const uint64_t *roots;             // nroots+1 offsets, or null: one root [0, n)
+  const RootRec *root_recs;          // or the roots one by one (then roots is ignored)
+  unsigned long long *req_left;      // keys not yet final, per request (null: not tracked)
+  volatile unsigned int *req_flag;   // host-visible: set to 1 when a request's count hits 0
+  volatile unsigned int *done_ring;  // host-visible: request + 1 of each completion, in order
+  unsigned int *done_pos;            // completions so far (next ring position)
+  uint32_t done_cap;                 // ring entries
+  uint32_t pad1;
+  int root_level;                    // level whose parts and finish work the roots join
+  uint32_t ring;                     // 1: level indices wrap around kMaxLevels
   uint64_t n;
   uint32_t nroots;
   uint32_t small_max;
@@ -313,25 +330,49 @@ __device__ inline void stat_add(const Ctx &c, int which, unsigned long long v) {
   if (v) atomicAdd(&c.stats[(size_t)(blockIdx.x % kStripes) * kStatWords + which], v);
 }
 
+// Index of the level after d (with ring, indices wrap; without, kMaxLevels is
+// out of range and reported as an error where it is used).
+__device__ inline int level_after(const Ctx &c, int d) {
+  return d + 1 < kMaxLevels ? d + 1 : (c.ring ? 0 : kMaxLevels);
+}
+
+// n keys of request req are final (one thread; the caller has made its stores
+// visible at device scope).  The thread that brings the count to zero raises the
+// request's host-visible flag and appends the request to the completion ring.
+__device__ inline void req_final(const Ctx &c, uint32_t req, uint32_t n) {
+  if (n == 0) return;
+  const unsigned long long old = atomicSub(&c.req_left[req], (unsigned long long)n);
+  if (old == (unsigned long long)n) {
+    __threadfence_system();
+    c.req_flag[req] = 1u;
+    const unsigned int p = atomicAdd(c.done_pos, 1u);
+    c.done_ring[p % c.done_cap] = req + 1u;
+  }
+}
+
 // Writes the small-part item of a child into its fixed slot of the wave or the
-// workgroup array and an empty item into the other (one lane).
-__device__ inline void put_small(const Ctx &c, uint32_t slot, uint64_t off, uint32_t len, bool in_s) {
+// workgroup array and an empty item into the other (one lane).  A single key
+// already in K needs no work and is final at once.
+__device__ inline void put_small(const Ctx &c, uint32_t slot, uint64_t off, uint32_t len, bool in_s,
+                                 uint32_t req) {
   const bool real = len > 1 || (len == 1 && in_s);
   const bool wave = next_pow2(len) <= c.wave_max;
   FinItem it;
-  it.off = off; it.src = 0; it.pivot = 0; it.kind = in_s ? 2u : 0u;
+  it.off = off; it.src = 0; it.pivot = 0; it.kind = (in_s ? 2u : 0u) | (req << 2);
   it.len = (real && wave) ? len : 0u;
   c.finw[slot] = it;
   it.len = (real && !wave) ? len : 0u;
   c.fin[slot] = it;
+  if (!real && len == 1 && c.req_left) req_final(c, req, 1u);
 }
 
 // Band of a part: short bands go to the part's band slot, long ones are cut
 // into kBandChunk pieces appended to the long-band list (one lane).
 __device__ inline void put_band(const Ctx &c, int level, uint32_t si, uint64_t off, uint64_t src,
-                                uint32_t len, uint64_t pivot) {
+                                uint32_t len, uint64_t pivot, uint32_t req) {
   FinItem it;
-  it.off = off; it.src = src; it.pivot = pivot; it.len = len <= kBandChunk ? len : 0u; it.kind = 0;
+  it.off = off; it.src = src; it.pivot = pivot; it.len = len <= kBandChunk ? len : 0u;
+  it.kind = req << 2;
   c.band[si] = it;
   if (len <= kBandChunk) return;
   const uint32_t nch = (len + kBandChunk - 1) / kBandChunk;
@@ -369,7 +410,7 @@ __device__ inline typename Codec<DT>::B child_pivot(const Ctx &c, uint64_t off, 
 struct Pending {
   uint64_t off0, off1, pivot0, pivot1;
   uint32_t len0, len1, chunks0, chunks1;
-  uint32_t n;
+  uint32_t n, req;
 };
 
 template <int DT, bool HASV>
@@ -411,7 +452,7 @@ __device__ inline void flush_parts(const Ctx &c, int lvl_next, const Pending &pd
       Seg s;
       s.off = q ? pd.off1 : pd.off0; s.pivot = q ? pd.pivot1 : pd.pivot0;
       s.len = q ? pd.len1 : pd.len0; s.chunk_begin = cb;
-      s.depth = depth; s.dmax = dmax;
+      s.depth = depth; s.dmax = dmax; s.req = pd.req; s.pad = 0;
       segs[idx] = s;
       ctr[(size_t)idx * kCtrStride] = 0ull;
       if (HASV) ctr[(size_t)idx * kCtrStride + 1] = 0ull;
@@ -424,24 +465,25 @@ __device__ inline void flush_parts(const Ctx &c, int lvl_next, const Pending &pd
 // A child of depth `depth`: small -> slot item; large -> pivot + pending part.
 template <int DT, bool HASV>
 __device__ inline void child(const Ctx &c, uint32_t slot, uint64_t off, uint32_t len, uint32_t depth,
-                             uint32_t dmax, uint32_t *hist, Pending &pd,
+                             uint32_t dmax, uint32_t req, uint32_t *hist, Pending &pd,
                              unsigned long long &small_parts, unsigned long long &small_keys) {
   const bool in_s = (depth & 1) != 0;
   const uint32_t lane = lane_id();
   if (len <= c.small_max) {
     if (lane == 0) {
-      put_small(c, slot, off, len, in_s);
+      put_small(c, slot, off, len, in_s, req);
       if (len > 1 || (len == 1 && in_s)) { small_parts++; small_keys += len; }
     }
     return;
   }
   const typename Codec<DT>::B p = child_pivot<DT>(c, off, len, depth, dmax, hist);
   if (lane == 0) {
-    put_small(c, slot, 0, 0, false);
+    put_small(c, slot, 0, 0, false, req);
     const uint32_t ch = part_chunks<DT, HASV>((depth & 1) ? c.S : c.K, off, len);
     if (pd.n == 0) { pd.off0 = off; pd.pivot0 = (uint64_t)p; pd.len0 = len; pd.chunks0 = ch; }
     else { pd.off1 = off; pd.pivot1 = (uint64_t)p; pd.len1 = len; pd.chunks1 = ch; }
     pd.n++;
+    pd.req = req;
   }
 }
 
@@ -455,6 +497,14 @@ __global__ void k_reset(Ctx c) {
   if (threadIdx.x == 0) *c.err = 0u;
 }
 
+// Clears the counters of level `lvl` (a serving tick reuses level indices
+// around a ring; the counters of the next level must start at zero).
+__global__ void k_level_clear(Ctx c, int lvl) {
+  if (threadIdx.x == 0) {
+    c.lvl[lvl].packed = 0ull; c.lvl[lvl].keys = 0ull; c.lvl[lvl].nbig = 0u;
+  }
+}
+
 // Roots: one wave per array (workgroup-uniform iterations).  A root is depth 0,
 // lives in K, and its small-part slot is 2 * seg_cap + root index.
 template <int DT, bool HASV>
@@ -466,18 +516,26 @@ __global__ __launch_bounds__(kPlanNT) void k_init(Ctx c) {
   unsigned long long small_parts = 0, small_keys = 0;
   for (uint32_t base = blockIdx.x * kPlanNW; base < c.nroots; base += gridDim.x * kPlanNW) {
     const uint32_t j = base + wv;
-    Pending pd = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    Pending pd = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
     uint32_t dmax = 0;
     if (j < c.nroots) {
-      const uint64_t off = c.roots ? c.roots[j] : 0ull;
-      const uint64_t end = c.roots ? c.roots[j + 1] : c.n;
-      const uint32_t len = (uint32_t)(end - off);
+      uint64_t off;
+      uint32_t len, req = 0;
+      if (c.root_recs) {
+        const RootRec r = c.root_recs[j];
+        off = r.off; len = r.len; req = r.req;
+        if (c.req_left && lane_id() == 0) c.req_left[req] = len;
+      } else {
+        off = c.roots ? c.roots[j] : 0ull;
+        len = (uint32_t)((c.roots ? c.roots[j + 1] : c.n) - off);
+      }
       uint32_t lg = 0;
       while (lg < 32 && (1ull << lg) < (unsigned long long)len) lg++;
       dmax = c.depth_factor * lg;
-      child<DT, HASV>(c, 2 * c.seg_cap + j, off, len, 0u, dmax, hist[wv], pd, small_parts, small_keys);
+      child<DT, HASV>(c, 2 * c.seg_cap + j, off, len, 0u, dmax, req, hist[wv], pd, small_parts,
+                      small_keys);
     }
-    flush_parts<DT, HASV>(c, 0, pd, 0u, dmax, sh_n, sh_ch, sh_keys, &sh_old);
+    flush_parts<DT, HASV>(c, c.root_level, pd, 0u, dmax, sh_n, sh_ch, sh_keys, &sh_old);
   }
   if ((threadIdx.x & 63u) == 0) {
     stat_add(c, kStSmallParts, small_parts);
@@ -537,12 +595,7 @@ __global__ __launch_bounds__(kPartNT) void k_partition(Ctx c, int d) {
 
   const Seg *segs = (d & 1) ? c.seg1 : c.seg0;
   unsigned long long *ctr = (d & 1) ? c.ctr1 : c.ctr0;
-  const B *X = (const B *)((d & 1) ? c.S : c.K);
-  B *Y = (B *)((d & 1) ? c.K : c.S);
-  const uint32_t *VX = (d & 1) ? c.VS : c.V;
-  uint32_t *VY = (d & 1) ? c.V : c.VS;
   const uint32_t tid = threadIdx.x, lane = tid & 63u, w = tid >> 6;
-  const uint64_t xabs0 = (uint64_t)(uintptr_t)X / KB;
 
   // part containing chunk t0: 64-ary search by wave 0
   if (w == 0) {
@@ -571,6 +624,13 @@ __global__ __launch_bounds__(kPartNT) void k_partition(Ctx c, int d) {
       s = segs[pi];
       nxt_begin = (pi + 1 < nseg) ? segs[pi + 1].chunk_begin : 0xFFFFFFFFu;
     }
+    // source X and destination Y by the part's depth (K when even, S when odd)
+    const bool odd = (s.depth & 1u) != 0;
+    const B *X = (const B *)(odd ? c.S : c.K);
+    B *Y = (B *)(odd ? c.K : c.S);
+    const uint32_t *VX = odd ? c.VS : c.V;
+    uint32_t *VY = odd ? c.V : c.VS;
+    const uint64_t xabs0 = (uint64_t)(uintptr_t)X / KB;
     // chunk window [W, W + CH) in absolute key coordinates; the keys of this
     // part occupy window indices [lo, hi)
     const uint64_t A0 = xabs0 + s.off, A1 = A0 + s.len;
@@ -738,23 +798,26 @@ __global__ __launch_bounds__(kPlanNT) void k_plan(Ctx c, int d) {
   unsigned long long small_parts = 0, small_keys = 0, band_keys = 0;
   for (uint32_t base = blockIdx.x * kPlanNW; base < nseg; base += gridDim.x * kPlanNW) {
     const uint32_t si = base + wv;
-    Pending pd = {0, 0, 0, 0, 0, 0, 0, 0, 0};
-    uint32_t dmax = 0;
+    Pending pd = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+    uint32_t dmax = 0, cdepth = 0;
     if (si < nseg) {
       const Seg s = segs[si];
       const unsigned long long cv = ctr[(size_t)si * kCtrStride];
       const uint32_t L = (uint32_t)cv, G = (uint32_t)(cv >> 32);
       const uint32_t E = s.len - L - G;
       dmax = s.dmax;
+      cdepth = s.depth + 1;
       if (lane == 0) {
-        put_band(c, d, si, s.off + L, s.off, E, s.pivot);
+        put_band(c, d, si, s.off + L, s.off, E, s.pivot, s.req);
         band_keys += E;
       }
-      child<DT, HASV>(c, 2 * si, s.off, L, s.depth + 1, dmax, hist[wv], pd, small_parts, small_keys);
-      child<DT, HASV>(c, 2 * si + 1, s.off + s.len - G, G, s.depth + 1, dmax, hist[wv], pd,
+      child<DT, HASV>(c, 2 * si, s.off, L, cdepth, dmax, s.req, hist[wv], pd, small_parts,
+                      small_keys);
+      child<DT, HASV>(c, 2 * si + 1, s.off + s.len - G, G, cdepth, dmax, s.req, hist[wv], pd,
                       small_parts, small_keys);
     }
-    flush_parts<DT, HASV>(c, d + 1, pd, (uint32_t)d + 1, dmax, sh_n, sh_ch, sh_keys, &sh_old);
+    // each wave writes its own records, with its own depth and limit
+    flush_parts<DT, HASV>(c, level_after(c, d), pd, cdepth, dmax, sh_n, sh_ch, sh_keys, &sh_old);
   }
   if (lane == 0) {
     stat_add(c, kStSmallParts, small_parts);
@@ -1001,7 +1064,9 @@ __device__ void sort_group(const Ctx &c, const FinItem &it,
       if (x < len) K[off + x] = Codec<DT>::dec(R::code(lds[lds_pad(x)]));
     }
   }
+  if (c.req_left) __threadfence();
   group_sync<NT>();
+  if (c.req_left && t == 0) req_final(c, it.kind >> 2, len);
 }
 
 template <int DT, bool HASV>
@@ -1029,11 +1094,17 @@ __global__ __launch_bounds__(kFinNT) void k_finish(Ctx c, int d) {
   const uint32_t nbig = c.lvl[d].nbig;
   if (nseg > c.seg_cap || nbig > c.big_cap) return;
   const uint32_t nchild = 2 * nseg;
-  const uint32_t nslots = nchild + (d == 0 ? c.nroots : 0u);
+  const uint32_t nslots = nchild + (d == c.root_level ? c.nroots : 0u);
   const uint32_t tid = threadIdx.x;
   for (uint32_t ii = blockIdx.x; ii < nbig + nslots; ii += gridDim.x) {
     if (ii < nbig) {
-      fill_band<DT, HASV>(c, c.big[ii], tid, kFinNT);
+      const FinItem bg = c.big[ii];
+      fill_band<DT, HASV>(c, bg, tid, kFinNT);
+      if (c.req_left) {
+        __threadfence();
+        __syncthreads();
+        if (tid == 0) req_final(c, bg.kind >> 2, bg.len);
+      }
       continue;
     }
     const uint32_t q = ii - nbig;
@@ -1055,7 +1126,14 @@ __global__ __launch_bounds__(kFinNT) void k_finish(Ctx c, int d) {
   for (uint32_t q = gw; q < nslots + nseg; q += nw) {
     if (q >= nslots) {
       const FinItem bd = c.band[q - nslots];
-      if (bd.len) fill_band<DT, HASV>(c, bd, lane, kWave);
+      if (bd.len) {
+        fill_band<DT, HASV>(c, bd, lane, kWave);
+        if (c.req_left) {
+          __threadfence();
+          __builtin_amdgcn_wave_barrier();
+          if (lane == 0) req_final(c, bd.kind >> 2, bd.len);
+        }
+      }
       continue;
     }
     const uint32_t slot = q < nchild ? q : 2 * c.seg_cap + (q - nchild);

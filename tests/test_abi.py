@@ -18,8 +18,8 @@ def lib():
     return tsqs.load_library()
 
 
-def _declared():
-    with open(os.path.join(ROOT, "include", "tsqs.h")) as f:
+def _declared(header="tsqs.h"):
+    with open(os.path.join(ROOT, "include", header)) as f:
         txt = f.read()
     return sorted(set(re.findall(r"\b(tsqs_[a-z_]+)\s*\(", txt)))
 
@@ -36,12 +36,15 @@ def test_exports_every_declared_symbol(lib):
     for n in _declared():
         assert hasattr(lib, n), n
     assert sorted(tsqs.SYMBOLS) == _declared()
+    for n in _declared("tsqs_queue.h"):
+        assert hasattr(lib, n), n
+    assert sorted(tsqs.QUEUE_SYMBOLS) == _declared("tsqs_queue.h")
 
 
 def test_version_and_strerror(lib):
     assert lib.tsqs_version() == 1
     import paper_1505_00558_amd as tsqs
-    for code in (0, -1, -2, -3, -4, -5):
+    for code in (0, -1, -2, -3, -4, -5, -6):
         assert tsqs.strerror(code) and tsqs.strerror(code) != "unknown error code"
     assert tsqs.strerror(-99) == "unknown error code"
 
@@ -116,3 +119,20 @@ def test_product_path_has_no_oracle_import():
                 with open(os.path.join(dirpath, fn)) as f:
                     txt = f.read()
                 assert "oracle" not in txt, fn
+
+
+def test_queue_argument_errors(lib):
+    """Queue calls reject bad arguments before any HIP call."""
+    fake = ctypes.c_void_p(0x1000)
+    out = ctypes.c_void_p()
+    t = ctypes.c_uint64()
+    assert lib.tsqs_queue_open(1 << 30, None, None) == -1
+    assert lib.tsqs_queue_open(1 << 20, None, ctypes.byref(out)) == -1     # below 64 MiB
+    assert lib.tsqs_queue_submit(None, fake, 5, 0, ctypes.byref(t)) == -1
+    assert lib.tsqs_queue_step(None) == -1
+    assert lib.tsqs_queue_poll(None, 1) == -1
+    assert lib.tsqs_queue_result(None, 1, None, None) == -1
+    assert lib.tsqs_queue_release(None, 1) == -1
+    assert lib.tsqs_queue_reap(None, None, 0, None) == -1
+    assert lib.tsqs_queue_info(None, None, None, None, None, None) == -1
+    assert lib.tsqs_queue_close(None) == -1
