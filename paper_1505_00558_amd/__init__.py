@@ -20,7 +20,7 @@ LIB_PATH = os.path.join(HERE, "libtsqs.so")
 INT32, UINT32, INT64, UINT64, FLOAT32 = 0, 1, 2, 3, 4
 OK, EINVAL, ENOMEM, EDEVICE, EUNSUPPORTED, EINTERNAL, EAGAIN = 0, -1, -2, -3, -4, -5, -6
 OPT_SMALL_MAX, OPT_SAMPLES, OPT_DEPTH_FACTOR, OPT_PIVOT_MODE = 1, 2, 3, 4
-OPT_SEED, OPT_TIMING, OPT_PART_GRID, OPT_FINISH_GRID = 5, 6, 7, 8
+OPT_SEED, OPT_TIMING, OPT_PART_GRID, OPT_FINISH_GRID, OPT_FINISH_ALGO = 5, 6, 7, 8, 9
 MAX_LEVELS = 192
 
 SYMBOLS = ["tsqs_sort", "tsqs_sort_pairs", "tsqs_sort_batch", "tsqs_free_storage",

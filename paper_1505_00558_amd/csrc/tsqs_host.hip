@@ -36,6 +36,7 @@ struct Options {
   int64_t timing = 0;
   int64_t part_grid = 0;
   int64_t finish_grid = 0;
+  int64_t finish_algo = 0;
 };
 
 struct Workspace {
@@ -238,7 +239,9 @@ int run_t(Workspace &w, void *keys, uint32_t *vals, const uint64_t *h_offs, size
   const int plan_grid = 4 * w.cus;
   const size_t fin_lds = geo.fin_lds;
   if (fin_lds > 65536) {
-    HIPCHK(hipFuncSetAttribute((const void *)k_finish<DT, HASV>,
+    HIPCHK(hipFuncSetAttribute((const void *)k_finish<DT, HASV, false>,
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)fin_lds));
+    HIPCHK(hipFuncSetAttribute((const void *)k_finish<DT, HASV, true>,
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)fin_lds));
   }
   const size_t waves_init = (nroots + kPlanNW - 1) / kPlanNW;
@@ -271,7 +274,10 @@ int run_t(Workspace &w, void *keys, uint32_t *vals, const uint64_t *h_offs, size
       }
       if (g_opt.timing) HIPCHK(hipEventRecord(w.ev[2 * d + 1], s));
       if (!idle) hipLaunchKernelGGL((k_plan<DT, HASV>), dim3(plan_grid), dim3(kPlanNT), 0, s, c, d);
-      hipLaunchKernelGGL((k_finish<DT, HASV>), dim3(fin_grid), dim3(kFinNT), fin_lds, s, c, d);
+      if (g_opt.finish_algo == 0)
+        hipLaunchKernelGGL((k_finish<DT, HASV, true>), dim3(fin_grid), dim3(kFinNT), fin_lds, s, c, d);
+      else
+        hipLaunchKernelGGL((k_finish<DT, HASV, false>), dim3(fin_grid), dim3(kFinNT), fin_lds, s, c, d);
       HIPCHK(hipGetLastError());
     }
     HIPCHK(hipMemcpyAsync(w.h_lvl, w.lvl, sizeof(LevelCtl) * (size_t)(d + 1), hipMemcpyDeviceToHost, s));
@@ -411,6 +417,7 @@ int tsqs_set_option(int key, int64_t v) {
     case TSQS_OPT_TIMING: g_opt.timing = v ? 1 : 0; return TSQS_OK;
     case TSQS_OPT_PART_GRID: if (v < 0 || v > 65536) return TSQS_EINVAL; g_opt.part_grid = v; return TSQS_OK;
     case TSQS_OPT_FINISH_GRID: if (v < 0 || v > 65536) return TSQS_EINVAL; g_opt.finish_grid = v; return TSQS_OK;
+    case TSQS_OPT_FINISH_ALGO: if (v < 0 || v > 1) return TSQS_EINVAL; g_opt.finish_algo = v; return TSQS_OK;
     default: return TSQS_EUNSUPPORTED;
   }
 }
@@ -426,6 +433,7 @@ int64_t tsqs_get_option(int key) {
     case TSQS_OPT_TIMING: return g_opt.timing;
     case TSQS_OPT_PART_GRID: return g_opt.part_grid;
     case TSQS_OPT_FINISH_GRID: return g_opt.finish_grid;
+    case TSQS_OPT_FINISH_ALGO: return g_opt.finish_algo;
     default: return INT64_MIN;
   }
 }

@@ -838,6 +838,7 @@ template <typename B> struct Rec<B, false> {
   __device__ static inline B code(T r) { return r; }
   __device__ static inline uint32_t idx(T) { return 0; }
   __device__ static inline bool less(T a, T b) { return a < b; }
+  __device__ static inline T sel(bool c, T a, T b) { return c ? a : b; }
 };
 template <> struct Rec<uint32_t, true> {
   using T = uint64_t;
@@ -846,6 +847,7 @@ template <> struct Rec<uint32_t, true> {
   __device__ static inline uint32_t code(T r) { return (uint32_t)(r >> 32); }
   __device__ static inline uint32_t idx(T r) { return (uint32_t)r; }
   __device__ static inline bool less(T a, T b) { return a < b; }
+  __device__ static inline T sel(bool c, T a, T b) { return c ? a : b; }
 };
 struct R64 { uint64_t k; uint32_t i; uint32_t pad; };
 template <> struct Rec<uint64_t, true> {
@@ -855,6 +857,14 @@ template <> struct Rec<uint64_t, true> {
   __device__ static inline uint64_t code(T r) { return r.k; }
   __device__ static inline uint32_t idx(T r) { return r.i; }
   __device__ static inline bool less(T a, T b) { return a.k < b.k || (a.k == b.k && a.i < b.i); }
+  // field by field: a select of the whole struct can be lowered through memory
+  __device__ static inline T sel(bool c, T a, T b) {
+    T r;
+    r.k = c ? a.k : b.k;
+    r.i = c ? a.i : b.i;
+    r.pad = 0;
+    return r;
+  }
 };
 
 // Partner exchange inside a wave: the value of lane (lane ^ DD).  Distances
@@ -893,7 +903,7 @@ template <typename T> constexpr int max_e() { return sizeof(T) <= 4 ? 32 : (size
 template <typename R>
 __device__ inline void cas_asc(typename R::T &a, typename R::T &b) {
   const bool sw = R::less(b, a);
-  const typename R::T lo = sw ? b : a, hi = sw ? a : b;
+  const typename R::T lo = R::sel(sw, b, a), hi = R::sel(sw, a, b);
   a = lo; b = hi;
 }
 
@@ -932,8 +942,8 @@ __device__ inline void reverse_if(typename R::T (&v)[E], bool cond) {
 #pragma unroll
   for (int i = 0; i < E / 2; i++) {
     const typename R::T a = v[i], b = v[E - 1 - i];
-    v[i] = cond ? b : a;
-    v[E - 1 - i] = cond ? a : b;
+    v[i] = R::sel(cond, b, a);
+    v[E - 1 - i] = R::sel(cond, a, b);
   }
 }
 
@@ -959,8 +969,8 @@ __device__ inline void cross_stage(typename R::T (&v)[E], bool take_min, int add
 #pragma unroll
     for (int g = 0; g < GB; g++) {
       const bool ol = R::less(o[g], v[i0 + g]);
-      const T mn = ol ? o[g] : v[i0 + g], mx = ol ? v[i0 + g] : o[g];
-      v[i0 + g] = take_min ? mn : mx;
+      const T mn = R::sel(ol, o[g], v[i0 + g]), mx = R::sel(ol, v[i0 + g], o[g]);
+      v[i0 + g] = R::sel(take_min, mn, mx);
     }
   }
 }
@@ -1028,8 +1038,8 @@ __device__ void sort_group(const Ctx &c, const FinItem &it,
         for (int i = 0; i < E; i++) {
           const T o = lds[lds_pad((uint32_t)i * NT + (t ^ dd))];
           const bool ol = R::less(o, v[i]);
-          const T mn = ol ? o : v[i], mx = ol ? v[i] : o;
-          v[i] = take_min ? mn : mx;
+          const T mn = R::sel(ol, o, v[i]), mx = R::sel(ol, v[i], o);
+          v[i] = R::sel(take_min, mn, mx);
         }
         group_sync<NT>();
       }
@@ -1039,6 +1049,126 @@ __device__ void sort_group(const Ctx &c, const FinItem &it,
   }
 #pragma unroll
   for (int i = 0; i < E; i++) lds[lds_pad(t * E + i)] = v[i];
+  group_sync<NT>();
+  if constexpr (HASV) {
+    uint32_t pv[E];
+#pragma unroll
+    for (int i = 0; i < E; i++) {
+      const uint32_t x = (uint32_t)i * NT + t;
+      const uint32_t li = x < len ? R::idx(lds[lds_pad(x)]) : 0u;
+      pv[i] = srcV[off + li];
+    }
+    group_sync<NT>();   // every payload is read before any is overwritten (in-place parts)
+#pragma unroll
+    for (int i = 0; i < E; i++) {
+      const uint32_t x = (uint32_t)i * NT + t;
+      if (x < len) {
+        K[off + x] = Codec<DT>::dec(R::code(lds[lds_pad(x)]));
+        c.V[off + x] = pv[i];
+      }
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < E; i++) {
+      const uint32_t x = (uint32_t)i * NT + t;
+      if (x < len) K[off + x] = Codec<DT>::dec(R::code(lds[lds_pad(x)]));
+    }
+  }
+  if (c.req_left) __threadfence();
+  group_sync<NT>();
+  if (c.req_left && t == 0) req_final(c, it.kind >> 2, len);
+}
+
+// Sort one small part of len <= NT*E keys with NT threads by merging: every
+// thread sorts E consecutive records in registers (a sorting network), then
+// runs of E, 2E, 4E, ... keys are merged pairwise in LDS.  For each merge a
+// thread owns E consecutive outputs: it finds where they start on the merge
+// path of its two runs (binary search along the cross diagonal) and produces
+// them in order, one LDS read per output.  Positions len..Lp-1 (Lp = len
+// rounded up to E) hold padding records, which sort last.
+template <int DT, bool HASV, int NT, int E>
+__device__ void merge_group(const Ctx &c, const FinItem &it,
+                            typename Rec<typename Codec<DT>::B, HASV>::T *lds, uint32_t t) {
+  using B = typename Codec<DT>::B;
+  using R = Rec<B, HASV>;
+  using T = typename R::T;
+  const bool in_s = (it.kind & 2u) != 0;
+  const B *src = (const B *)(in_s ? c.S : c.K);
+  const uint32_t *srcV = in_s ? c.VS : c.V;
+  B *K = (B *)c.K;
+  const uint32_t len = it.len;
+  const uint64_t off = it.off;
+  const uint32_t Lp = (len + E - 1) / E * E;
+  const bool act = t * (uint32_t)E < Lp;
+  // coalesced load into LDS (unconditional loads, index clamped into the part,
+  // issued eight at a time)
+  constexpr int LB = E < 8 ? E : 8;
+#pragma unroll
+  for (int i0 = 0; i0 < E; i0 += LB) {
+    B kin[LB];
+#pragma unroll
+    for (int g = 0; g < LB; g++) {
+      const uint32_t x = (uint32_t)(i0 + g) * NT + t;
+      kin[g] = src[off + (x < len ? x : len - 1)];
+    }
+#pragma unroll
+    for (int g = 0; g < LB; g++) {
+      const uint32_t x = (uint32_t)(i0 + g) * NT + t;
+      if (x < Lp) lds[lds_pad(x)] = x < len ? R::make(Codec<DT>::enc(kin[g]), x) : R::pad();
+    }
+  }
+  group_sync<NT>();
+  T v[E];
+  if (act) {
+#pragma unroll
+    for (int i = 0; i < E; i++) v[i] = lds[lds_pad(t * E + i)];
+    sort_regs_asc<R, E>(v);
+  }
+  group_sync<NT>();
+  if (act) {
+#pragma unroll
+    for (int i = 0; i < E; i++) lds[lds_pad(t * E + i)] = v[i];
+  }
+  for (uint32_t r = E; r < Lp; r <<= 1) {
+    group_sync<NT>();
+    const uint32_t p0 = t * E;
+    const uint32_t base = p0 & ~(2 * r - 1);
+    const uint32_t diag = p0 - base;
+    const uint32_t rA = Lp - base < r ? Lp - base : r;
+    const uint32_t rB = Lp - base > r ? (Lp - base - r < r ? Lp - base - r : r) : 0u;
+    if (act && rB > 0) {
+      const uint32_t a0 = base, b0 = base + rA;
+      // first diag outputs take lo records of A: the largest lo with
+      // A[lo-1] <= B[diag-lo] (ties go to A)
+      uint32_t lo = diag > rB ? diag - rB : 0u, hi = diag < rA ? diag : rA;
+      while (lo < hi) {
+        const uint32_t m = (lo + hi) >> 1;
+        if (!R::less(lds[lds_pad(b0 + diag - 1 - m)], lds[lds_pad(a0 + m)])) lo = m + 1;
+        else hi = m;
+      }
+      uint32_t ai = lo, bi = diag - lo;
+      const uint32_t last = Lp - 1;
+      T a = lds[lds_pad(a0 + (ai < rA ? ai : rA - 1))];
+      T b = lds[lds_pad(b0 + (bi < rB ? bi : rB - 1))];
+#pragma unroll
+      for (int i = 0; i < E; i++) {
+        const bool ta = bi >= rB || (ai < rA && !R::less(b, a));
+        v[i] = R::sel(ta, a, b);
+        ai += ta ? 1u : 0u;
+        bi += ta ? 0u : 1u;
+        uint32_t nx = ta ? a0 + ai : b0 + bi;
+        nx = nx < last ? nx : last;
+        const T y = lds[lds_pad(nx)];
+        a = R::sel(ta, y, a);
+        b = R::sel(ta, b, y);
+      }
+    }
+    group_sync<NT>();
+    if (act && rB > 0) {
+#pragma unroll
+      for (int i = 0; i < E; i++) lds[lds_pad(t * E + i)] = v[i];
+    }
+  }
   group_sync<NT>();
   if constexpr (HASV) {
     uint32_t pv[E];
@@ -1083,7 +1213,7 @@ __device__ inline void fill_band(const Ctx &c, const FinItem &it, uint32_t t, ui
 // Level d's finishing work: long-band chunks and workgroup-sized small parts
 // (workgroup each), then wave-sized small parts and short bands (wave each).
 // Child slots are [0, 2 * parts of level d); at level 0 also the root slots.
-template <int DT, bool HASV>
+template <int DT, bool HASV, bool BITONIC>
 __global__ __launch_bounds__(kFinNT) void k_finish(Ctx c, int d) {
   using B = typename Codec<DT>::B;
   using R = Rec<B, HASV>;
@@ -1113,11 +1243,20 @@ __global__ __launch_bounds__(kFinNT) void k_finish(Ctx c, int d) {
     if (it.len == 0) continue;
     const uint32_t P = next_pow2(it.len);
     constexpr int ME = max_e<T>();
-    if (P <= 1024) sort_group<DT, HASV, kFinNT, 4>(c, it, lds, tid);
-    else if (P <= 2048 || ME < 16) sort_group<DT, HASV, kFinNT, 8>(c, it, lds, tid);
-    else if constexpr (ME >= 16) {
-      if (P <= 4096 || ME < 32) sort_group<DT, HASV, kFinNT, 16>(c, it, lds, tid);
-      else if constexpr (ME >= 32) sort_group<DT, HASV, kFinNT, 32>(c, it, lds, tid);
+    if constexpr (BITONIC) {
+      if (P <= 1024) sort_group<DT, HASV, kFinNT, 4>(c, it, lds, tid);
+      else if (P <= 2048 || ME < 16) sort_group<DT, HASV, kFinNT, 8>(c, it, lds, tid);
+      else if constexpr (ME >= 16) {
+        if (P <= 4096 || ME < 32) sort_group<DT, HASV, kFinNT, 16>(c, it, lds, tid);
+        else if constexpr (ME >= 32) sort_group<DT, HASV, kFinNT, 32>(c, it, lds, tid);
+      }
+    } else {
+      if (P <= 1024) merge_group<DT, HASV, kFinNT, 4>(c, it, lds, tid);
+      else if (P <= 2048 || ME < 16) merge_group<DT, HASV, kFinNT, 8>(c, it, lds, tid);
+      else if constexpr (ME >= 16) {
+        if (P <= 4096 || ME < 32) merge_group<DT, HASV, kFinNT, 16>(c, it, lds, tid);
+        else if constexpr (ME >= 32) merge_group<DT, HASV, kFinNT, 32>(c, it, lds, tid);
+      }
     }
   }
   const uint32_t wv = tid / kWave, lane = tid & 63u;
@@ -1141,13 +1280,24 @@ __global__ __launch_bounds__(kFinNT) void k_finish(Ctx c, int d) {
     if (it.len == 0) continue;
     const uint32_t P = next_pow2(it.len);
     constexpr int ME = max_e<T>();
-    if (P <= 64) sort_group<DT, HASV, kWave, 1>(c, it, wl, lane);
-    else if (P <= 128) sort_group<DT, HASV, kWave, 2>(c, it, wl, lane);
-    else if (P <= 256) sort_group<DT, HASV, kWave, 4>(c, it, wl, lane);
-    else if (P <= 512 || ME < 16) sort_group<DT, HASV, kWave, 8>(c, it, wl, lane);
-    else if constexpr (ME >= 16) {
-      if (P <= 1024 || ME < 32) sort_group<DT, HASV, kWave, 16>(c, it, wl, lane);
-      else if constexpr (ME >= 32) sort_group<DT, HASV, kWave, 32>(c, it, wl, lane);
+    if constexpr (BITONIC) {
+      if (P <= 64) sort_group<DT, HASV, kWave, 1>(c, it, wl, lane);
+      else if (P <= 128) sort_group<DT, HASV, kWave, 2>(c, it, wl, lane);
+      else if (P <= 256) sort_group<DT, HASV, kWave, 4>(c, it, wl, lane);
+      else if (P <= 512 || ME < 16) sort_group<DT, HASV, kWave, 8>(c, it, wl, lane);
+      else if constexpr (ME >= 16) {
+        if (P <= 1024 || ME < 32) sort_group<DT, HASV, kWave, 16>(c, it, wl, lane);
+        else if constexpr (ME >= 32) sort_group<DT, HASV, kWave, 32>(c, it, wl, lane);
+      }
+    } else {
+      if (P <= 64) merge_group<DT, HASV, kWave, 1>(c, it, wl, lane);
+      else if (P <= 128) merge_group<DT, HASV, kWave, 2>(c, it, wl, lane);
+      else if (P <= 256) merge_group<DT, HASV, kWave, 4>(c, it, wl, lane);
+      else if (P <= 512 || ME < 16) merge_group<DT, HASV, kWave, 8>(c, it, wl, lane);
+      else if constexpr (ME >= 16) {
+        if (P <= 1024 || ME < 32) merge_group<DT, HASV, kWave, 16>(c, it, wl, lane);
+        else if constexpr (ME >= 32) merge_group<DT, HASV, kWave, 32>(c, it, wl, lane);
+      }
     }
   }
 }

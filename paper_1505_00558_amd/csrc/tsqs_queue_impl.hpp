@@ -321,7 +321,10 @@ int launch_tick(tsqs_queue *q, QGroup &G) {
   else
     hipLaunchKernelGGL((k_partition<DT, false, false>), dim3(grid), dim3(kPartNT), 0, G.s, c, d);
   hipLaunchKernelGGL((k_plan<DT, false>), dim3(grid), dim3(kPlanNT), 0, G.s, c, d);
-  hipLaunchKernelGGL((k_finish<DT, false>), dim3(grid), dim3(kFinNT), G.geo.fin_lds, G.s, c, d);
+  if (g_opt.finish_algo == 0)
+    hipLaunchKernelGGL((k_finish<DT, false, true>), dim3(grid), dim3(kFinNT), G.geo.fin_lds, G.s, c, d);
+  else
+    hipLaunchKernelGGL((k_finish<DT, false, false>), dim3(grid), dim3(kFinNT), G.geo.fin_lds, G.s, c, d);
   HIPCHK(hipGetLastError());
   HIPCHK(hipMemcpyAsync(&G.h_err[slot], c.err, sizeof(unsigned int), hipMemcpyDeviceToHost, G.s));
   HIPCHK(hipEventRecord(G.ev[slot], G.s));
@@ -344,9 +347,12 @@ int tick_dt(tsqs_queue *q, int dt) {
 
 template <int DT>
 int set_fin_lds(const FinGeom &geo) {
-  if (geo.fin_lds > 65536)
-    HIPCHK(hipFuncSetAttribute((const void *)k_finish<DT, false>,
+  if (geo.fin_lds > 65536) {
+    HIPCHK(hipFuncSetAttribute((const void *)k_finish<DT, false, false>,
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)geo.fin_lds));
+    HIPCHK(hipFuncSetAttribute((const void *)k_finish<DT, false, true>,
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)geo.fin_lds));
+  }
   return TSQS_OK;
 }
 

@@ -22,6 +22,7 @@ def gpu():
     import paper_1505_00558_amd as tsqs
     tsqs.load_library()
     yield
+    tsqs.set_option(tsqs.OPT_FINISH_ALGO, 0)
     tsqs.set_option(tsqs.OPT_SMALL_MAX, 8192)
     tsqs.set_option(tsqs.OPT_SAMPLES, 63)
     tsqs.set_option(tsqs.OPT_PIVOT_MODE, 0)
@@ -230,3 +231,21 @@ def test_full_size_int32_properties():
     assert np.array_equal(got, part[ranks])
     del ref
     torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("dtype", list(ti.DTYPES))
+def test_merge_path_finish_variant(oracle_mod, dtype):
+    """The alternative small-part sort (per-thread network + merge-path merging,
+    TSQS_OPT_FINISH_ALGO = 1): keys and payloads as for the default."""
+    import paper_1505_00558_amd as tsqs
+    tsqs.set_option(tsqs.OPT_FINISH_ALGO, 1)
+    try:
+        for fam, n in (("uniform", 300007), ("many_equals", 70001), ("organ_pipe", 8191),
+                       ("reversed", 4097), ("uniform", 333), ("sorted", 65)):
+            k = ti.family(fam, n, dtype, seed=ti.seed_for(3, fam) + 7)
+            assert same_bits(gpu_sort(k), oracle_mod.sort(k)), (fam, n)
+            v = np.arange(n, dtype=np.uint32)
+            gk, gv = gpu_sort_pairs(k, v)
+            assert same_bits(gk, oracle_mod.sort(k)) and payload_valid(k, gk, gv), (fam, n)
+    finally:
+        tsqs.set_option(tsqs.OPT_FINISH_ALGO, 0)
