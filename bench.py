@@ -95,6 +95,9 @@ def run_single_arrays(args, workload, arrays, dtype, with_vals, config):
     import paper_1505_00558_amd as tsqs
     tsqs.load_library()
     dt = CODES[dtype]
+    if args.autotune:
+        log("autotune: %s, %d keys" % (dtype, max(a.size for a in arrays)))
+        config["tuned"] = tsqs.autotune(dt, max(a.size for a in arrays), with_payload=with_vals)
     pristine = [to_dev(a) for a in arrays]
     n_max = max(a.size for a in arrays)
     work = torch.empty(n_max, dtype=pristine[0].dtype, device="cuda:0")
@@ -322,6 +325,12 @@ def workload_batch(args):
     import tsqs_inputs as ti
     seed = ti.seed_for(4, 0)
     cases = []
+    tuned = None
+    if args.autotune:
+        import paper_1505_00558_amd as tsqs
+        _, toffs, _, _ = ti.batch_plan(seed, args.batch_count, 4, 20, max_total=1 << 28)
+        log("autotune on the capped batch shape (%d arrays)" % (toffs.size - 1))
+        tuned = tsqs.autotune(tsqs.INT32, int(toffs[-1]), offsets=toffs)
     for label, max_total in (("full", None), ("capped_2^28", 1 << 28)):
         log("batch %s: generating %d arrays" % (label, args.batch_count))
         keys0, offs, fams = ti.device_batch(seed, args.batch_count, 4, 20, "int32",
@@ -348,7 +357,8 @@ def workload_batch(args):
                                "[16, 2^20], family per array drawn from the seven; one "
                                "tsqs_sort_batch call vs one tsqs_sort call per array"
                                % args.batch_count,
-                   "arrays": head["arrays"], "total_keys": head["total_keys"]},
+                   "arrays": head["arrays"], "total_keys": head["total_keys"],
+                   "tuned": tuned},
         "cases": cases,
     }
     return out
@@ -548,6 +558,9 @@ def main():
     ap.add_argument("--families", default="all")
     ap.add_argument("--cpu-log2n", type=int, default=26)
     ap.add_argument("--batch-count", type=int, default=100000)
+    ap.add_argument("--no-autotune", dest="autotune", action="store_false",
+                    help="skip the library's autotuner (run by default on the workload's shape "
+                         "before timing)")
     ap.add_argument("--serve-requests", type=int, default=20000)
     ap.add_argument("--serve-warmup", type=int, default=1000)
     ap.add_argument("--serve-templates", type=int, default=256)

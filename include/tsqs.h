@@ -74,9 +74,9 @@ enum {
   TSQS_OPT_SEED = 5,         /* seed of the per-call sample jitter (SV.C) */
   TSQS_OPT_TIMING = 6,       /* 1 = time every partition launch with HIP events */
   TSQS_OPT_PART_GRID = 7,    /* workgroups of the partition kernel (0 = auto) */
-  TSQS_OPT_FINISH_GRID = 8,  /* workgroups of the finish kernel (0 = auto) */
-  TSQS_OPT_FINISH_ALGO = 9   /* small parts: 0 = bitonic sorting network (default),
-                                1 = per-thread sorting network + merge-path merging */
+  TSQS_OPT_FINISH_GRID = 8,  /* workgroups of the finish kernel (0 = auto: 8 per CU) */
+  TSQS_OPT_FINISH_ALGO = 9   /* small parts: 0 = bitonic sorting network, 1 = per-thread
+                                sorting network + merge-path merging in LDS (default) */
 };
 
 #define TSQS_MAX_LEVELS 192
@@ -115,6 +115,32 @@ int tsqs_sort_pairs(void *d_keys, uint32_t *d_vals, size_t nmemb, int dt, void *
  * of the same layout.  All arrays are sorted by one schedule of launches. */
 int tsqs_sort_batch(void *d_keys, uint32_t *d_vals, const uint64_t *h_offsets, size_t nseg,
                     int dt, void *stream);
+
+/* Result of tsqs_autotune: the options it chose and the times it measured. */
+typedef struct {
+  int64_t small_max;     /* TSQS_OPT_SMALL_MAX */
+  int64_t samples;       /* TSQS_OPT_SAMPLES */
+  int64_t part_grid;     /* TSQS_OPT_PART_GRID (workgroups) */
+  int64_t finish_grid;   /* TSQS_OPT_FINISH_GRID (workgroups) */
+  int64_t finish_algo;   /* TSQS_OPT_FINISH_ALGO */
+  double ms_default;     /* sort time with the options in force at the call */
+  double ms_best;        /* sort time with the chosen options */
+  uint32_t trials;       /* configurations timed */
+  uint32_t reserved;
+} tsqs_tune_t;
+
+/* Autotuner: times sorts of seeded uniform keys of type dt (with a uint32
+ * payload if with_payload) shaped like the caller's work -- one array of n keys
+ * when h_offsets is NULL, else the nseg arrays of h_offsets (as for
+ * tsqs_sort_batch; n must equal h_offsets[nseg]) -- over candidate values of
+ * the small-part threshold, the pivot sample count, the partition and finish
+ * grids and the small-part algorithm (one parameter at a time, keeping the best
+ * so far), then sets the fastest as the current options and reports it in *out
+ * (may be NULL).  Uses 2 n keys (+ 2 n payloads) of temporary device memory,
+ * freed before it returns.  Returns TSQS_OK or an error code; on error the
+ * options in force at the call are restored. */
+int tsqs_autotune(int dt, int with_payload, size_t n, const uint64_t *h_offsets, size_t nseg,
+                  void *stream, tsqs_tune_t *out);
 
 /* Release the workspace of every device (SIII.G's manual release). */
 void tsqs_free_storage(void);

@@ -23,9 +23,9 @@ OPT_SMALL_MAX, OPT_SAMPLES, OPT_DEPTH_FACTOR, OPT_PIVOT_MODE = 1, 2, 3, 4
 OPT_SEED, OPT_TIMING, OPT_PART_GRID, OPT_FINISH_GRID, OPT_FINISH_ALGO = 5, 6, 7, 8, 9
 MAX_LEVELS = 192
 
-SYMBOLS = ["tsqs_sort", "tsqs_sort_pairs", "tsqs_sort_batch", "tsqs_free_storage",
-           "tsqs_set_option", "tsqs_get_option", "tsqs_get_stats", "tsqs_strerror",
-           "tsqs_version"]
+SYMBOLS = ["tsqs_sort", "tsqs_sort_pairs", "tsqs_sort_batch", "tsqs_autotune",
+           "tsqs_free_storage", "tsqs_set_option", "tsqs_get_option", "tsqs_get_stats",
+           "tsqs_strerror", "tsqs_version"]
 QUEUE_SYMBOLS = ["tsqs_queue_open", "tsqs_queue_submit", "tsqs_queue_step", "tsqs_queue_poll",
                  "tsqs_queue_result", "tsqs_queue_reap", "tsqs_queue_release",
                  "tsqs_queue_info", "tsqs_queue_close"]
@@ -67,6 +67,24 @@ class Stats(ctypes.Structure):
         }
 
 
+class Tune(ctypes.Structure):
+    _fields_ = [
+        ("small_max", ctypes.c_int64),
+        ("samples", ctypes.c_int64),
+        ("part_grid", ctypes.c_int64),
+        ("finish_grid", ctypes.c_int64),
+        ("finish_algo", ctypes.c_int64),
+        ("ms_default", ctypes.c_double),
+        ("ms_best", ctypes.c_double),
+        ("trials", ctypes.c_uint32),
+        ("reserved", ctypes.c_uint32),
+    ]
+
+    def as_dict(self) -> dict:
+        return {k: (getattr(self, k) if isinstance(getattr(self, k), float) else int(getattr(self, k)))
+                for k, _ in self._fields_ if k != "reserved"}
+
+
 class TsqsError(RuntimeError):
     pass
 
@@ -89,6 +107,8 @@ def load_library():
     lib.tsqs_sort_pairs.restype = ctypes.c_int
     lib.tsqs_sort_batch.argtypes = [vp, vp, vp, sz, ctypes.c_int, vp]
     lib.tsqs_sort_batch.restype = ctypes.c_int
+    lib.tsqs_autotune.argtypes = [ctypes.c_int, ctypes.c_int, sz, vp, sz, vp, ctypes.POINTER(Tune)]
+    lib.tsqs_autotune.restype = ctypes.c_int
     lib.tsqs_free_storage.argtypes = []
     lib.tsqs_free_storage.restype = None
     lib.tsqs_set_option.argtypes = [ctypes.c_int, ctypes.c_int64]
@@ -195,6 +215,23 @@ def sort_batch(keys, offsets, vals=None, dtype_code: int | None = None):
                                           offs.ctypes.data_as(ctypes.c_void_p), nseg, dt,
                                           _stream_handle()))
     return keys
+
+
+def autotune(dtype_code: int, n: int, with_payload: bool = False, offsets=None) -> dict:
+    """Time candidate options on seeded keys shaped like the work (one array of n
+    keys, or the arrays of ``offsets``), set the fastest, and return them."""
+    import numpy as np
+    t = Tune()
+    offs = None
+    nseg = 0
+    if offsets is not None:
+        offs = np.ascontiguousarray(np.asarray(offsets, dtype=np.uint64))
+        nseg = offs.size - 1
+        n = int(offs[-1])
+    _check(load_library().tsqs_autotune(int(dtype_code), 1 if with_payload else 0, int(n),
+                                        offs.ctypes.data_as(ctypes.c_void_p) if offs is not None
+                                        else None, nseg, _stream_handle(), ctypes.byref(t)))
+    return t.as_dict()
 
 
 def free_storage() -> None:

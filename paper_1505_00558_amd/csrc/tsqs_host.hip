@@ -13,6 +13,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <chrono>
 #include <climits>
 #include <cstring>
 #include <deque>
@@ -36,7 +37,7 @@ struct Options {
   int64_t timing = 0;
   int64_t part_grid = 0;
   int64_t finish_grid = 0;
-  int64_t finish_algo = 0;
+  int64_t finish_algo = 1;
 };
 
 struct Workspace {
@@ -235,7 +236,7 @@ int run_t(Workspace &w, void *keys, uint32_t *vals, const uint64_t *h_offs, size
   c.big_cap = (uint32_t)big_cap;
 
   const int part_grid = g_opt.part_grid > 0 ? (int)g_opt.part_grid : 4 * w.cus;
-  const int fin_grid = g_opt.finish_grid > 0 ? (int)g_opt.finish_grid : 4 * w.cus;
+  const int fin_grid = g_opt.finish_grid > 0 ? (int)g_opt.finish_grid : 8 * w.cus;
   const int plan_grid = 4 * w.cus;
   const size_t fin_lds = geo.fin_lds;
   if (fin_lds > 65536) {
@@ -350,6 +351,25 @@ int dispatch(void *keys, uint32_t *vals, const uint64_t *h_offs, size_t nroots, 
 
 bool dtype_ok(int dt) { return dt >= TSQS_INT32 && dt <= TSQS_FLOAT32; }
 
+// ---- autotuner inputs: seeded uniform keys (SplitMix64) and payload = index ----
+
+__global__ void k_tune_keys(void *out, uint64_t n, int kb, uint64_t seed) {
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+    uint64_t z = seed + (i + 1) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    z ^= z >> 31;
+    if (kb == 4) ((uint32_t *)out)[i] = (uint32_t)z;
+    else ((uint64_t *)out)[i] = z;
+  }
+}
+
+__global__ void k_tune_iota(uint32_t *v, uint64_t n) {
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) v[i] = (uint32_t)i;
+}
+
 }  // namespace
 
 extern "C" {
@@ -460,6 +480,112 @@ const char *tsqs_strerror(int code) {
 }
 
 int tsqs_version(void) { return 1; }
+
+}  // extern "C"
+
+
+extern "C" {
+
+int tsqs_autotune(int dt, int with_payload, size_t n, const uint64_t *h_offsets, size_t nseg,
+                  void *stream, tsqs_tune_t *out) {
+  if (!dtype_ok(dt)) return TSQS_EUNSUPPORTED;
+  if (n < 2 || n > ((size_t)1 << 36)) return TSQS_EINVAL;
+  if (h_offsets) {
+    if (nseg == 0 || nseg >= (1ull << 24) || h_offsets[0] != 0 || h_offsets[nseg] != n) return TSQS_EINVAL;
+    for (size_t j = 0; j < nseg; j++)
+      if (h_offsets[j + 1] < h_offsets[j] || h_offsets[j + 1] - h_offsets[j] > 0xFFFFFFFFull) return TSQS_EINVAL;
+  } else if (n > 0xFFFFFFFFull) {
+    return TSQS_EINVAL;
+  }
+  hipStream_t s = (hipStream_t)stream;
+  const size_t kb = (dt == TSQS_INT64 || dt == TSQS_UINT64) ? 8 : 4;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return TSQS_EDEVICE;
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return TSQS_EDEVICE;
+  const int64_t cus = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
+  Options saved;
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    saved = g_opt;
+  }
+  unsigned char *keys0 = nullptr, *keys = nullptr;
+  uint32_t *vals = nullptr;
+  int rc = TSQS_OK;
+  if (hipMalloc(&keys0, n * kb) != hipSuccess || hipMalloc(&keys, n * kb) != hipSuccess ||
+      (with_payload && hipMalloc(&vals, n * sizeof(uint32_t)) != hipSuccess)) {
+    (void)hipGetLastError();
+    rc = TSQS_ENOMEM;
+  }
+  if (rc == TSQS_OK) {
+    hipLaunchKernelGGL(k_tune_keys, dim3(4 * (unsigned)cus), dim3(256), 0, s, (void *)keys0, (uint64_t)n,
+                       (int)kb, (uint64_t)0x7E57ull);
+    if (hipGetLastError() != hipSuccess || hipStreamSynchronize(s) != hipSuccess) rc = TSQS_EDEVICE;
+  }
+  // fastest of two timed sorts after one untimed, with options o
+  auto trial = [&](const Options &o, double *ms) -> int {
+    {
+      std::lock_guard<std::mutex> lk(g_mu);
+      g_opt = o;
+    }
+    double best = 1e30;
+    for (int rep = 0; rep < 3; rep++) {
+      HIPCHK(hipMemcpyAsync(keys, keys0, n * kb, hipMemcpyDeviceToDevice, s));
+      if (with_payload) hipLaunchKernelGGL(k_tune_iota, dim3(4 * (unsigned)cus), dim3(256), 0, s, vals, (uint64_t)n);
+      HIPCHK(hipStreamSynchronize(s));
+      const auto t0 = std::chrono::steady_clock::now();
+      int r;
+      if (h_offsets) r = tsqs_sort_batch(keys, with_payload ? vals : nullptr, h_offsets, nseg, dt, s);
+      else if (with_payload) r = tsqs_sort_pairs(keys, vals, n, dt, s);
+      else r = tsqs_sort(keys, n, dt, s);
+      if (r != TSQS_OK) return r;
+      const double t = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+      if (rep > 0 && t < best) best = t;
+    }
+    *ms = best;
+    return TSQS_OK;
+  };
+  Options best = saved;
+  double ms_default = 0.0, ms_best = 0.0;
+  uint32_t trials = 0;
+  if (rc == TSQS_OK) rc = trial(best, &ms_default);
+  ms_best = ms_default;
+  trials = 1;
+  // one parameter at a time, keeping the best so far
+  auto try_value = [&](int64_t Options::*field, int64_t v) {
+    if (rc != TSQS_OK || best.*field == v) return;
+    Options o = best;
+    o.*field = v;
+    double ms = 0.0;
+    rc = trial(o, &ms);
+    trials++;
+    if (rc == TSQS_OK && ms < ms_best) { ms_best = ms; best = o; }
+  };
+  for (int64_t t : {2048, 4096, 8192}) try_value(&Options::small_max, t);
+  for (int64_t v : {31, 63}) try_value(&Options::samples, v);
+  for (int64_t m : {2, 4, 8}) try_value(&Options::part_grid, m * cus);
+  for (int64_t m : {2, 4, 8}) try_value(&Options::finish_grid, m * cus);
+  for (int64_t a : {0, 1}) try_value(&Options::finish_algo, a);
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_opt = rc == TSQS_OK ? best : saved;
+  }
+  (void)hipFree(keys0);
+  (void)hipFree(keys);
+  (void)hipFree(vals);
+  if (rc == TSQS_OK && out) {
+    out->small_max = best.small_max;
+    out->samples = best.samples;
+    out->part_grid = best.part_grid;
+    out->finish_grid = best.finish_grid;
+    out->finish_algo = best.finish_algo;
+    out->ms_default = ms_default;
+    out->ms_best = ms_best;
+    out->trials = trials;
+    out->reserved = 0;
+  }
+  return rc;
+}
 
 }  // extern "C"
 

@@ -321,10 +321,11 @@ int launch_tick(tsqs_queue *q, QGroup &G) {
   else
     hipLaunchKernelGGL((k_partition<DT, false, false>), dim3(grid), dim3(kPartNT), 0, G.s, c, d);
   hipLaunchKernelGGL((k_plan<DT, false>), dim3(grid), dim3(kPlanNT), 0, G.s, c, d);
+  const int fgrid = g_opt.finish_grid > 0 ? (int)g_opt.finish_grid : 8 * q->cus;
   if (g_opt.finish_algo == 0)
-    hipLaunchKernelGGL((k_finish<DT, false, true>), dim3(grid), dim3(kFinNT), G.geo.fin_lds, G.s, c, d);
+    hipLaunchKernelGGL((k_finish<DT, false, true>), dim3(fgrid), dim3(kFinNT), G.geo.fin_lds, G.s, c, d);
   else
-    hipLaunchKernelGGL((k_finish<DT, false, false>), dim3(grid), dim3(kFinNT), G.geo.fin_lds, G.s, c, d);
+    hipLaunchKernelGGL((k_finish<DT, false, false>), dim3(fgrid), dim3(kFinNT), G.geo.fin_lds, G.s, c, d);
   HIPCHK(hipGetLastError());
   HIPCHK(hipMemcpyAsync(&G.h_err[slot], c.err, sizeof(unsigned int), hipMemcpyDeviceToHost, G.s));
   HIPCHK(hipEventRecord(G.ev[slot], G.s));

@@ -26,7 +26,7 @@ def _declared(header="tsqs.h"):
 
 def test_header_declares_the_api():
     names = _declared()
-    for n in ("tsqs_sort", "tsqs_sort_pairs", "tsqs_sort_batch", "tsqs_free_storage",
+    for n in ("tsqs_sort", "tsqs_sort_pairs", "tsqs_sort_batch", "tsqs_autotune", "tsqs_free_storage",
               "tsqs_set_option", "tsqs_get_option", "tsqs_get_stats", "tsqs_strerror"):
         assert n in names
 
@@ -97,7 +97,7 @@ def test_options(lib):
         assert lib.tsqs_set_option(tsqs.OPT_SAMPLES, 65) == -1
         assert lib.tsqs_set_option(tsqs.OPT_PIVOT_MODE, 2) == -1
         assert lib.tsqs_set_option(tsqs.OPT_FINISH_ALGO, 2) == -1
-        assert tsqs.get_option(tsqs.OPT_FINISH_ALGO) == 0
+        assert tsqs.get_option(tsqs.OPT_FINISH_ALGO) == 1
         assert lib.tsqs_set_option(999, 1) == -4
         assert tsqs.get_option(999) == -(1 << 63)
     finally:
@@ -138,3 +138,15 @@ def test_queue_argument_errors(lib):
     assert lib.tsqs_queue_reap(None, None, 0, None) == -1
     assert lib.tsqs_queue_info(None, None, None, None, None, None) == -1
     assert lib.tsqs_queue_close(None) == -1
+
+
+def test_autotune_argument_errors(lib):
+    import paper_1505_00558_amd as tsqs
+    t = tsqs.Tune()
+    assert lib.tsqs_autotune(9, 0, 1000, None, 0, None, ctypes.byref(t)) == -4
+    assert lib.tsqs_autotune(0, 0, 1, None, 0, None, ctypes.byref(t)) == -1
+    assert lib.tsqs_autotune(0, 0, 1 << 32, None, 0, None, ctypes.byref(t)) == -1
+    p, keep = _offs([0, 5, 3])
+    assert lib.tsqs_autotune(0, 0, 3, p, 2, None, ctypes.byref(t)) == -1     # decreasing
+    p, keep = _offs([0, 5, 9])
+    assert lib.tsqs_autotune(0, 0, 10, p, 2, None, ctypes.byref(t)) == -1    # n != last offset

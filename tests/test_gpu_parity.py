@@ -22,7 +22,9 @@ def gpu():
     import paper_1505_00558_amd as tsqs
     tsqs.load_library()
     yield
-    tsqs.set_option(tsqs.OPT_FINISH_ALGO, 0)
+    tsqs.set_option(tsqs.OPT_FINISH_ALGO, 1)
+    tsqs.set_option(tsqs.OPT_PART_GRID, 0)
+    tsqs.set_option(tsqs.OPT_FINISH_GRID, 0)
     tsqs.set_option(tsqs.OPT_SMALL_MAX, 8192)
     tsqs.set_option(tsqs.OPT_SAMPLES, 63)
     tsqs.set_option(tsqs.OPT_PIVOT_MODE, 0)
@@ -234,11 +236,11 @@ def test_full_size_int32_properties():
 
 
 @pytest.mark.parametrize("dtype", list(ti.DTYPES))
-def test_merge_path_finish_variant(oracle_mod, dtype):
-    """The alternative small-part sort (per-thread network + merge-path merging,
-    TSQS_OPT_FINISH_ALGO = 1): keys and payloads as for the default."""
+def test_bitonic_finish_variant(oracle_mod, dtype):
+    """The alternative small-part sort (the bitonic network, TSQS_OPT_FINISH_ALGO
+    = 0): keys and payloads as for the default merge-path sort."""
     import paper_1505_00558_amd as tsqs
-    tsqs.set_option(tsqs.OPT_FINISH_ALGO, 1)
+    tsqs.set_option(tsqs.OPT_FINISH_ALGO, 0)
     try:
         for fam, n in (("uniform", 300007), ("many_equals", 70001), ("organ_pipe", 8191),
                        ("reversed", 4097), ("uniform", 333), ("sorted", 65)):
@@ -248,4 +250,29 @@ def test_merge_path_finish_variant(oracle_mod, dtype):
             gk, gv = gpu_sort_pairs(k, v)
             assert same_bits(gk, oracle_mod.sort(k)) and payload_valid(k, gk, gv), (fam, n)
     finally:
-        tsqs.set_option(tsqs.OPT_FINISH_ALGO, 0)
+        tsqs.set_option(tsqs.OPT_FINISH_ALGO, 1)
+
+
+def test_autotune_chooses_valid_options_and_sorts(oracle_mod):
+    """The autotuner measures candidate options, sets the fastest, and sorts
+    under them still agree with the oracle (options restored afterwards)."""
+    import paper_1505_00558_amd as tsqs
+    before = {k: tsqs.get_option(k) for k in (tsqs.OPT_SMALL_MAX, tsqs.OPT_SAMPLES,
+                                               tsqs.OPT_PART_GRID, tsqs.OPT_FINISH_GRID,
+                                               tsqs.OPT_FINISH_ALGO)}
+    try:
+        r = tsqs.autotune(tsqs.INT32, 1 << 22)
+        print("case: autotune", r, flush=True)
+        assert r["trials"] >= 5 and r["ms_best"] <= r["ms_default"]
+        assert tsqs.get_option(tsqs.OPT_SMALL_MAX) == r["small_max"]
+        assert tsqs.get_option(tsqs.OPT_SAMPLES) == r["samples"]
+        assert tsqs.get_option(tsqs.OPT_FINISH_ALGO) == r["finish_algo"]
+        for fam in ("uniform", "organ_pipe", "many_equals"):
+            k = ti.family(fam, 1 << 20, "int32", seed=ti.seed_for(2, fam) + 3)
+            assert same_bits(gpu_sort(k), oracle_mod.sort(k)), fam
+        offs = np.array([0, 1000, 1000, 70000, 70001, 200000], dtype=np.uint64)
+        r2 = tsqs.autotune(tsqs.UINT64, 0, with_payload=True, offsets=offs)
+        assert r2["trials"] >= 5
+    finally:
+        for k, v in before.items():
+            tsqs.set_option(k, v)
