@@ -165,7 +165,7 @@ int run_t(Workspace &w, void *keys, uint32_t *vals, const uint64_t *h_offs, size
 
   // workspace sizes
   const size_t seg_cap = (size_t)(n / (small_max + 1)) + 2;
-  const size_t slot_cap = 2 * seg_cap + nroots;
+  const size_t slot_cap = 4 * seg_cap + nroots;   // 4 child slots per part, then the roots
   const size_t big_cap = 2 * (size_t)(n / kBandChunk) + 16;
   int rc;
   {
@@ -194,7 +194,7 @@ int run_t(Workspace &w, void *keys, uint32_t *vals, const uint64_t *h_offs, size
     if ((rc = grow(&w.finw, &b, slot_cap)) != TSQS_OK) return rc;
     w.slot_cap = slot_cap;
   }
-  if ((rc = grow(&w.band, &w.band_cap, seg_cap)) != TSQS_OK) return rc;
+  if ((rc = grow(&w.band, &w.band_cap, 3 * seg_cap)) != TSQS_OK) return rc;
   if ((rc = grow(&w.big, &w.big_cap, big_cap)) != TSQS_OK) return rc;
   if (h_offs) {
     if ((rc = grow(&w.offs, &w.off_cap, nroots + 1)) != TSQS_OK) return rc;
@@ -258,9 +258,11 @@ int run_t(Workspace &w, void *keys, uint32_t *vals, const uint64_t *h_offs, size
   // 32-bit byte offsets within a part suffice unless a part reaches 4 GiB
   const bool wide = (uint64_t)max_root * sizeof(typename Codec<DT>::B) > 0xFFFFFFFFull;
   const uint32_t lv = ceil_log2((max_root + small_max - 1) / small_max);
-  // every root small: level 0 has no parts, only its finish work
+  // every root small: level 0 has no parts, only its finish work.  Without
+  // payloads the first pass is one level and the rest two levels each.
   const bool roots_small = max_root <= small_max;
-  uint32_t expected = roots_small ? 1u : lv + (lv + 4) / 5 + 2;
+  const uint32_t lv_all = lv + (lv + 4) / 5 + 2;
+  uint32_t expected = roots_small ? 1u : (HASV ? lv_all : 2 + lv_all / 2);
   int d = 0, target = (int)expected;
   if (target > kMaxLevels - 1) target = kMaxLevels - 1;
   for (;;) {
@@ -269,9 +271,13 @@ int run_t(Workspace &w, void *keys, uint32_t *vals, const uint64_t *h_offs, size
       if (g_opt.timing) HIPCHK(hipEventRecord(w.ev[2 * d], s));
       if (idle) {
       } else if (wide) {
-        hipLaunchKernelGGL((k_partition<DT, HASV, true>), dim3(part_grid), dim3(kPartNT), 0, s, c, d);
+        hipLaunchKernelGGL((k_partition<DT, HASV, true, false>), dim3(part_grid), dim3(kPartNT), 0, s, c, d);
+        if (!HASV && d > 0)
+          hipLaunchKernelGGL((k_partition<DT, HASV, true, true>), dim3(part_grid), dim3(kPartNT), 0, s, c, d);
       } else {
-        hipLaunchKernelGGL((k_partition<DT, HASV, false>), dim3(part_grid), dim3(kPartNT), 0, s, c, d);
+        hipLaunchKernelGGL((k_partition<DT, HASV, false, false>), dim3(part_grid), dim3(kPartNT), 0, s, c, d);
+        if (!HASV && d > 0)
+          hipLaunchKernelGGL((k_partition<DT, HASV, false, true>), dim3(part_grid), dim3(kPartNT), 0, s, c, d);
       }
       if (g_opt.timing) HIPCHK(hipEventRecord(w.ev[2 * d + 1], s));
       if (!idle) hipLaunchKernelGGL((k_plan<DT, HASV>), dim3(plan_grid), dim3(kPlanNT), 0, s, c, d);

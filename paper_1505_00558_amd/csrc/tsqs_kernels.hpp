@@ -4,35 +4,36 @@
 // 1505.00558, SIII): pick a pivot from samples, split a part into keys < p,
 // keys == p and keys > p, put the == p keys in a middle band that is final and
 // never compared again, recurse on the two sides.  The paper's single-threaded
-// hole-juggling scan (SIII.A-F) is not used; on the GPU one level of the
-// recursion is one data-parallel pass over every active part:
+// hole-juggling scan (SIII.A-F) is not used; on the GPU the recursion runs as
+// data-parallel passes over every active part, one or two recursion levels per
+// read and write of the keys:
 //
 //   k_partition  every chunk of every part at this level.  A chunk is an
 //                address-aligned window of 16384 keys (8192 / 4096 for wider
 //                elements) read with 16-byte loads by a 512-thread workgroup;
-//                two compares per key on an order-preserving unsigned code;
-//                ranks from 64-lane ballots + mbcnt; an LDS prefix over
-//                (item, wave); ONE packed 64-bit atomic per chunk reserves
-//                [left cursor, right cursor] in the part (counters of
-//                different parts sit in different 128-byte lines); the < and >
-//                keys are stored into the other buffer (ping-pong K <-> S).
-//                Each workgroup takes a contiguous run of chunks, so the part
-//                of the next chunk is found by advancing, not by searching.
-//   k_plan       one wave per part just partitioned: reads the final cursors,
-//                writes the equal band and the small children into fixed slots
-//                (slot = 2 * part + side, no list atomics), and for large
-//                children picks a pivot (median of up to 63 samples sorted
-//                inside the wave; the exact median by radix select once the
-//                depth limit is reached); the workgroup then reserves all its
-//                next-level parts with one atomic.
-//   k_finish     small parts are sorted by a bitonic network held in registers
-//                (blocked layout, partner exchange by lane permutes inside a
-//                wave and through LDS across waves): one wave per part up to
-//                2048 keys, the 256-thread workgroup above; bands write the
-//                pivot value (equality means identical bits) and the staged
-//                payloads.
+//                compares on an order-preserving unsigned code; ranks from
+//                64-lane ballots + mbcnt; per-wave scalar cursors and one
+//                reservation per chunk.  One-level parts are split by their
+//                pivot with a left and a right cursor, and the keys of each side
+//                are counted against that side's pivot; two-level parts (whose
+//                class sizes that counting gave) get their < and > regions
+//                placed exactly and each region split by its own pivot with two
+//                cursors, so one pass does two levels (keys only).  The keys
+//                move to the other buffer (ping-pong K <-> S).
+//   k_plan       one wave per part just partitioned: reads the final counters,
+//                writes the equal bands and the small children into fixed
+//                slots (no list atomics), and for large children picks the
+//                pivots of the next two levels from one sorted sample of up to
+//                63 keys (the exact median by radix select once the depth limit
+//                is reached); the workgroup then reserves all its next-level
+//                parts with one atomic.
+//   k_finish     small parts are sorted in LDS / registers (a per-thread
+//                sorting network and merge-path merging, or a bitonic network):
+//                one wave per part up to 2048 keys, the 256-thread workgroup
+//                above; bands write the pivot value (equality means identical
+//                bits) and the staged payloads.
 //
-// Buffers: a part at depth d lives in K when d is even, in S when d is odd.
+// Buffers: each part records whether its keys are in K or in S.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -55,7 +56,7 @@ constexpr int kCtrStride = 16;   // u64 words between part counters: one 128-byt
 constexpr int kStripes = 64;     // statistics counters are spread over this many lines
 constexpr int kStatWords = 16;
 enum { kStFallback = 0, kStSmallParts = 1, kStSmallKeys = 2, kStBandKeys = 3 };
-constexpr uint32_t kErrSegCap = 1, kErrFinCap = 2, kErrLevel = 4;
+constexpr uint32_t kErrSegCap = 1, kErrFinCap = 2, kErrLevel = 4, kErrCount = 8;
 
 // ---- order-preserving codes (compares are done on these, never on floats) --
 
@@ -104,16 +105,38 @@ template <int DT, bool HASV> struct PartCfg {
 
 // ---- device tables -----------------------------------------------------------
 
-struct Seg {                 // one part of a level
+// A part of a level.  Pivots are codes: piv[0] splits the part; piv[1] and
+// piv[2] split its < and > sides (its children); piv[3..6] split the children's
+// < and > sides (its grandchildren, in the order <<, <>, ><, >>).
+//
+// One-level pass (flags without kSegTwo): the part is split by piv[0] with a
+// left and a right cursor (sizes unknown in advance); the keys of each side are
+// also counted against that side's pivot (piv[1] / piv[2]), so the children
+// enter the next level with the sizes of their own classes known.
+// Two-level pass (kSegTwo): nlt / neq, the numbers of keys below / equal to
+// piv[0], are known, so the < and > regions are placed exactly and each is split
+// by its own pivot with two cursors in the same pass: two levels of the
+// recursion per read and write of the keys; the four grandchildren are counted
+// against piv[3..6] for the pass after.
+constexpr uint32_t kSegInS = 1, kSegTwo = 2;
+struct Seg {
   uint64_t off;              // first key
-  uint64_t pivot;            // encoded pivot
+  uint64_t piv[7];
   uint32_t len;
   uint32_t chunk_begin;      // first chunk of this part in the level's chunk space
-  uint32_t depth;            // recursion depth: the part lives in K when even, S when odd
+  uint32_t depth;            // recursion depth
   uint32_t dmax;             // depth limit of the array it came from
   uint32_t req;              // request (array) the part belongs to
-  uint32_t pad;
+  uint32_t flags;            // kSegInS: the keys are in S (else K); kSegTwo: two-level pass
+  uint32_t nlt, neq;         // keys below / equal to piv[0] (two-level pass)
 };
+
+// Counters of a part (kCtrStride words, one 128-byte line): [0] left | right
+// cursor (one-level: < | >; two-level: << | <>), [1] keys equal to piv[0]
+// (staged payloads), [2] two-level: >< | >> cursors, [4..7] look-ahead counts
+// (below | equal << 32): one-level [4] < side vs piv[1], [5] > side vs piv[2];
+// two-level [4..7] the four grandchildren vs piv[3..6].
+constexpr int kCtrA = 0, kCtrE = 1, kCtrB = 2, kCtrLook = 4;
 
 struct FinItem {             // work of the finish kernel (len 0 = empty slot)
   uint64_t off;              // small part: first key; band: first band slot
@@ -142,8 +165,8 @@ struct Ctx {
   uint32_t *V, *VS, *VE;
   Seg *seg0, *seg1;
   unsigned long long *ctr0, *ctr1;   // per part, stride kCtrStride: [0] = L | G << 32, [1] = E
-  FinItem *fin, *finw;               // small-part slots: workgroup / wave sized
-  FinItem *band;                     // band slot per part
+  FinItem *fin, *finw;               // small-part slots (4 per part): workgroup / wave sized
+  FinItem *band;                     // band slots (3 per part)
   FinItem *big;                      // chunks of long bands (appended)
   LevelCtl *lvl;
   unsigned long long *stats;         // kStripes x kStatWords
@@ -166,7 +189,7 @@ struct Ctx {
   uint32_t depth_factor;
   uint32_t pivot_mode;               // 0 sampled median, 1 exact minimum
   uint32_t jitter;                   // per-call sample shift
-  uint32_t seg_cap;                  // part records per level; child slots are 2 * seg_cap
+  uint32_t seg_cap;                  // part records per level; child slots are 4 * seg_cap
   uint32_t big_cap;
   uint32_t pad0;
 };
@@ -262,6 +285,58 @@ __device__ inline typename Codec<DT>::B wave_sample_pivot(const typename Codec<D
   v = wave_sort64<B>(v);
   if constexpr (sizeof(B) == 8) return shfl_u64(v, (int)(S / 2));
   else return shfl_u32(v, (int)(S / 2));
+}
+
+template <typename B>
+__device__ inline B shfl_any(B v, int src) {
+  if constexpr (sizeof(B) == 8) return shfl_u64(v, src);
+  else return shfl_u32(v, src);
+}
+
+// Pivots of a part from one sorted sample (whole wave).  S samples of
+// Y[off, off+len) as in wave_sample_pivot; with own = the part's own pivot
+// (own_known) or the sample median, the children's pivots are the medians of
+// the samples below / above own, and the grandchildren's the medians of the
+// samples in the four ranges those cut (a side without samples reuses the
+// pivot that bounds it: the split then makes no progress there, and the depth
+// limit bounds how often that can happen).  piv[0] = own.
+template <int DT>
+__device__ inline void wave_part_pivots(const typename Codec<DT>::B *Y, uint64_t off, uint32_t len,
+                                        uint32_t S, uint32_t jitter, bool own_known,
+                                        typename Codec<DT>::B own, uint64_t piv[7]) {
+  using B = typename Codec<DT>::B;
+  const uint32_t lane = lane_id();
+  B v = ~(B)0;
+  if (lane < S) {
+    const uint64_t span = (uint64_t)len - 1;
+    uint64_t pos = (uint64_t)lane * span / (S - 1);
+    const uint64_t h = span / (S - 1);
+    const uint32_t half = S / 2;
+    if (lane != 0 && lane != half && lane != S - 1 && h >= 4) {
+      int64_t dd = (int64_t)(((uint64_t)jitter * (h / 2)) >> 32) - (int64_t)(h / 4);
+      pos = lane < half ? (uint64_t)((int64_t)pos + dd) : (uint64_t)((int64_t)pos - dd);
+    }
+    v = Codec<DT>::enc(Y[off + pos]);
+  }
+  v = wave_sort64<B>(v);
+  const bool in = lane < S;
+  if (!own_known) own = shfl_any<B>(v, (int)(S / 2));
+  // samples below / not above a value: the sorted prefix lengths
+  auto below = [&](B x) { return (uint32_t)__popcll(__ballot(in && v < x)); };
+  auto upto = [&](B x) { return (uint32_t)__popcll(__ballot(in && v <= x)); };
+  auto med = [&](uint32_t lo, uint32_t hi, B dflt) {   // median of samples [lo, hi)
+    return hi > lo ? shfl_any<B>(v, (int)(lo + (hi - lo - 1) / 2)) : dflt;
+  };
+  const uint32_t a = below(own), b = upto(own);
+  const B pl = med(0, a, own), pg = med(b, S, own);
+  const uint32_t a1 = below(pl), b1 = upto(pl), a2 = below(pg), b2 = upto(pg);
+  piv[0] = (uint64_t)own;
+  piv[1] = (uint64_t)pl;
+  piv[2] = (uint64_t)pg;
+  piv[3] = (uint64_t)med(0, a1 < a ? a1 : a, pl);
+  piv[4] = (uint64_t)med(b1 < a ? b1 : a, a, pl);
+  piv[5] = (uint64_t)med(b, a2 > b ? a2 : b, pg);
+  piv[6] = (uint64_t)med(b2 > b ? b2 : b, S, pg);
 }
 
 // Exact k-th smallest code of Y[off, off+len) by most-significant-digit radix
@@ -386,88 +461,30 @@ __device__ inline void put_band(const Ctx &c, int level, uint32_t si, uint64_t o
   }
 }
 
-// Pivot of a large child (whole wave): median of samples, or the exact k-th
-// code by radix select (the depth-limit fallback, or the minimum in the test
-// mode that forces it).
-template <int DT>
-__device__ inline typename Codec<DT>::B child_pivot(const Ctx &c, uint64_t off, uint32_t len,
-                                                    uint32_t depth, uint32_t dmax, uint32_t *hist) {
-  using B = typename Codec<DT>::B;
-  const B *Y = (const B *)((depth & 1) ? c.S : c.K);
-  if (c.pivot_mode == 1 || depth >= dmax) {
-    const uint32_t k = (c.pivot_mode == 1 && depth < dmax) ? 0u : len / 2;
-    if (lane_id() == 0 && depth >= dmax) stat_add(c, kStFallback, 1ull);
-    return wave_select<DT>(Y, off, len, k, hist);
-  }
-  uint32_t S = c.samples;
-  if (S > len) S = (len & 1) ? len : len - 1;
-  return wave_sample_pivot<DT>(Y, off, len, S, c.jitter);
-}
-
-// Large children found by the waves of a workgroup in one iteration, reserved
-// in the next level with a single atomic (records keep the wave order, so
-// chunk_begin stays increasing with the record index).
-struct Pending {
-  uint64_t off0, off1, pivot0, pivot1;
-  uint32_t len0, len1, chunks0, chunks1;
-  uint32_t n, req;
+// Parts a workgroup emits in one iteration (up to 4 per wave), staged in LDS
+// and reserved in the next level with a single atomic (records keep the wave
+// order, so chunk_begin stays increasing with the record index).
+constexpr int kPendPerWave = 4;
+struct PendLds {
+  Seg rec[kPlanNW][kPendPerWave];
+  uint32_t n[kPlanNW], ch[kPlanNW];
+  unsigned long long keys[kPlanNW], old;
 };
 
-template <int DT, bool HASV>
-__device__ inline void flush_parts(const Ctx &c, int lvl_next, const Pending &pd, uint32_t depth,
-                                   uint32_t dmax, uint32_t *sh_n, uint32_t *sh_ch,
-                                   unsigned long long *sh_keys, unsigned long long *sh_old) {
-  const uint32_t wv = threadIdx.x / kWave, lane = threadIdx.x & 63u;
-  if (lane == 0) {
-    sh_n[wv] = pd.n;
-    sh_ch[wv] = (pd.n > 0 ? pd.chunks0 : 0u) + (pd.n > 1 ? pd.chunks1 : 0u);
-    sh_keys[wv] = (pd.n > 0 ? (unsigned long long)pd.len0 : 0ull) + (pd.n > 1 ? (unsigned long long)pd.len1 : 0ull);
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    uint32_t tp = 0, tc = 0;
-    unsigned long long tk = 0;
-    for (int i = 0; i < kPlanNW; i++) { tp += sh_n[i]; tc += sh_ch[i]; tk += sh_keys[i]; }
-    *sh_old = 0;
-    if (tp > 0) {
-      if (lvl_next >= kMaxLevels) {
-        atomicOr(c.err, kErrLevel);
-        *sh_old = ~0ull;
-      } else {
-        *sh_old = atomicAdd(&c.lvl[lvl_next].packed, ((unsigned long long)tp << 40) | tc);
-        atomicAdd(&c.lvl[lvl_next].keys, tk);
-      }
-    }
-  }
-  __syncthreads();
-  if (lane == 0 && pd.n > 0 && *sh_old != ~0ull) {
-    uint32_t idx = (uint32_t)(*sh_old >> 40), cb = (uint32_t)(*sh_old & kTileMask);
-    for (uint32_t i = 0; i < wv; i++) { idx += sh_n[i]; cb += sh_ch[i]; }
-    Seg *segs = (lvl_next & 1) ? c.seg1 : c.seg0;
-    unsigned long long *ctr = (lvl_next & 1) ? c.ctr1 : c.ctr0;
-#pragma unroll
-    for (uint32_t q = 0; q < 2; q++, idx++) {
-      if (q >= pd.n) break;
-      if (idx >= c.seg_cap) { atomicOr(c.err, kErrSegCap); break; }
-      Seg s;
-      s.off = q ? pd.off1 : pd.off0; s.pivot = q ? pd.pivot1 : pd.pivot0;
-      s.len = q ? pd.len1 : pd.len0; s.chunk_begin = cb;
-      s.depth = depth; s.dmax = dmax; s.req = pd.req; s.pad = 0;
-      segs[idx] = s;
-      ctr[(size_t)idx * kCtrStride] = 0ull;
-      if (HASV) ctr[(size_t)idx * kCtrStride + 1] = 0ull;
-      cb += q ? pd.chunks1 : pd.chunks0;
-    }
-  }
-  __syncthreads();
-}
-
-// A child of depth `depth`: small -> slot item; large -> pivot + pending part.
+// A child part of `len` keys at Y[off, ...) (Y = S if in_s, else K), depth
+// `depth`.  Small: its finish slot.  Large: its pivots and pass type, staged in
+// pend (lane 0).  With own_known, own is the pivot the child already has and
+// nlt / neq the counts of its keys below / equal to it (look-ahead of the pass
+// that produced it): the child gets a two-level pass.  Otherwise (payloads, the
+// depth limit, the exact-minimum test mode, or a root) it gets a one-level pass
+// around the sample median, or around the exact median / minimum found by radix
+// select.  Whole wave.
 template <int DT, bool HASV>
 __device__ inline void child(const Ctx &c, uint32_t slot, uint64_t off, uint32_t len, uint32_t depth,
-                             uint32_t dmax, uint32_t req, uint32_t *hist, Pending &pd,
+                             uint32_t dmax, uint32_t req, bool in_s, bool own_known, uint64_t own,
+                             uint32_t nlt, uint32_t neq, uint32_t *hist, PendLds &pend, uint32_t wv,
                              unsigned long long &small_parts, unsigned long long &small_keys) {
-  const bool in_s = (depth & 1) != 0;
+  using B = typename Codec<DT>::B;
   const uint32_t lane = lane_id();
   if (len <= c.small_max) {
     if (lane == 0) {
@@ -476,15 +493,87 @@ __device__ inline void child(const Ctx &c, uint32_t slot, uint64_t off, uint32_t
     }
     return;
   }
-  const typename Codec<DT>::B p = child_pivot<DT>(c, off, len, depth, dmax, hist);
+  const B *Y = (const B *)(in_s ? c.S : c.K);
+  uint32_t S = c.samples;
+  if (S > len) S = (len & 1) ? len : len - 1;
+  const bool exact = c.pivot_mode == 1 || depth >= dmax;
+  const bool fits = (uint64_t)nlt + neq <= len;
+  if (!HASV && own_known && !fits && lane == 0) atomicOr(c.err, kErrCount);
+  const bool two = !HASV && own_known && !exact && fits;
+  B p0 = (B)own;
+  if (exact) {
+    const uint32_t k = (c.pivot_mode == 1 && depth < dmax) ? 0u : len / 2;
+    if (lane == 0 && depth >= dmax) stat_add(c, kStFallback, 1ull);
+    p0 = wave_select<DT>(Y, off, len, k, hist);
+  }
+  uint64_t piv[7];
+  wave_part_pivots<DT>(Y, off, len, S, c.jitter, exact || two, p0, piv);
   if (lane == 0) {
     put_small(c, slot, 0, 0, false, req);
-    const uint32_t ch = part_chunks<DT, HASV>((depth & 1) ? c.S : c.K, off, len);
-    if (pd.n == 0) { pd.off0 = off; pd.pivot0 = (uint64_t)p; pd.len0 = len; pd.chunks0 = ch; }
-    else { pd.off1 = off; pd.pivot1 = (uint64_t)p; pd.len1 = len; pd.chunks1 = ch; }
-    pd.n++;
-    pd.req = req;
+    const uint32_t i = pend.n[wv];
+    Seg &r = pend.rec[wv][i];
+    r.off = off;
+#pragma unroll
+    for (int k = 0; k < 7; k++) r.piv[k] = piv[k];
+    r.len = len;
+    r.chunk_begin = part_chunks<DT, HASV>(in_s ? c.S : c.K, off, len);   // chunks, until flushed
+    r.depth = depth;
+    r.dmax = dmax;
+    r.req = req;
+    r.flags = (in_s ? kSegInS : 0u) | (two ? kSegTwo : 0u);
+    r.nlt = two ? nlt : 0u;
+    r.neq = two ? neq : 0u;
+    pend.n[wv] = i + 1;
+    pend.ch[wv] += r.chunk_begin;
+    pend.keys[wv] += len;
   }
+}
+
+// Reserve the workgroup's staged parts in level lvl_next with one atomic and
+// write them out (whole workgroup; clears the staging area).
+template <int DT, bool HASV>
+__device__ inline void flush_parts(const Ctx &c, int lvl_next, PendLds &pend) {
+  const uint32_t wv = threadIdx.x / kWave, lane = threadIdx.x & 63u;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t tp = 0, tc = 0;
+    unsigned long long tk = 0;
+    for (int i = 0; i < kPlanNW; i++) { tp += pend.n[i]; tc += pend.ch[i]; tk += pend.keys[i]; }
+    pend.old = 0;
+    if (tp > 0) {
+      if (lvl_next >= kMaxLevels) {
+        atomicOr(c.err, kErrLevel);
+        pend.old = ~0ull;
+      } else {
+        pend.old = atomicAdd(&c.lvl[lvl_next].packed, ((unsigned long long)tp << 40) | tc);
+        atomicAdd(&c.lvl[lvl_next].keys, tk);
+      }
+    }
+  }
+  __syncthreads();
+  if (lane == 0 && pend.n[wv] > 0 && pend.old != ~0ull) {
+    uint32_t idx = (uint32_t)(pend.old >> 40), cb = (uint32_t)(pend.old & kTileMask);
+    for (uint32_t i = 0; i < wv; i++) { idx += pend.n[i]; cb += pend.ch[i]; }
+    Seg *segs = (lvl_next & 1) ? c.seg1 : c.seg0;
+    unsigned long long *ctr = (lvl_next & 1) ? c.ctr1 : c.ctr0;
+    for (uint32_t q = 0; q < pend.n[wv]; q++, idx++) {
+      if (idx >= c.seg_cap) { atomicOr(c.err, kErrSegCap); break; }
+      Seg r = pend.rec[wv][q];
+      const uint32_t nch = r.chunk_begin;
+      r.chunk_begin = cb;
+      segs[idx] = r;
+      unsigned long long *cp = ctr + (size_t)idx * kCtrStride;
+      cp[kCtrA] = 0ull;
+      cp[kCtrE] = 0ull;
+      cp[kCtrB] = 0ull;
+#pragma unroll
+      for (int k = 0; k < 4; k++) cp[kCtrLook + k] = 0ull;
+      cb += nch;
+    }
+  }
+  __syncthreads();
+  if (lane == 0) { pend.n[wv] = 0; pend.ch[wv] = 0; pend.keys[wv] = 0; }
+  __syncthreads();
 }
 
 // ---- kernels ------------------------------------------------------------------------
@@ -506,18 +595,18 @@ __global__ void k_level_clear(Ctx c, int lvl) {
 }
 
 // Roots: one wave per array (workgroup-uniform iterations).  A root is depth 0,
-// lives in K, and its small-part slot is 2 * seg_cap + root index.
+// lives in K, gets a one-level pass, and its small-part slot is 4 * seg_cap +
+// root index.
 template <int DT, bool HASV>
 __global__ __launch_bounds__(kPlanNT) void k_init(Ctx c) {
   __shared__ uint32_t hist[kPlanNW][256];
-  __shared__ uint32_t sh_n[kPlanNW], sh_ch[kPlanNW];
-  __shared__ unsigned long long sh_keys[kPlanNW], sh_old;
+  __shared__ PendLds pend;
   const uint32_t wv = threadIdx.x / kWave;
+  if ((threadIdx.x & 63u) == 0) { pend.n[wv] = 0; pend.ch[wv] = 0; pend.keys[wv] = 0; }
+  __syncthreads();
   unsigned long long small_parts = 0, small_keys = 0;
   for (uint32_t base = blockIdx.x * kPlanNW; base < c.nroots; base += gridDim.x * kPlanNW) {
     const uint32_t j = base + wv;
-    Pending pd = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
-    uint32_t dmax = 0;
     if (j < c.nroots) {
       uint64_t off;
       uint32_t len, req = 0;
@@ -531,11 +620,10 @@ __global__ __launch_bounds__(kPlanNT) void k_init(Ctx c) {
       }
       uint32_t lg = 0;
       while (lg < 32 && (1ull << lg) < (unsigned long long)len) lg++;
-      dmax = c.depth_factor * lg;
-      child<DT, HASV>(c, 2 * c.seg_cap + j, off, len, 0u, dmax, req, hist[wv], pd, small_parts,
-                      small_keys);
+      child<DT, HASV>(c, 4 * c.seg_cap + j, off, len, 0u, c.depth_factor * lg, req, false, false, 0ull,
+                      0u, 0u, hist[wv], pend, wv, small_parts, small_keys);
     }
-    flush_parts<DT, HASV>(c, c.root_level, pd, 0u, dmax, sh_n, sh_ch, sh_keys, &sh_old);
+    flush_parts<DT, HASV>(c, c.root_level, pend);
   }
   if ((threadIdx.x & 63u) == 0) {
     stat_add(c, kStSmallParts, small_parts);
@@ -550,7 +638,7 @@ __device__ inline void lane_put(uint32_t &v, uint32_t x) {
 }
 // f(integral_constant<int, I>) for I = B .. E-1, expanded at compile time
 template <int B, int E, typename F>
-__device__ inline void static_for(F &&f) {
+__device__ __attribute__((always_inline)) inline void static_for(F &&f) {
   if constexpr (B < E) {
     f(std::integral_constant<int, B>{});
     static_for<B + 1, E>(f);
@@ -562,6 +650,11 @@ __device__ inline void opaque_v(T &x) { asm volatile("" : "+v"(x)); }
 template <typename T>
 __device__ inline void opaque_s(T &x) { asm volatile("" : "+s"(x)); }
 
+// c ? a : b on values (a conditional on lvalues would select their addresses,
+// which keeps the variables out of registers)
+template <typename T>
+__device__ __attribute__((always_inline)) inline T pick(bool c, T a, T b) { return c ? a : b; }
+
 // &base[i]; unless WIDE, i * sizeof(T) must fit in 32 bits (the address is
 // then formed as a uniform base plus a 32-bit lane offset)
 template <bool WIDE, typename T>
@@ -570,16 +663,20 @@ __device__ inline T *at(T *base, uint32_t i) {
   else return (T *)((char *)base + (uint32_t)(i * (uint32_t)sizeof(T)));
 }
 
-// One partition level: every chunk of every part of level d.  WIDE: some part
-// may span 4 GiB or more of keys or payloads.
-template <int DT, bool HASV, bool WIDE>
+// One partition level: every chunk of every part of level d whose pass type is
+// TWO (two-level parts: keys only); the parts of the other type are skipped (a
+// kernel per type, so each has the registers, and the occupancy, its own work
+// needs).  WIDE: some part may span 4 GiB or more of keys or payloads.
+template <int DT, bool HASV, bool WIDE, bool TWO>
 __global__ __launch_bounds__(kPartNT) void k_partition(Ctx c, int d) {
   using Cfg = PartCfg<DT, HASV>;
   using B = typename Cfg::B;
   constexpr int NT = kPartNT, NW = kPartNW, VEC = Cfg::VEC, KPT = Cfg::KPT;
   constexpr int NLOAD = Cfg::NLOAD, KB = Cfg::KB;
   constexpr uint64_t CH = Cfg::CH;
-  constexpr int NCLS = HASV ? 3 : 2;
+  // per-wave class counts: one-level [<, >, = (payloads) | look-ahead <<, <=, ><, >=],
+  // two-level [<<, <>, ><, >>, then look-ahead (below, equal) of each]
+  constexpr int NCLS = HASV ? 3 : 12;
   __shared__ uint32_t cnt[2][NCLS][NW];
   __shared__ uint32_t sh_part;
 
@@ -624,8 +721,9 @@ __global__ __launch_bounds__(kPartNT) void k_partition(Ctx c, int d) {
       s = segs[pi];
       nxt_begin = (pi + 1 < nseg) ? segs[pi + 1].chunk_begin : 0xFFFFFFFFu;
     }
-    // source X and destination Y by the part's depth (K when even, S when odd)
-    const bool odd = (s.depth & 1u) != 0;
+    if (((s.flags & kSegTwo) != 0) != TWO) continue;
+    // source X (where the part is) and destination Y (the other buffer)
+    const bool odd = (s.flags & kSegInS) != 0;
     const B *X = (const B *)(odd ? c.S : c.K);
     B *Y = (B *)(odd ? c.K : c.S);
     const uint32_t *VX = odd ? c.VS : c.V;
@@ -642,14 +740,13 @@ __global__ __launch_bounds__(kPartNT) void k_partition(Ctx c, int d) {
     const uint4 *win = (const uint4 *)(X + (int64_t)(W - xabs0));
     // payloads from window index lo on (part index max(W - A0, 0) on)
     const uint32_t *VXp = VX + s.off + (A0 > W ? 0u : (uint32_t)(W - A0));
+    const uint32_t rel0 = tid * VEC - lo;   // window index - lo, modulo 2^32
+    const uint32_t wlen = hi - lo;
+    B *Yp = Y + s.off;
 
-    // FULL: every window index holds a key of this part (no range checks)
-    auto body = [&](auto full_tag) {
+    // keys (and payloads) of this thread: KPT items, VEC consecutive per load
+    auto load = [&](auto full_tag, B (&key)[KPT], uint32_t (&val)[HASV ? KPT : 1]) __attribute__((always_inline)) {
       constexpr bool FULL = decltype(full_tag)::value;
-      const uint32_t rel0 = tid * VEC - lo;   // window index - lo, modulo 2^32
-      const uint32_t wlen = hi - lo;
-      B key[KPT];
-      uint32_t val[HASV ? KPT : 1];
 #pragma unroll
       for (int j = 0; j < NLOAD; j++) {
         const uint32_t e0 = (uint32_t)(j * NT + tid) * VEC;
@@ -670,35 +767,30 @@ __global__ __launch_bounds__(kPartNT) void k_partition(Ctx c, int d) {
           }
         }
       }
-      // item it of this lane: ok = holds a key of this part, lt / gt = the key
-      // is below / above the pivot; lm / gm / om are the wave's masks of lt /
-      // gt / ok (each a plain compare ballot, combined on the scalar unit)
-      B pvc = (B)s.pivot;
+    };
+    // range mask of item it (partial chunks): the lanes whose key is in the part
+    auto range_mask = [&](auto full_tag, int it, uint32_t relc) __attribute__((always_inline)) -> unsigned long long {
+      constexpr bool FULL = decltype(full_tag)::value;
+      if constexpr (FULL) return ~0ull;
+      else return wave_ballot(relc + (uint32_t)((it / VEC) * NT * VEC + (it % VEC)) < wlen);
+    };
+
+    // ---- one-level pass: split by piv[0] with a left and a right cursor ----
+    auto body1 = [&](auto full_tag) __attribute__((always_inline)) {
+      constexpr bool FULL = decltype(full_tag)::value;
+      B key[KPT];
+      uint32_t val[HASV ? KPT : 1];
+      load(full_tag, key, val);
+      B pvc = (B)s.piv[0], pl = (B)s.piv[1], pg = (B)s.piv[2];
       uint32_t relc = rel0;
-      auto classify = [&](int it, bool &lt, bool &gt, unsigned long long &lm,
-                          unsigned long long &gm, unsigned long long &om) {
-        const B u = Codec<DT>::enc(key[it]);
-        lt = u < pvc;
-        gt = u > pvc;
-        lm = wave_ballot(lt);
-        gm = wave_ballot(gt);
-        om = ~0ull;
-        if constexpr (!FULL) {
-          const bool ok = relc + (uint32_t)((it / VEC) * NT * VEC + (it % VEC)) < wlen;
-          om = wave_ballot(ok);
-          lm &= om;
-          gm &= om;
-          lt = lt && ok;
-          gt = gt && ok;
-        }
-      };
-      // pass 1: this wave's class totals (scalar)
-      uint32_t sL = 0, sG = 0, sO = 0;
-      static_for<0, KPT>([&](auto I) {
+      // pass 1: this wave's class totals, and the look-ahead counts of each side
+      // against its own pivot (scalar)
+      uint32_t sL = 0, sG = 0, sO = 0, aLl = 0, aLe = 0, aGl = 0, aGe = 0;
+      static_for<0, KPT>([&](auto I) __attribute__((always_inline)) {
         constexpr int it = decltype(I)::value;
-        bool lt, gt;
-        unsigned long long lm, gm, om;
-        classify(it, lt, gt, lm, gm, om);
+        const B u = Codec<DT>::enc(key[it]);
+        const unsigned long long om = range_mask(full_tag, it, relc);
+        const unsigned long long lm = wave_ballot(u < pvc) & om, gm = wave_ballot(u > pvc) & om;
         sL += (uint32_t)__popcll(lm);
         sG += (uint32_t)__popcll(gm);
         if constexpr (HASV && !FULL) sO += (uint32_t)__popcll(om);
@@ -706,12 +798,25 @@ __global__ __launch_bounds__(kPartNT) void k_partition(Ctx c, int d) {
         opaque_s(sL);
         opaque_s(sG);
         if constexpr (HASV && !FULL) opaque_s(sO);
+        if constexpr (!HASV) {
+          const B pc = pick<B>(u < pvc, pl, pg);
+          const unsigned long long m1 = wave_ballot(u < pc), e1 = wave_ballot(u == pc);
+          aLl += (uint32_t)__popcll(lm & m1);
+          aLe += (uint32_t)__popcll(lm & e1);
+          aGl += (uint32_t)__popcll(gm & m1);
+          aGe += (uint32_t)__popcll(gm & e1);
+          opaque_s(aLl); opaque_s(aLe); opaque_s(aGl); opaque_s(aGe);
+        }
       });
       if constexpr (HASV && FULL) sO = (uint32_t)(kWave * KPT);
       if (lane == 0) {
         cnt[bf][0][w] = sL;
         cnt[bf][1][w] = sG;
-        if constexpr (HASV) cnt[bf][2][w] = sO - sL - sG;
+        if constexpr (HASV) {
+          cnt[bf][2][w] = sO - sL - sG;
+        } else {
+          cnt[bf][2][w] = aLl; cnt[bf][3][w] = aLe; cnt[bf][4][w] = aGl; cnt[bf][5][w] = aGe;
+        }
       }
       __syncthreads();
       // exclusive prefix over the waves of each class; one reservation per chunk
@@ -723,12 +828,20 @@ __global__ __launch_bounds__(kPartNT) void k_partition(Ctx c, int d) {
         const uint32_t ia = wave_incl_scan(a), ib = wave_incl_scan(b);
         uint32_t ie = 0;
         if constexpr (HASV) ie = wave_incl_scan(e);
+        unsigned long long *cp = ctr + (size_t)pi * kCtrStride;
         unsigned long long rb = 0;
         uint32_t re = 0;
         if (lane == (uint32_t)NW - 1) {
-          unsigned long long *cp = ctr + (size_t)pi * kCtrStride;
-          rb = atomicAdd(cp, ((unsigned long long)ib << 32) | ia);
-          if constexpr (HASV) re = (uint32_t)atomicAdd(cp + 1, (unsigned long long)ie);
+          rb = atomicAdd(cp + kCtrA, ((unsigned long long)ib << 32) | ia);
+          if constexpr (HASV) re = (uint32_t)atomicAdd(cp + kCtrE, (unsigned long long)ie);
+        }
+        if constexpr (!HASV) {
+          // look-ahead totals: lane 0 the < side, lane 1 the > side
+          if (lane < 2) {
+            uint32_t tl = 0, te = 0;
+            for (int q = 0; q < NW; q++) { tl += cnt[bf][2 + 2 * lane][q]; te += cnt[bf][3 + 2 * lane][q]; }
+            if (tl | te) atomicAdd(cp + kCtrLook + lane, ((unsigned long long)te << 32) | tl);
+          }
         }
         // < keys fill from the left cursor, > keys from the right cursor
         // (the reserved block ends where the previous reservations began)
@@ -746,23 +859,30 @@ __global__ __launch_bounds__(kPartNT) void k_partition(Ctx c, int d) {
       uint32_t runG = __builtin_amdgcn_readfirstlane(cnt[bf][1][w]);
       uint32_t runE = 0;
       if constexpr (HASV) runE = __builtin_amdgcn_readfirstlane(cnt[bf][2][w]);
-      B *Yp = Y + s.off;
       uint32_t *VYp = VY + s.off;
       uint32_t *VEp = c.VE + s.off;
+      // codes are recomputed from the keys (no second register copy)
+      static_for<0, KPT>([&](auto I) __attribute__((always_inline)) { opaque_v(key[decltype(I)::value]); });
       // pass 2: the comparisons are recomputed rather than kept (2 x KPT wave
       // masks do not fit in scalar registers); the opaque copies stop the
       // compiler from keeping them
       opaque_v(pvc);
       opaque_v(relc);
-      static_for<0, KPT>([&](auto I) {
+      static_for<0, KPT>([&](auto I) __attribute__((always_inline)) {
         constexpr int it = decltype(I)::value;
-        bool lt, gt;
-        unsigned long long lm, gm, om;
-        classify(it, lt, gt, lm, gm, om);
+        const B u = Codec<DT>::enc(key[it]);
+        const unsigned long long om = range_mask(full_tag, it, relc);
+        bool lt = u < pvc, gt = u > pvc;
+        if constexpr (!FULL) {
+          const bool ok = relc + (uint32_t)((it / VEC) * NT * VEC + (it % VEC)) < wlen;
+          lt = lt && ok;
+          gt = gt && ok;
+        }
+        const unsigned long long lm = wave_ballot(lt), gm = wave_ballot(gt);
         uint32_t posL = runL + mbcnt(lm), posG = runG + mbcnt(gm);
         opaque_v(posL);   // select the position, not the masks
         opaque_v(posG);
-        const uint32_t pos = lt ? posL : posG;
+        const uint32_t pos = pick<uint32_t>(lt, posL, posG);
         runL += (uint32_t)__popcll(lm);
         runG += (uint32_t)__popcll(gm);
         if (lt || gt) {
@@ -777,47 +897,212 @@ __global__ __launch_bounds__(kPartNT) void k_partition(Ctx c, int d) {
         __builtin_amdgcn_sched_barrier(0);
       });
     };
-    if (lo == 0u && hi == (uint32_t)CH) body(std::true_type{});
-    else body(std::false_type{});
+
+    // ---- two-level pass: regions of piv[0] placed exactly, each split by its
+    // own pivot with two cursors (keys only) ----
+    auto body2 = [&](auto full_tag) __attribute__((always_inline)) {
+      B key[KPT];
+      uint32_t val[HASV ? KPT : 1];
+      load(full_tag, key, val);
+      B p0 = (B)s.piv[0], pl = (B)s.piv[1], pg = (B)s.piv[2];
+      const B pll = (B)s.piv[3], plg = (B)s.piv[4], pgl = (B)s.piv[5], pgg = (B)s.piv[6];
+      uint32_t relc = rel0;
+      // pass 1: the four grandchild classes (<<, <>, ><, >>) (scalar)
+      uint32_t n0 = 0, n1 = 0, n2 = 0, n3 = 0;
+      static_for<0, KPT>([&](auto I) __attribute__((always_inline)) {
+        constexpr int it = decltype(I)::value;
+        const B u = Codec<DT>::enc(key[it]);
+        const unsigned long long om = range_mask(full_tag, it, relc);
+        const bool lt0 = u < p0;
+        const unsigned long long ma = wave_ballot(lt0) & om, mb = wave_ballot(u > p0) & om;
+        const B pc = pick<B>(lt0, pl, pg);
+        const unsigned long long m1l = wave_ballot(u < pc), m1g = wave_ballot(u > pc);
+        n0 += (uint32_t)__popcll(ma & m1l); n1 += (uint32_t)__popcll(ma & m1g);
+        n2 += (uint32_t)__popcll(mb & m1l); n3 += (uint32_t)__popcll(mb & m1g);
+        opaque_s(n0); opaque_s(n1); opaque_s(n2); opaque_s(n3);
+      });
+      if (lane == 0) {
+        cnt[bf][0][w] = n0; cnt[bf][1][w] = n1; cnt[bf][2][w] = n2; cnt[bf][3][w] = n3;
+      }
+      __syncthreads();
+      if (w == 0) {
+        uint32_t x[4], ix[4];
+#pragma unroll
+        for (int k = 0; k < 4; k++) {
+          x[k] = lane < (uint32_t)NW ? cnt[bf][k][lane] : 0u;
+          ix[k] = wave_incl_scan(x[k]);
+        }
+        unsigned long long *cp = ctr + (size_t)pi * kCtrStride;
+        unsigned long long ra = 0, rb = 0;
+        if (lane == (uint32_t)NW - 1) {
+          ra = atomicAdd(cp + kCtrA, ((unsigned long long)ix[1] << 32) | ix[0]);
+          rb = atomicAdd(cp + kCtrB, ((unsigned long long)ix[3] << 32) | ix[2]);
+        }
+        ra = __shfl(ra, NW - 1);
+        rb = __shfl(rb, NW - 1);
+        const uint32_t t0 = __shfl(ix[0], NW - 1), t2 = __shfl(ix[2], NW - 1);
+        const uint32_t t1 = __shfl(ix[1], NW - 1), t3 = __shfl(ix[3], NW - 1);
+        const uint32_t g0 = s.nlt + s.neq;
+        // the regions come from the previous pass's counts: a chunk that would
+        // overfill one reports an internal error (its stores are also bounded)
+        if (lane == 0 && ((uint64_t)(uint32_t)ra + t0 + (uint32_t)(ra >> 32) + t1 > s.nlt ||
+                          (uint64_t)(uint32_t)rb + t2 + (uint32_t)(rb >> 32) + t3 + g0 > s.len))
+          atomicOr(c.err, kErrCount);
+        if (lane < (uint32_t)NW) {
+          // << from the start of the < region, <> as blocks from its end, ><
+          // from the start of the > region, >> as blocks from the part's end
+          cnt[bf][0][lane] = (uint32_t)ra + ix[0] - x[0];
+          cnt[bf][1][lane] = s.nlt - (uint32_t)(ra >> 32) - t1 + ix[1] - x[1];
+          cnt[bf][2][lane] = g0 + (uint32_t)rb + ix[2] - x[2];
+          cnt[bf][3][lane] = s.len - (uint32_t)(rb >> 32) - t3 + ix[3] - x[3];
+        }
+      }
+      __syncthreads();
+      uint32_t r0 = __builtin_amdgcn_readfirstlane(cnt[bf][0][w]);
+      uint32_t r1 = __builtin_amdgcn_readfirstlane(cnt[bf][1][w]);
+      uint32_t r2 = __builtin_amdgcn_readfirstlane(cnt[bf][2][w]);
+      uint32_t r3 = __builtin_amdgcn_readfirstlane(cnt[bf][3][w]);
+      // codes are recomputed from the keys (no second register copy)
+      static_for<0, KPT>([&](auto I) __attribute__((always_inline)) { opaque_v(key[decltype(I)::value]); });
+      // pass 2: stores, and the look-ahead counts of the grandchildren against
+      // piv[3..6] (scalar, reduced over the waves after the pass)
+      uint32_t l0 = 0, e0 = 0, l1 = 0, e1 = 0, l2 = 0, e2 = 0, l3 = 0, e3 = 0;
+      opaque_v(p0);
+      opaque_v(relc);
+      static_for<0, KPT>([&](auto I) __attribute__((always_inline)) {
+        constexpr int it = decltype(I)::value;
+        const B u = Codec<DT>::enc(key[it]);
+        const unsigned long long om = range_mask(full_tag, it, relc);
+        const bool lt0 = u < p0, gt0 = u > p0;
+        const B pc = pick<B>(lt0, pl, pg);
+        const bool lt1 = u < pc, gt1 = u > pc;
+        const unsigned long long ma = wave_ballot(lt0) & om, mb = wave_ballot(gt0) & om;
+        const unsigned long long m1l = wave_ballot(lt1), m1g = wave_ballot(gt1);
+        const unsigned long long q0 = ma & m1l, q1 = ma & m1g, q2 = mb & m1l, q3 = mb & m1g;
+        uint32_t x0 = r0 + mbcnt(q0), x1 = r1 + mbcnt(q1), x2 = r2 + mbcnt(q2), x3 = r3 + mbcnt(q3);
+        opaque_v(x0); opaque_v(x1); opaque_v(x2); opaque_v(x3);
+        const uint32_t pos = pick<uint32_t>(lt0, pick<uint32_t>(lt1, x0, x1), pick<uint32_t>(lt1, x2, x3));
+        r0 += (uint32_t)__popcll(q0); r1 += (uint32_t)__popcll(q1);
+        r2 += (uint32_t)__popcll(q2); r3 += (uint32_t)__popcll(q3);
+        if (((om >> lane) & 1ull) && (lt0 || gt0) && (lt1 || gt1) && pos < s.len)
+          *at<WIDE>(Yp, pos) = key[it];
+        const B pq = pick<B>(lt0, pick<B>(lt1, pll, plg), pick<B>(lt1, pgl, pgg));
+        const unsigned long long m2l = wave_ballot(u < pq), m2e = wave_ballot(u == pq);
+        l0 += (uint32_t)__popcll(q0 & m2l); e0 += (uint32_t)__popcll(q0 & m2e);
+        l1 += (uint32_t)__popcll(q1 & m2l); e1 += (uint32_t)__popcll(q1 & m2e);
+        l2 += (uint32_t)__popcll(q2 & m2l); e2 += (uint32_t)__popcll(q2 & m2e);
+        l3 += (uint32_t)__popcll(q3 & m2l); e3 += (uint32_t)__popcll(q3 & m2e);
+        opaque_s(l0); opaque_s(e0); opaque_s(l1); opaque_s(e1);
+        opaque_s(l2); opaque_s(e2); opaque_s(l3); opaque_s(e3);
+        opaque_s(r0); opaque_s(r1); opaque_s(r2); opaque_s(r3);
+        __builtin_amdgcn_sched_barrier(0);
+      });
+      if (lane == 0) {
+        cnt[bf][4][w] = l0; cnt[bf][5][w] = e0; cnt[bf][6][w] = l1; cnt[bf][7][w] = e1;
+        cnt[bf][8][w] = l2; cnt[bf][9][w] = e2; cnt[bf][10][w] = l3; cnt[bf][11][w] = e3;
+      }
+      __syncthreads();
+      if (w == 0 && lane < 4) {
+        uint32_t tl = 0, te = 0;
+        for (int q = 0; q < NW; q++) { tl += cnt[bf][4 + 2 * lane][q]; te += cnt[bf][5 + 2 * lane][q]; }
+        if (tl | te) atomicAdd(ctr + (size_t)pi * kCtrStride + kCtrLook + lane,
+                               ((unsigned long long)te << 32) | tl);
+      }
+    };
+
+    const bool full = lo == 0u && hi == (uint32_t)CH;
+    if constexpr (TWO && !HASV) {
+      if (full) body2(std::true_type{});
+      else body2(std::false_type{});
+    } else {
+      if (full) body1(std::true_type{});
+      else body1(std::false_type{});
+    }
   }
 }
 
 // After level d: bands, small children, next-level parts with pivots (a wave per
 // part, workgroup-uniform iterations so the workgroup can reserve together).
+// A one-level part leaves its < child (slot 4i), its > child (slot 4i+3) and the
+// band of piv[0] (band slot 3i+1); a two-level part leaves four grandchildren
+// (slots 4i..4i+3) and three bands: piv[1] inside the < region (3i), piv[0]
+// (3i+1), piv[2] inside the > region (3i+2).  Unused slots are written empty.
 template <int DT, bool HASV>
 __global__ __launch_bounds__(kPlanNT) void k_plan(Ctx c, int d) {
   __shared__ uint32_t hist[kPlanNW][256];
-  __shared__ uint32_t sh_n[kPlanNW], sh_ch[kPlanNW];
-  __shared__ unsigned long long sh_keys[kPlanNW], sh_old;
+  __shared__ PendLds pend;
   const unsigned long long packed = c.lvl[d].packed;
   const uint32_t nseg = (uint32_t)(packed >> 40);
   if (nseg > c.seg_cap) return;
   const Seg *segs = (d & 1) ? c.seg1 : c.seg0;
   const unsigned long long *ctr = (d & 1) ? c.ctr1 : c.ctr0;
   const uint32_t wv = threadIdx.x / kWave, lane = threadIdx.x & 63u;
+  if (lane == 0) { pend.n[wv] = 0; pend.ch[wv] = 0; pend.keys[wv] = 0; }
+  __syncthreads();
   unsigned long long small_parts = 0, small_keys = 0, band_keys = 0;
+  const int next = level_after(c, d);
   for (uint32_t base = blockIdx.x * kPlanNW; base < nseg; base += gridDim.x * kPlanNW) {
     const uint32_t si = base + wv;
-    Pending pd = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
-    uint32_t dmax = 0, cdepth = 0;
     if (si < nseg) {
       const Seg s = segs[si];
-      const unsigned long long cv = ctr[(size_t)si * kCtrStride];
-      const uint32_t L = (uint32_t)cv, G = (uint32_t)(cv >> 32);
-      const uint32_t E = s.len - L - G;
-      dmax = s.dmax;
-      cdepth = s.depth + 1;
-      if (lane == 0) {
-        put_band(c, d, si, s.off + L, s.off, E, s.pivot, s.req);
-        band_keys += E;
+      const unsigned long long *cp = ctr + (size_t)si * kCtrStride;
+      const bool out_s = (s.flags & kSegInS) == 0;     // children live in the other buffer
+      if (s.flags & kSegTwo) {
+        const unsigned long long ca = cp[kCtrA], cb = cp[kCtrB];
+        const uint32_t nll = (uint32_t)ca, nlg = (uint32_t)(ca >> 32);
+        const uint32_t ngl = (uint32_t)cb, ngg = (uint32_t)(cb >> 32);
+        const uint32_t nlt = s.nlt, neq = s.neq, g0 = nlt + neq;
+        const uint32_t ele = nlt - nll - nlg, egt = (s.len - g0) - ngl - ngg;
+        if ((uint64_t)nll + nlg > nlt || (uint64_t)g0 + ngl + ngg > s.len) {
+          // counts that do not fit the regions (a bug): report, emit nothing
+          if (lane == 0) {
+            atomicOr(c.err, kErrCount);
+            FinItem z;
+            z.off = 0; z.src = 0; z.pivot = 0; z.len = 0; z.kind = 0;
+            for (int k = 0; k < 3; k++) c.band[3 * si + k] = z;
+            for (int k = 0; k < 4; k++) put_small(c, 4 * si + k, 0, 0, false, s.req);
+          }
+        } else {
+        if (lane == 0) {
+          put_band(c, d, 3 * si + 0, s.off + nll, s.off, ele, s.piv[1], s.req);
+          put_band(c, d, 3 * si + 1, s.off + nlt, s.off, neq, s.piv[0], s.req);
+          put_band(c, d, 3 * si + 2, s.off + g0 + ngl, s.off, egt, s.piv[2], s.req);
+          band_keys += (unsigned long long)ele + neq + egt;
+        }
+        const uint64_t coff[4] = {s.off, s.off + nlt - nlg, s.off + g0, s.off + s.len - ngg};
+        const uint32_t clen[4] = {nll, nlg, ngl, ngg};
+#pragma unroll
+        for (int k = 0; k < 4; k++) {
+          const unsigned long long la = cp[kCtrLook + k];
+          child<DT, HASV>(c, 4 * si + k, coff[k], clen[k], s.depth + 2, s.dmax, s.req, out_s, true,
+                          s.piv[3 + k], (uint32_t)la, (uint32_t)(la >> 32), hist[wv], pend, wv,
+                          small_parts, small_keys);
+        }
+        }
+      } else {
+        const unsigned long long cv = cp[kCtrA];
+        const uint32_t L = (uint32_t)cv, G = (uint32_t)(cv >> 32);
+        const uint32_t E = s.len - L - G;
+        if (lane == 0) {
+          FinItem z;
+          z.off = 0; z.src = 0; z.pivot = 0; z.len = 0; z.kind = 0;
+          c.band[3 * si + 0] = z;
+          c.band[3 * si + 2] = z;
+          put_band(c, d, 3 * si + 1, s.off + L, s.off, E, s.piv[0], s.req);
+          band_keys += E;
+          put_small(c, 4 * si + 1, 0, 0, false, s.req);
+          put_small(c, 4 * si + 2, 0, 0, false, s.req);
+        }
+        const unsigned long long la = cp[kCtrLook + 0], ga = cp[kCtrLook + 1];
+        child<DT, HASV>(c, 4 * si, s.off, L, s.depth + 1, s.dmax, s.req, out_s, true, s.piv[1],
+                        (uint32_t)la, (uint32_t)(la >> 32), hist[wv], pend, wv, small_parts,
+                        small_keys);
+        child<DT, HASV>(c, 4 * si + 3, s.off + s.len - G, G, s.depth + 1, s.dmax, s.req, out_s, true,
+                        s.piv[2], (uint32_t)ga, (uint32_t)(ga >> 32), hist[wv], pend, wv,
+                        small_parts, small_keys);
       }
-      child<DT, HASV>(c, 2 * si, s.off, L, cdepth, dmax, s.req, hist[wv], pd, small_parts,
-                      small_keys);
-      child<DT, HASV>(c, 2 * si + 1, s.off + s.len - G, G, cdepth, dmax, s.req, hist[wv], pd,
-                      small_parts, small_keys);
     }
-    // each wave writes its own records, with its own depth and limit
-    flush_parts<DT, HASV>(c, level_after(c, d), pd, cdepth, dmax, sh_n, sh_ch, sh_keys, &sh_old);
+    flush_parts<DT, HASV>(c, next, pend);
   }
   if (lane == 0) {
     stat_add(c, kStSmallParts, small_parts);
@@ -1212,7 +1497,8 @@ __device__ inline void fill_band(const Ctx &c, const FinItem &it, uint32_t t, ui
 
 // Level d's finishing work: long-band chunks and workgroup-sized small parts
 // (workgroup each), then wave-sized small parts and short bands (wave each).
-// Child slots are [0, 2 * parts of level d); at level 0 also the root slots.
+// Child slots are [0, 4 * parts of level d), band slots [0, 3 * parts); at the
+// roots' level also the root slots.
 template <int DT, bool HASV, bool BITONIC>
 __global__ __launch_bounds__(kFinNT) void k_finish(Ctx c, int d) {
   using B = typename Codec<DT>::B;
@@ -1223,7 +1509,7 @@ __global__ __launch_bounds__(kFinNT) void k_finish(Ctx c, int d) {
   const uint32_t nseg = (uint32_t)(c.lvl[d].packed >> 40);
   const uint32_t nbig = c.lvl[d].nbig;
   if (nseg > c.seg_cap || nbig > c.big_cap) return;
-  const uint32_t nchild = 2 * nseg;
+  const uint32_t nchild = 4 * nseg;
   const uint32_t nslots = nchild + (d == c.root_level ? c.nroots : 0u);
   const uint32_t tid = threadIdx.x;
   for (uint32_t ii = blockIdx.x; ii < nbig + nslots; ii += gridDim.x) {
@@ -1238,7 +1524,7 @@ __global__ __launch_bounds__(kFinNT) void k_finish(Ctx c, int d) {
       continue;
     }
     const uint32_t q = ii - nbig;
-    const uint32_t slot = q < nchild ? q : 2 * c.seg_cap + (q - nchild);
+    const uint32_t slot = q < nchild ? q : 4 * c.seg_cap + (q - nchild);
     const FinItem it = c.fin[slot];
     if (it.len == 0) continue;
     const uint32_t P = next_pow2(it.len);
@@ -1262,7 +1548,7 @@ __global__ __launch_bounds__(kFinNT) void k_finish(Ctx c, int d) {
   const uint32_t wv = tid / kWave, lane = tid & 63u;
   T *wl = lds + (size_t)wv * lds_pad(c.wave_max);
   const uint32_t gw = blockIdx.x * kFinNW + wv, nw = gridDim.x * kFinNW;
-  for (uint32_t q = gw; q < nslots + nseg; q += nw) {
+  for (uint32_t q = gw; q < nslots + 3 * nseg; q += nw) {
     if (q >= nslots) {
       const FinItem bd = c.band[q - nslots];
       if (bd.len) {
@@ -1275,7 +1561,7 @@ __global__ __launch_bounds__(kFinNT) void k_finish(Ctx c, int d) {
       }
       continue;
     }
-    const uint32_t slot = q < nchild ? q : 2 * c.seg_cap + (q - nchild);
+    const uint32_t slot = q < nchild ? q : 4 * c.seg_cap + (q - nchild);
     const FinItem it = c.finw[slot];
     if (it.len == 0) continue;
     const uint32_t P = next_pow2(it.len);

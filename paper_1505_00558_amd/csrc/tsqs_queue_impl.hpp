@@ -98,13 +98,13 @@ namespace {
 size_t group_table_bytes(size_t elems, uint32_t small_max, size_t *seg_cap, size_t *slot_cap,
                          size_t *big_cap) {
   const size_t sc = elems / ((size_t)small_max + 1) + 2;
-  const size_t fc = 2 * sc + kQRootsPerTick;
+  const size_t fc = 4 * sc + kQRootsPerTick;
   const size_t bc = 2 * (elems / kBandChunk) + 16;
   if (seg_cap) *seg_cap = sc;
   if (slot_cap) *slot_cap = fc;
   if (big_cap) *big_cap = bc;
   return 2 * sc * (sizeof(Seg) + kCtrStride * sizeof(unsigned long long)) +
-         2 * fc * sizeof(FinItem) + sc * sizeof(FinItem) + bc * sizeof(FinItem) +
+         2 * fc * sizeof(FinItem) + 3 * sc * sizeof(FinItem) + bc * sizeof(FinItem) +
          sizeof(LevelCtl) * kMaxLevels + sizeof(unsigned long long) * (kStripes * kStatWords + 16) +
          kInFlight * kQRootsPerTick * sizeof(RootRec);
 }
@@ -140,7 +140,7 @@ int group_init(tsqs_queue *q, int dt) {
   }
   c0 = 0; if (grow(&G.fin, &c0, G.slot_cap) != TSQS_OK) return TSQS_ENOMEM;
   c0 = 0; if (grow(&G.finw, &c0, G.slot_cap) != TSQS_OK) return TSQS_ENOMEM;
-  c0 = 0; if (grow(&G.band, &c0, G.seg_cap) != TSQS_OK) return TSQS_ENOMEM;
+  c0 = 0; if (grow(&G.band, &c0, 3 * G.seg_cap) != TSQS_OK) return TSQS_ENOMEM;
   c0 = 0; if (grow(&G.big, &c0, G.big_cap) != TSQS_OK) return TSQS_ENOMEM;
   c0 = 0; if (grow(&G.lvl, &c0, (size_t)kMaxLevels) != TSQS_OK) return TSQS_ENOMEM;
   c0 = 0; if (grow(&G.stats, &c0, (size_t)(kStripes * kStatWords + 16)) != TSQS_OK) return TSQS_ENOMEM;
@@ -316,10 +316,13 @@ int launch_tick(tsqs_queue *q, QGroup &G) {
     hipLaunchKernelGGL((k_init<DT, false>), dim3(wgs < (uint32_t)grid ? wgs : (uint32_t)grid),
                        dim3(kPlanNT), 0, G.s, c);
   }
-  if ((uint64_t)G.max_n * G.kb > 0xFFFFFFFFull)
-    hipLaunchKernelGGL((k_partition<DT, false, true>), dim3(grid), dim3(kPartNT), 0, G.s, c, d);
-  else
-    hipLaunchKernelGGL((k_partition<DT, false, false>), dim3(grid), dim3(kPartNT), 0, G.s, c, d);
+  if ((uint64_t)G.max_n * G.kb > 0xFFFFFFFFull) {
+    hipLaunchKernelGGL((k_partition<DT, false, true, false>), dim3(grid), dim3(kPartNT), 0, G.s, c, d);
+    hipLaunchKernelGGL((k_partition<DT, false, true, true>), dim3(grid), dim3(kPartNT), 0, G.s, c, d);
+  } else {
+    hipLaunchKernelGGL((k_partition<DT, false, false, false>), dim3(grid), dim3(kPartNT), 0, G.s, c, d);
+    hipLaunchKernelGGL((k_partition<DT, false, false, true>), dim3(grid), dim3(kPartNT), 0, G.s, c, d);
+  }
   hipLaunchKernelGGL((k_plan<DT, false>), dim3(grid), dim3(kPlanNT), 0, G.s, c, d);
   const int fgrid = g_opt.finish_grid > 0 ? (int)g_opt.finish_grid : 8 * q->cus;
   if (g_opt.finish_algo == 0)
