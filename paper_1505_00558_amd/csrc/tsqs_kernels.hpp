@@ -99,6 +99,7 @@ template <int DT, bool HASV> struct PartCfg {
   static constexpr int KPT = KB == 4 ? (HASV ? 16 : 32) : (HASV ? 8 : 16);  // keys per thread
   static constexpr int NLOAD = KPT / VEC;
   static constexpr uint64_t CH = (uint64_t)kPartNT * KPT;               // keys per chunk
+  static constexpr uint64_t LINE = 128 / KB;                            // keys per 128-byte line
   static_assert(KPT % VEC == 0 && kPartNW <= kWave, "layout");
 };
 
@@ -391,13 +392,15 @@ __device__ inline uint32_t next_pow2(uint32_t x) {
   return p;
 }
 
-// Number of chunks of a part [off, off+len) of a buffer: chunks are aligned to
-// CH keys in the absolute (address / key size) coordinate.
+// Number of chunks of a part [off, off+len) of a buffer: the part's chunks are
+// consecutive windows of CH keys from the 128-byte line holding its first key
+// (so a part of up to CH keys, less its offset in that line, is one chunk, and
+// every wave's loads cover whole lines).
 template <int DT, bool HASV>
 __device__ inline uint32_t part_chunks(const void *buf, uint64_t off, uint32_t len) {
   using Cfg = PartCfg<DT, HASV>;
   const uint64_t a0 = (uint64_t)(uintptr_t)buf / Cfg::KB + off;
-  return (uint32_t)((a0 + len - 1) / Cfg::CH - a0 / Cfg::CH + 1);
+  return (uint32_t)((a0 % Cfg::LINE + len + Cfg::CH - 1) / Cfg::CH);
 }
 
 
@@ -657,6 +660,24 @@ __device__ __attribute__((always_inline)) inline T pick(bool c, T a, T b) { retu
 
 // &base[i]; unless WIDE, i * sizeof(T) must fit in 32 bits (the address is
 // then formed as a uniform base plus a 32-bit lane offset)
+// partition passes that stage the next chunk's keys through LDS
+constexpr bool kStageOne = true, kStageTwo = false;
+
+// a part record in the constant address space
+using CSeg = __attribute__((address_space(4))) Seg;
+__device__ inline Seg load_seg(const CSeg *p) {
+  Seg r;
+  r.off = p->off;
+#pragma unroll
+  for (int k = 0; k < 7; k++) r.piv[k] = p->piv[k];
+  r.len = p->len; r.chunk_begin = p->chunk_begin; r.depth = p->depth; r.dmax = p->dmax;
+  r.req = p->req; r.flags = p->flags; r.nlt = p->nlt; r.neq = p->neq;
+  return r;
+}
+
+// s_waitcnt immediate (gfx9 encoding): lgkmcnt(0), the other counters free
+constexpr int kWaitLgkm0 = 0xC07F;
+
 template <bool WIDE, typename T>
 __device__ inline T *at(T *base, uint32_t i) {
   if constexpr (WIDE) return base + i;
@@ -671,14 +692,21 @@ template <int DT, bool HASV, bool WIDE, bool TWO>
 __global__ __launch_bounds__(kPartNT) void k_partition(Ctx c, int d) {
   using Cfg = PartCfg<DT, HASV>;
   using B = typename Cfg::B;
+  // keys staged through LDS (the next chunk's loads in flight during this one)
+  constexpr bool STAGE = TWO ? kStageTwo : kStageOne;
   constexpr int NT = kPartNT, NW = kPartNW, VEC = Cfg::VEC, KPT = Cfg::KPT;
   constexpr int NLOAD = Cfg::NLOAD, KB = Cfg::KB;
   constexpr uint64_t CH = Cfg::CH;
   // per-wave class counts: one-level [<, >, = (payloads) | look-ahead <<, <=, ><, >=],
-  // two-level [<<, <>, ><, >>, then look-ahead (below, equal) of each]
-  constexpr int NCLS = HASV ? 3 : 12;
+  // two-level [<<, <>, ><, >>, then the look-ahead sums as packed 16-bit fields]
+  constexpr int NCLS = HASV ? 3 : 8;
   __shared__ uint32_t cnt[2][NCLS][NW];
   __shared__ uint32_t sh_part;
+  // the keys of the next chunk, loaded from HBM straight into LDS while the
+  // current chunk is processed; each wave loads, and later reads, only its own
+  // blocks (element j * NT + tid is window block j * NT + tid), so no barrier
+  // guards the stage
+  __shared__ uint4 stage[STAGE ? NLOAD * NT : 1];
 
   const unsigned long long packed = c.lvl[d].packed;
   const uint32_t nseg = (uint32_t)(packed >> 40);
@@ -690,7 +718,10 @@ __global__ __launch_bounds__(kPartNT) void k_partition(Ctx c, int d) {
   if (t0 >= nch) return;
   const uint32_t t1 = (nch - t0 < per) ? nch : t0 + per;
 
-  const Seg *segs = (d & 1) ? c.seg1 : c.seg0;
+  // the records of level d are read-only here (written by the previous level's
+  // planning): read through the constant address space, so that uniform reads
+  // become scalar loads even after this kernel's own stores
+  const CSeg *segs = (const CSeg *)((d & 1) ? c.seg1 : c.seg0);
   unsigned long long *ctr = (d & 1) ? c.ctr1 : c.ctr0;
   const uint32_t tid = threadIdx.x, lane = tid & 63u, w = tid >> 6;
 
@@ -711,35 +742,66 @@ __global__ __launch_bounds__(kPartNT) void k_partition(Ctx c, int d) {
   }
   __syncthreads();
   uint32_t pi = __builtin_amdgcn_readfirstlane(sh_part);
-  Seg s = segs[pi];
-  uint32_t nxt_begin = (pi + 1 < nseg) ? segs[pi + 1].chunk_begin : 0xFFFFFFFFu;
 
-  for (uint32_t t = t0; t < t1; t++) {
-    const int bf = (int)((t - t0) & 1u);
-    while (nxt_begin <= t) {
-      pi++;
-      s = segs[pi];
-      nxt_begin = (pi + 1 < nseg) ? segs[pi + 1].chunk_begin : 0xFFFFFFFFu;
+  // first chunk >= t of this kernel's pass type (t1 if none); p: its part
+  auto advance = [&](uint32_t t, uint32_t &p) __attribute__((always_inline)) -> uint32_t {
+    while (t < t1) {
+      while (p + 1 < nseg && segs[p + 1].chunk_begin <= t) p++;
+      if (((segs[p].flags & kSegTwo) != 0) == TWO) return t;
+      t = p + 1 < nseg ? segs[p + 1].chunk_begin : t1;   // skip the rest of the part
     }
-    if (((s.flags & kSegTwo) != 0) != TWO) continue;
+    return t1;
+  };
+  // chunk window [W, W + CH) in absolute key coordinates of the buffer holding
+  // the part; the keys of the part occupy window indices [lo, hi), and win is
+  // the window's first 16-byte block as an address (it may lie before the
+  // buffer's start: only blocks that hold keys of the part are ever loaded)
+  struct Win { const uint4 *win; uint32_t lo, hi, skip; };   // skip: keys of the part before W
+  auto window = [&](uint64_t off, uint32_t len, uint32_t flags, uint32_t cb, uint32_t t)
+      __attribute__((always_inline)) -> Win {
+    const B *X = (const B *)((flags & kSegInS) ? c.S : c.K);
+    const uint64_t xabs0 = (uint64_t)(uintptr_t)X / KB;
+    const uint64_t A0 = xabs0 + off, A1 = A0 + len;
+    const uint64_t W = A0 - A0 % Cfg::LINE + (uint64_t)(t - cb) * CH;
+    Win r;
+    r.lo = A0 > W ? (uint32_t)(A0 - W) : 0u;
+    r.hi = A1 < W + CH ? (uint32_t)(A1 - W) : (uint32_t)CH;
+    r.win = (const uint4 *)(X + (int64_t)(W - xabs0));
+    r.skip = A0 > W ? 0u : (uint32_t)(W - A0);
+    return r;
+  };
+  // issue the loads of chunk t (part p) into the stage
+  auto prefetch = [&](uint32_t t, uint32_t p) __attribute__((always_inline)) {
+    const Win g = window(segs[p].off, segs[p].len, segs[p].flags, segs[p].chunk_begin, t);
+    const bool full = g.lo == 0u && g.hi == (uint32_t)CH;
+#pragma unroll
+    for (int j = 0; j < NLOAD; j++) {
+      const uint32_t e0 = (uint32_t)(j * NT + tid) * VEC;
+      if (full || (e0 + VEC > g.lo && e0 < g.hi))
+        __builtin_amdgcn_global_load_lds((const void *)(g.win + j * NT + tid),
+                                         (__attribute__((address_space(3))) void *)(stage + j * NT + w * kWave),
+                                         16, 0, 0);
+    }
+  };
+
+  uint32_t t = advance(t0, pi);
+  if constexpr (STAGE) {
+    if (t < t1) prefetch(t, pi);
+  }
+  while (t < t1) {
+    const int bf = (int)((t - t0) & 1u);
+    const Seg s = load_seg(segs + pi);
+    uint32_t pn = pi;
+    const uint32_t tn = advance(t + 1, pn);
     // source X (where the part is) and destination Y (the other buffer)
     const bool odd = (s.flags & kSegInS) != 0;
-    const B *X = (const B *)(odd ? c.S : c.K);
     B *Y = (B *)(odd ? c.K : c.S);
     const uint32_t *VX = odd ? c.VS : c.V;
     uint32_t *VY = odd ? c.V : c.VS;
-    const uint64_t xabs0 = (uint64_t)(uintptr_t)X / KB;
-    // chunk window [W, W + CH) in absolute key coordinates; the keys of this
-    // part occupy window indices [lo, hi)
-    const uint64_t A0 = xabs0 + s.off, A1 = A0 + s.len;
-    const uint64_t W = (A0 / CH + (uint64_t)(t - s.chunk_begin)) * CH;
-    const uint32_t lo = A0 > W ? (uint32_t)(A0 - W) : 0u;
-    const uint32_t hi = A1 < W + CH ? (uint32_t)(A1 - W) : (uint32_t)CH;
-    // window start as an offset from X (it may begin before X[0]; only 16-byte
-    // blocks that hold keys of this part are loaded)
-    const uint4 *win = (const uint4 *)(X + (int64_t)(W - xabs0));
+    const Win g = window(s.off, s.len, s.flags, s.chunk_begin, t);
+    const uint32_t lo = g.lo, hi = g.hi;
     // payloads from window index lo on (part index max(W - A0, 0) on)
-    const uint32_t *VXp = VX + s.off + (A0 > W ? 0u : (uint32_t)(W - A0));
+    const uint32_t *VXp = VX + s.off + g.skip;
     const uint32_t rel0 = tid * VEC - lo;   // window index - lo, modulo 2^32
     const uint32_t wlen = hi - lo;
     B *Yp = Y + s.off;
@@ -749,9 +811,14 @@ __global__ __launch_bounds__(kPartNT) void k_partition(Ctx c, int d) {
       constexpr bool FULL = decltype(full_tag)::value;
 #pragma unroll
       for (int j = 0; j < NLOAD; j++) {
-        const uint32_t e0 = (uint32_t)(j * NT + tid) * VEC;
         uint4 v = make_uint4(0u, 0u, 0u, 0u);
-        if (FULL || (e0 + VEC > lo && e0 < hi)) v = win[j * NT + tid];
+        if constexpr (STAGE) {
+          // blocks outside the part hold stale values: the range masks drop them
+          v = stage[j * NT + tid];
+        } else {
+          const uint32_t e0 = (uint32_t)(j * NT + tid) * VEC;
+          if (FULL || (e0 + VEC > lo && e0 < hi)) v = g.win[j * NT + tid];
+        }
         if constexpr (KB == 4) {
           key[j * VEC + 0] = v.x; key[j * VEC + 1] = v.y; key[j * VEC + 2] = v.z; key[j * VEC + 3] = v.w;
         } else {
@@ -766,6 +833,11 @@ __global__ __launch_bounds__(kPartNT) void k_partition(Ctx c, int d) {
             val[j * VEC + q] = *at<false>(VXp, (FULL || r < wlen) ? r : 0u);
           }
         }
+      }
+      if constexpr (STAGE) {
+        // the stage is free once its blocks are in registers: load the next chunk
+        __builtin_amdgcn_s_waitcnt(kWaitLgkm0);
+        if (tn < t1) prefetch(tn, pn);
       }
     };
     // range mask of item it (partial chunks): the lanes whose key is in the part
@@ -905,7 +977,7 @@ __global__ __launch_bounds__(kPartNT) void k_partition(Ctx c, int d) {
       uint32_t val[HASV ? KPT : 1];
       load(full_tag, key, val);
       B p0 = (B)s.piv[0], pl = (B)s.piv[1], pg = (B)s.piv[2];
-      const B pll = (B)s.piv[3], plg = (B)s.piv[4], pgl = (B)s.piv[5], pgg = (B)s.piv[6];
+      B pll = (B)s.piv[3], plg = (B)s.piv[4], pgl = (B)s.piv[5], pgg = (B)s.piv[6];
       uint32_t relc = rel0;
       // pass 1: the four grandchild classes (<<, <>, ><, >>) (scalar)
       uint32_t n0 = 0, n1 = 0, n2 = 0, n3 = 0;
@@ -965,8 +1037,15 @@ __global__ __launch_bounds__(kPartNT) void k_partition(Ctx c, int d) {
       // codes are recomputed from the keys (no second register copy)
       static_for<0, KPT>([&](auto I) __attribute__((always_inline)) { opaque_v(key[decltype(I)::value]); });
       // pass 2: stores, and the look-ahead counts of the grandchildren against
-      // piv[3..6] (scalar, reduced over the waves after the pass)
-      uint32_t l0 = 0, e0 = 0, l1 = 0, e1 = 0, l2 = 0, e2 = 0, l3 = 0, e3 = 0;
+      // piv[3..6]: per lane, 8-bit counters packed by grandchild (byte k: keys
+      // of grandchild k below / equal to its pivot; at most KPT <= 255 per lane),
+      // reduced over the wave and the workgroup after the pass
+      static_assert(KPT <= 255, "packed look-ahead counters");
+      uint32_t accL = 0, accE = 0;
+      // pivots selected per lane live in vector registers (a select takes at
+      // most one scalar operand)
+      opaque_v(pl); opaque_v(pg);
+      opaque_v(pll); opaque_v(plg); opaque_v(pgl); opaque_v(pgg);
       opaque_v(p0);
       opaque_v(relc);
       static_for<0, KPT>([&](auto I) __attribute__((always_inline)) {
@@ -984,27 +1063,40 @@ __global__ __launch_bounds__(kPartNT) void k_partition(Ctx c, int d) {
         const uint32_t pos = pick<uint32_t>(lt0, pick<uint32_t>(lt1, x0, x1), pick<uint32_t>(lt1, x2, x3));
         r0 += (uint32_t)__popcll(q0); r1 += (uint32_t)__popcll(q1);
         r2 += (uint32_t)__popcll(q2); r3 += (uint32_t)__popcll(q3);
-        if (((om >> lane) & 1ull) && (lt0 || gt0) && (lt1 || gt1) && pos < s.len)
-          *at<WIDE>(Yp, pos) = key[it];
+        const bool in = ((om >> lane) & 1ull) && (lt0 || gt0) && (lt1 || gt1);
         const B pq = pick<B>(lt0, pick<B>(lt1, pll, plg), pick<B>(lt1, pgl, pgg));
-        const unsigned long long m2l = wave_ballot(u < pq), m2e = wave_ballot(u == pq);
-        l0 += (uint32_t)__popcll(q0 & m2l); e0 += (uint32_t)__popcll(q0 & m2e);
-        l1 += (uint32_t)__popcll(q1 & m2l); e1 += (uint32_t)__popcll(q1 & m2e);
-        l2 += (uint32_t)__popcll(q2 & m2l); e2 += (uint32_t)__popcll(q2 & m2e);
-        l3 += (uint32_t)__popcll(q3 & m2l); e3 += (uint32_t)__popcll(q3 & m2e);
-        opaque_s(l0); opaque_s(e0); opaque_s(l1); opaque_s(e1);
-        opaque_s(l2); opaque_s(e2); opaque_s(l3); opaque_s(e3);
+        const uint32_t one = 1u << (pick<uint32_t>(gt0, 16u, 0u) + pick<uint32_t>(gt1, 8u, 0u));
+        accL += (in && u < pq) ? one : 0u;
+        accE += (in && u == pq) ? one : 0u;
+        // counted before the store: the masks of this item end here
+        opaque_v(accL); opaque_v(accE);
+        if (in && pos < s.len) *at<WIDE>(Yp, pos) = key[it];
         opaque_s(r0); opaque_s(r1); opaque_s(r2); opaque_s(r3);
-        __builtin_amdgcn_sched_barrier(0);
+        // four items at a time: enough overlap to hide the compare-to-mask
+        // latency, few enough masks live to stay in scalar registers
+        if constexpr (it % 4 == 3) __builtin_amdgcn_sched_barrier(0);
       });
+      // widen to 16-bit fields (grandchildren 0 and 2 | 1 and 3; a chunk has at
+      // most 2^16 - 1 keys) and sum over the wave
+      static_assert(CH < 65536, "16-bit look-ahead sums");
+      uint32_t f[4] = {accL & 0x00FF00FFu, (accL >> 8) & 0x00FF00FFu,
+                       accE & 0x00FF00FFu, (accE >> 8) & 0x00FF00FFu};
+#pragma unroll
+      for (int k = 0; k < 4; k++) {
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) f[k] += shfl_xor_u32(f[k], o);
+      }
       if (lane == 0) {
-        cnt[bf][4][w] = l0; cnt[bf][5][w] = e0; cnt[bf][6][w] = l1; cnt[bf][7][w] = e1;
-        cnt[bf][8][w] = l2; cnt[bf][9][w] = e2; cnt[bf][10][w] = l3; cnt[bf][11][w] = e3;
+        cnt[bf][4][w] = f[0]; cnt[bf][5][w] = f[1]; cnt[bf][6][w] = f[2]; cnt[bf][7][w] = f[3];
       }
       __syncthreads();
       if (w == 0 && lane < 4) {
+        // grandchild q = lane: field (q & 2) * 8 of word q & 1
         uint32_t tl = 0, te = 0;
-        for (int q = 0; q < NW; q++) { tl += cnt[bf][4 + 2 * lane][q]; te += cnt[bf][5 + 2 * lane][q]; }
+        for (int q = 0; q < NW; q++) { tl += cnt[bf][4 + (lane & 1)][q]; te += cnt[bf][6 + (lane & 1)][q]; }
+        const int sh = (lane & 2) ? 16 : 0;
+        tl = (tl >> sh) & 0xFFFFu;
+        te = (te >> sh) & 0xFFFFu;
         if (tl | te) atomicAdd(ctr + (size_t)pi * kCtrStride + kCtrLook + lane,
                                ((unsigned long long)te << 32) | tl);
       }
@@ -1018,6 +1110,8 @@ __global__ __launch_bounds__(kPartNT) void k_partition(Ctx c, int d) {
       if (full) body1(std::true_type{});
       else body1(std::false_type{});
     }
+    t = tn;
+    pi = pn;
   }
 }
 
