@@ -76,7 +76,11 @@ enum {
   TSQS_OPT_PART_GRID = 7,    /* workgroups of the partition kernel (0 = auto) */
   TSQS_OPT_FINISH_GRID = 8,  /* workgroups of the finish kernel (0 = auto: 8 per CU) */
   TSQS_OPT_FINISH_ALGO = 9   /* small parts: 0 = bitonic sorting network, 1 = per-thread
-                                sorting network + merge-path merging in LDS (default) */
+                                sorting network + merge-path merging in LDS, one output
+                                at a time, 2 = the same with each thread's outputs
+                                merged by a register network, 3 = runs of up to one
+                                wave merged by cross-lane bitonic stages in registers
+                                first, then as 1 (default) */
 };
 
 #define TSQS_MAX_LEVELS 192

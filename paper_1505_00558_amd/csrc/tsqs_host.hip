@@ -37,7 +37,7 @@ struct Options {
   int64_t timing = 0;
   int64_t part_grid = 0;
   int64_t finish_grid = 0;
-  int64_t finish_algo = 1;
+  int64_t finish_algo = 3;
 };
 
 struct Workspace {
@@ -240,9 +240,13 @@ int run_t(Workspace &w, void *keys, uint32_t *vals, const uint64_t *h_offs, size
   const int plan_grid = 4 * w.cus;
   const size_t fin_lds = geo.fin_lds;
   if (fin_lds > 65536) {
-    HIPCHK(hipFuncSetAttribute((const void *)k_finish<DT, HASV, false>,
+    HIPCHK(hipFuncSetAttribute((const void *)k_finish<DT, HASV, 0>,
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)fin_lds));
-    HIPCHK(hipFuncSetAttribute((const void *)k_finish<DT, HASV, true>,
+    HIPCHK(hipFuncSetAttribute((const void *)k_finish<DT, HASV, 1>,
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)fin_lds));
+    HIPCHK(hipFuncSetAttribute((const void *)k_finish<DT, HASV, 2>,
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)fin_lds));
+    HIPCHK(hipFuncSetAttribute((const void *)k_finish<DT, HASV, 3>,
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)fin_lds));
   }
   const size_t waves_init = (nroots + kPlanNW - 1) / kPlanNW;
@@ -282,9 +286,13 @@ int run_t(Workspace &w, void *keys, uint32_t *vals, const uint64_t *h_offs, size
       if (g_opt.timing) HIPCHK(hipEventRecord(w.ev[2 * d + 1], s));
       if (!idle) hipLaunchKernelGGL((k_plan<DT, HASV>), dim3(plan_grid), dim3(kPlanNT), 0, s, c, d);
       if (g_opt.finish_algo == 0)
-        hipLaunchKernelGGL((k_finish<DT, HASV, true>), dim3(fin_grid), dim3(kFinNT), fin_lds, s, c, d);
+        hipLaunchKernelGGL((k_finish<DT, HASV, 0>), dim3(fin_grid), dim3(kFinNT), fin_lds, s, c, d);
+      else if (g_opt.finish_algo == 1)
+        hipLaunchKernelGGL((k_finish<DT, HASV, 1>), dim3(fin_grid), dim3(kFinNT), fin_lds, s, c, d);
+      else if (g_opt.finish_algo == 2)
+        hipLaunchKernelGGL((k_finish<DT, HASV, 2>), dim3(fin_grid), dim3(kFinNT), fin_lds, s, c, d);
       else
-        hipLaunchKernelGGL((k_finish<DT, HASV, false>), dim3(fin_grid), dim3(kFinNT), fin_lds, s, c, d);
+        hipLaunchKernelGGL((k_finish<DT, HASV, 3>), dim3(fin_grid), dim3(kFinNT), fin_lds, s, c, d);
       HIPCHK(hipGetLastError());
     }
     HIPCHK(hipMemcpyAsync(w.h_lvl, w.lvl, sizeof(LevelCtl) * (size_t)(d + 1), hipMemcpyDeviceToHost, s));
@@ -443,7 +451,7 @@ int tsqs_set_option(int key, int64_t v) {
     case TSQS_OPT_TIMING: g_opt.timing = v ? 1 : 0; return TSQS_OK;
     case TSQS_OPT_PART_GRID: if (v < 0 || v > 65536) return TSQS_EINVAL; g_opt.part_grid = v; return TSQS_OK;
     case TSQS_OPT_FINISH_GRID: if (v < 0 || v > 65536) return TSQS_EINVAL; g_opt.finish_grid = v; return TSQS_OK;
-    case TSQS_OPT_FINISH_ALGO: if (v < 0 || v > 1) return TSQS_EINVAL; g_opt.finish_algo = v; return TSQS_OK;
+    case TSQS_OPT_FINISH_ALGO: if (v < 0 || v > 3) return TSQS_EINVAL; g_opt.finish_algo = v; return TSQS_OK;
     default: return TSQS_EUNSUPPORTED;
   }
 }
@@ -571,7 +579,7 @@ int tsqs_autotune(int dt, int with_payload, size_t n, const uint64_t *h_offsets,
   for (int64_t v : {31, 63}) try_value(&Options::samples, v);
   for (int64_t m : {2, 4, 8}) try_value(&Options::part_grid, m * cus);
   for (int64_t m : {2, 4, 8}) try_value(&Options::finish_grid, m * cus);
-  for (int64_t a : {0, 1}) try_value(&Options::finish_algo, a);
+  for (int64_t a : {0, 1, 2, 3}) try_value(&Options::finish_algo, a);
   {
     std::lock_guard<std::mutex> lk(g_mu);
     g_opt = rc == TSQS_OK ? best : saved;

@@ -8,18 +8,20 @@
 // data-parallel passes over every active part, one or two recursion levels per
 // read and write of the keys:
 //
-//   k_partition  every chunk of every part at this level.  A chunk is an
-//                address-aligned window of 16384 keys (8192 / 4096 for wider
-//                elements) read with 16-byte loads by a 512-thread workgroup;
-//                compares on an order-preserving unsigned code; ranks from
-//                64-lane ballots + mbcnt; per-wave scalar cursors and one
-//                reservation per chunk.  One-level parts are split by their
-//                pivot with a left and a right cursor, and the keys of each side
-//                are counted against that side's pivot; two-level parts (whose
-//                class sizes that counting gave) get their < and > regions
-//                placed exactly and each region split by its own pivot with two
-//                cursors, so one pass does two levels (keys only).  The keys
-//                move to the other buffer (ping-pong K <-> S).
+//   k_partition  every chunk of every part at this level.  A chunk is a
+//                window of 16384 keys (8192 / 4096 for wider elements) from the
+//                128-byte line of the part's first key, read with 16-byte loads
+//                by a 512-thread workgroup (one-level passes: loaded straight
+//                into LDS while the previous chunk is processed); compares on an
+//                order-preserving unsigned code; ranks from 64-lane ballots +
+//                mbcnt; per-wave scalar cursors and one reservation per chunk.
+//                One-level parts are split by their pivot with a left and a
+//                right cursor, and the keys of each side are counted against
+//                that side's pivot; two-level parts (whose class sizes that
+//                counting gave) get their < and > regions placed exactly and
+//                each region split by its own pivot with two cursors, so one
+//                pass does two levels (keys only).  The keys move to the other
+//                buffer (ping-pong K <-> S).
 //   k_plan       one wave per part just partitioned: reads the final counters,
 //                writes the equal bands and the small children into fixed
 //                slots (no list atomics), and for large children picks the
@@ -27,11 +29,13 @@
 //                63 keys (the exact median by radix select once the depth limit
 //                is reached); the workgroup then reserves all its next-level
 //                parts with one atomic.
-//   k_finish     small parts are sorted in LDS / registers (a per-thread
-//                sorting network and merge-path merging, or a bitonic network):
-//                one wave per part up to 2048 keys, the 256-thread workgroup
-//                above; bands write the pivot value (equality means identical
-//                bits) and the staged payloads.
+//   k_finish     small parts are sorted in registers and LDS: a per-thread
+//                sorting network, bitonic merging across the lanes of a wave
+//                (lane exchanges, no LDS), then merge-path merging in LDS (or
+//                alternatives: a bitonic network throughout, merge-path merging
+//                from the per-thread runs on): one wave per part up to 2048
+//                keys, the 256-thread workgroup above; bands write the pivot
+//                value (equality means identical bits) and the staged payloads.
 //
 // Buffers: each part records whether its keys are in K or in S.
 #pragma once
@@ -1247,8 +1251,10 @@ template <> struct Rec<uint64_t, true> {
 };
 
 // Partner exchange inside a wave: the value of lane (lane ^ DD).  Distances
-// 1, 2, 4 and 8 use DPP moves (quad_perm, row_mirror, row_half_mirror: VALU
-// only, no LDS traffic); larger ones ds_bpermute with the byte address `addr`.
+// 1, 2, 4 and 8 use DPP moves (quad_perm, row_mirror, row_half_mirror), 16 and
+// 32 the gfx950 row swaps (v_permlane16_swap / v_permlane32_swap: each returns
+// the lower and the upper lane's value of the pair): VALU only, no LDS
+// traffic.  DD = 0: ds_bpermute with the byte address `addr`.
 template <int CTRL>
 __device__ inline uint32_t dpp32(uint32_t v) {
   return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, CTRL, 0xF, 0xF, false);
@@ -1259,8 +1265,35 @@ __device__ inline uint32_t xch(uint32_t v, int addr) {
   else if constexpr (DD == 2) return dpp32<0x4E>(v);            // quad_perm(2,3,0,1)
   else if constexpr (DD == 4) return dpp32<0x1B>(dpp32<0x141>(v));  // half_mirror, quad_perm(3,2,1,0)
   else if constexpr (DD == 8) return dpp32<0x141>(dpp32<0x140>(v)); // mirror, half_mirror
-  else return (uint32_t)__builtin_amdgcn_ds_bpermute(addr, (int)v);
+  else if constexpr (DD == 16) {
+    const auto r = __builtin_amdgcn_permlane16_swap(v, v, false, false);
+    return (__lane_id() & 16u) ? r[0] : r[1];
+  } else if constexpr (DD == 32) {
+    const auto r = __builtin_amdgcn_permlane32_swap(v, v, false, false);
+    return (__lane_id() & 32u) ? r[0] : r[1];
+  } else return (uint32_t)__builtin_amdgcn_ds_bpermute(addr, (int)v);
 }
+// The values of the lower and the upper lane of this lane's pair (lane and
+// lane ^ DD, DD = 16 or 32), from one row swap per 32-bit word.
+template <int DD>
+__device__ inline void swap_pair(uint32_t v, uint32_t &lo, uint32_t &hi) {
+  if constexpr (DD == 16) {
+    const auto r = __builtin_amdgcn_permlane16_swap(v, v, false, false);
+    lo = r[0]; hi = r[1];
+  } else {
+    const auto r = __builtin_amdgcn_permlane32_swap(v, v, false, false);
+    lo = r[0]; hi = r[1];
+  }
+}
+template <int DD>
+__device__ inline void swap_pair(uint64_t v, uint64_t &lo, uint64_t &hi) {
+  uint32_t l0, h0, l1, h1;
+  swap_pair<DD>((uint32_t)v, l0, h0);
+  swap_pair<DD>((uint32_t)(v >> 32), l1, h1);
+  lo = ((uint64_t)l1 << 32) | l0;
+  hi = ((uint64_t)h1 << 32) | h0;
+}
+
 template <int DD>
 __device__ inline uint64_t xch(uint64_t v, int addr) {
   const uint32_t lo = xch<DD>((uint32_t)v, addr), hi = xch<DD>((uint32_t)(v >> 32), addr);
@@ -1273,6 +1306,12 @@ __device__ inline R64 xch(R64 v, int addr) {
   r.i = xch<DD>(v.i, addr);
   r.pad = 0;
   return r;
+}
+template <int DD>
+__device__ inline void swap_pair(R64 v, R64 &lo, R64 &hi) {
+  swap_pair<DD>(v.k, lo.k, hi.k);
+  swap_pair<DD>(v.i, lo.i, hi.i);
+  lo.pad = 0; hi.pad = 0;
 }
 
 // keys per lane of the small-part sort, bounded by registers: 32 for 4-byte
@@ -1340,6 +1379,18 @@ template <typename R, int E, int DD>
 __device__ inline void cross_stage(typename R::T (&v)[E], bool take_min, int addr) {
   using T = typename R::T;
   constexpr int GB = E < 8 ? E : 8;
+  if constexpr (DD == 16 || DD == 32) {
+    // the row swap yields both values of the lane pair: no partner select
+#pragma unroll
+    for (int i = 0; i < E; i++) {
+      T lo, hi;
+      swap_pair<DD>(v[i], lo, hi);
+      const bool ol = R::less(hi, lo);
+      const T mn = R::sel(ol, hi, lo), mx = R::sel(ol, lo, hi);
+      v[i] = R::sel(take_min, mn, mx);
+    }
+    return;
+  }
 #pragma unroll
   for (int i0 = 0; i0 < E; i0 += GB) {
     T o[GB];
@@ -1407,6 +1458,8 @@ __device__ void sort_group(const Ctx &c, const FinItem &it,
           case 2: cross_stage<R, E, 2>(v, take_min, addr); break;
           case 4: cross_stage<R, E, 4>(v, take_min, addr); break;
           case 8: cross_stage<R, E, 8>(v, take_min, addr); break;
+          case 16: cross_stage<R, E, 16>(v, take_min, addr); break;
+          case 32: cross_stage<R, E, 32>(v, take_min, addr); break;
           default: cross_stage<R, E, 0>(v, take_min, addr); break;
         }
       } else {
@@ -1462,11 +1515,18 @@ __device__ void sort_group(const Ctx &c, const FinItem &it,
 // thread sorts E consecutive records in registers (a sorting network), then
 // runs of E, 2E, 4E, ... keys are merged pairwise in LDS.  For each merge a
 // thread owns E consecutive outputs: it finds where they start on the merge
-// path of its two runs (binary search along the cross diagonal) and produces
-// them in order, one LDS read per output.  Positions len..Lp-1 (Lp = len
-// rounded up to E) hold padding records, which sort last.
-template <int DT, bool HASV, int NT, int E>
-__device__ void merge_group(const Ctx &c, const FinItem &it,
+// path of its two runs (binary search along the cross diagonal), at A[ai] and
+// B[bi].  Positions len..Lp-1 (Lp = len rounded up to E) hold padding records,
+// which sort last.
+//   REG = false: the outputs are produced in order, one LDS read per output
+//   (each read waits for the previous comparison).
+//   REG = true: the outputs are the E smallest of A[ai, ai+E) and B[bi, bi+E)
+//   (padding past a run's end); the pairwise minima of A[ai+i] and
+//   B[bi+E-1-i] are exactly those E records, in bitonic order (Batcher's
+//   merge), and a half-cleaner network in registers sorts them: 2E independent
+//   LDS reads per thread and no dependent chain.
+template <int DT, bool HASV, int NT, int E, bool REG, bool HYB>
+__device__ __attribute__((always_inline)) void merge_group(const Ctx &c, const FinItem &it,
                             typename Rec<typename Codec<DT>::B, HASV>::T *lds, uint32_t t) {
   using B = typename Codec<DT>::B;
   using R = Rec<B, HASV>;
@@ -1498,7 +1558,45 @@ __device__ void merge_group(const Ctx &c, const FinItem &it,
   }
   group_sync<NT>();
   T v[E];
-  if (act) {
+  uint32_t r0 = E;   // sorted run length in LDS after the register phase
+  if constexpr (HYB) {
+    // runs of up to a wave's records are merged in registers by bitonic
+    // cross-lane stages (lane exchanges, no LDS), the last round ascending
+    // everywhere; records past Lp are padding
+#pragma unroll
+    for (int i = 0; i < E; i++) v[i] = act ? lds[lds_pad(t * E + i)] : R::pad();
+    sort_regs_asc<R, E>(v);
+    uint32_t kmax = E;
+    while (kmax < Lp && kmax < (uint32_t)kWave * E && kmax < (uint32_t)NT * E) kmax <<= 1;
+    if (kmax > (uint32_t)E) reverse_if<R, E>(v, (t & 1u) != 0);
+    // round m merges runs of E << (m - 1) into runs of E << m: partners at
+    // 2^(m-1), ..., 2, 1 lanes
+    static_for<1, 7>([&](auto M) __attribute__((always_inline)) {
+      constexpr int m = decltype(M)::value;
+      const uint32_t k = (uint32_t)E << m;
+      if (k <= kmax) {
+        const bool asc = k == kmax || ((t * E) & k) == 0;
+        // stage by stage: scheduling across stages only raises register pressure
+        if constexpr (m >= 6) cross_stage<R, E, 32>(v, ((t & 32u) == 0) == asc, 0);
+        __builtin_amdgcn_sched_barrier(0);
+        if constexpr (m >= 5) cross_stage<R, E, 16>(v, ((t & 16u) == 0) == asc, 0);
+        __builtin_amdgcn_sched_barrier(0);
+        if constexpr (m >= 4) cross_stage<R, E, 8>(v, ((t & 8u) == 0) == asc, 0);
+        __builtin_amdgcn_sched_barrier(0);
+        if constexpr (m >= 3) cross_stage<R, E, 4>(v, ((t & 4u) == 0) == asc, 0);
+        __builtin_amdgcn_sched_barrier(0);
+        if constexpr (m >= 2) cross_stage<R, E, 2>(v, ((t & 2u) == 0) == asc, 0);
+        __builtin_amdgcn_sched_barrier(0);
+        cross_stage<R, E, 1>(v, ((t & 1u) == 0) == asc, 0);
+        __builtin_amdgcn_sched_barrier(0);
+        merge_regs_asc<R, E>(v);
+        __builtin_amdgcn_sched_barrier(0);
+        reverse_if<R, E>(v, !asc);
+        __builtin_amdgcn_sched_barrier(0);
+      }
+    });
+    r0 = kmax;
+  } else if (act) {
 #pragma unroll
     for (int i = 0; i < E; i++) v[i] = lds[lds_pad(t * E + i)];
     sort_regs_asc<R, E>(v);
@@ -1508,7 +1606,7 @@ __device__ void merge_group(const Ctx &c, const FinItem &it,
 #pragma unroll
     for (int i = 0; i < E; i++) lds[lds_pad(t * E + i)] = v[i];
   }
-  for (uint32_t r = E; r < Lp; r <<= 1) {
+  for (uint32_t r = r0; r < Lp; r <<= 1) {
     group_sync<NT>();
     const uint32_t p0 = t * E;
     const uint32_t base = p0 & ~(2 * r - 1);
@@ -1526,20 +1624,32 @@ __device__ void merge_group(const Ctx &c, const FinItem &it,
         else hi = m;
       }
       uint32_t ai = lo, bi = diag - lo;
-      const uint32_t last = Lp - 1;
-      T a = lds[lds_pad(a0 + (ai < rA ? ai : rA - 1))];
-      T b = lds[lds_pad(b0 + (bi < rB ? bi : rB - 1))];
+      if constexpr (REG) {
 #pragma unroll
-      for (int i = 0; i < E; i++) {
-        const bool ta = bi >= rB || (ai < rA && !R::less(b, a));
-        v[i] = R::sel(ta, a, b);
-        ai += ta ? 1u : 0u;
-        bi += ta ? 0u : 1u;
-        uint32_t nx = ta ? a0 + ai : b0 + bi;
-        nx = nx < last ? nx : last;
-        const T y = lds[lds_pad(nx)];
-        a = R::sel(ta, y, a);
-        b = R::sel(ta, b, y);
+        for (int i = 0; i < E; i++) {
+          const uint32_t ia = ai + (uint32_t)i, ib = bi + (uint32_t)(E - 1 - i);
+          const T xa = lds[lds_pad(a0 + (ia < rA ? ia : rA - 1))];
+          const T xb = lds[lds_pad(b0 + (ib < rB ? ib : rB - 1))];
+          const T pa = R::sel(ia < rA, xa, R::pad()), pb = R::sel(ib < rB, xb, R::pad());
+          v[i] = R::sel(R::less(pb, pa), pb, pa);
+        }
+        merge_regs_asc<R, E>(v);
+      } else {
+        const uint32_t last = Lp - 1;
+        T a = lds[lds_pad(a0 + (ai < rA ? ai : rA - 1))];
+        T b = lds[lds_pad(b0 + (bi < rB ? bi : rB - 1))];
+#pragma unroll
+        for (int i = 0; i < E; i++) {
+          const bool ta = bi >= rB || (ai < rA && !R::less(b, a));
+          v[i] = R::sel(ta, a, b);
+          ai += ta ? 1u : 0u;
+          bi += ta ? 0u : 1u;
+          uint32_t nx = ta ? a0 + ai : b0 + bi;
+          nx = nx < last ? nx : last;
+          const T y = lds[lds_pad(nx)];
+          a = R::sel(ta, y, a);
+          b = R::sel(ta, b, y);
+        }
       }
     }
     group_sync<NT>();
@@ -1593,8 +1703,12 @@ __device__ inline void fill_band(const Ctx &c, const FinItem &it, uint32_t t, ui
 // (workgroup each), then wave-sized small parts and short bands (wave each).
 // Child slots are [0, 4 * parts of level d), band slots [0, 3 * parts); at the
 // roots' level also the root slots.
-template <int DT, bool HASV, bool BITONIC>
+// ALGO: 0 bitonic network, 1 merging with ordered outputs, 2 merging with
+// register merge networks, 3 as 1 after cross-lane bitonic merging of runs of
+// up to 16 threads (merge_group).
+template <int DT, bool HASV, int ALGO>
 __global__ __launch_bounds__(kFinNT) void k_finish(Ctx c, int d) {
+  constexpr bool BITONIC = ALGO == 0, REG = ALGO == 2, HYB = ALGO == 3;
   using B = typename Codec<DT>::B;
   using R = Rec<B, HASV>;
   using T = typename R::T;
@@ -1631,11 +1745,11 @@ __global__ __launch_bounds__(kFinNT) void k_finish(Ctx c, int d) {
         else if constexpr (ME >= 32) sort_group<DT, HASV, kFinNT, 32>(c, it, lds, tid);
       }
     } else {
-      if (P <= 1024) merge_group<DT, HASV, kFinNT, 4>(c, it, lds, tid);
-      else if (P <= 2048 || ME < 16) merge_group<DT, HASV, kFinNT, 8>(c, it, lds, tid);
+      if (P <= 1024) merge_group<DT, HASV, kFinNT, 4, REG, HYB>(c, it, lds, tid);
+      else if (P <= 2048 || ME < 16) merge_group<DT, HASV, kFinNT, 8, REG, HYB>(c, it, lds, tid);
       else if constexpr (ME >= 16) {
-        if (P <= 4096 || ME < 32) merge_group<DT, HASV, kFinNT, 16>(c, it, lds, tid);
-        else if constexpr (ME >= 32) merge_group<DT, HASV, kFinNT, 32>(c, it, lds, tid);
+        if (P <= 4096 || ME < 32) merge_group<DT, HASV, kFinNT, 16, REG, HYB>(c, it, lds, tid);
+        else if constexpr (ME >= 32) merge_group<DT, HASV, kFinNT, 32, REG, HYB>(c, it, lds, tid);
       }
     }
   }
@@ -1670,13 +1784,13 @@ __global__ __launch_bounds__(kFinNT) void k_finish(Ctx c, int d) {
         else if constexpr (ME >= 32) sort_group<DT, HASV, kWave, 32>(c, it, wl, lane);
       }
     } else {
-      if (P <= 64) merge_group<DT, HASV, kWave, 1>(c, it, wl, lane);
-      else if (P <= 128) merge_group<DT, HASV, kWave, 2>(c, it, wl, lane);
-      else if (P <= 256) merge_group<DT, HASV, kWave, 4>(c, it, wl, lane);
-      else if (P <= 512 || ME < 16) merge_group<DT, HASV, kWave, 8>(c, it, wl, lane);
+      if (P <= 64) merge_group<DT, HASV, kWave, 1, REG, HYB>(c, it, wl, lane);
+      else if (P <= 128) merge_group<DT, HASV, kWave, 2, REG, HYB>(c, it, wl, lane);
+      else if (P <= 256) merge_group<DT, HASV, kWave, 4, REG, HYB>(c, it, wl, lane);
+      else if (P <= 512 || ME < 16) merge_group<DT, HASV, kWave, 8, REG, HYB>(c, it, wl, lane);
       else if constexpr (ME >= 16) {
-        if (P <= 1024 || ME < 32) merge_group<DT, HASV, kWave, 16>(c, it, wl, lane);
-        else if constexpr (ME >= 32) merge_group<DT, HASV, kWave, 32>(c, it, wl, lane);
+        if (P <= 1024 || ME < 32) merge_group<DT, HASV, kWave, 16, REG, HYB>(c, it, wl, lane);
+        else if constexpr (ME >= 32) merge_group<DT, HASV, kWave, 32, REG, HYB>(c, it, wl, lane);
       }
     }
   }

@@ -326,9 +326,13 @@ int launch_tick(tsqs_queue *q, QGroup &G) {
   hipLaunchKernelGGL((k_plan<DT, false>), dim3(grid), dim3(kPlanNT), 0, G.s, c, d);
   const int fgrid = g_opt.finish_grid > 0 ? (int)g_opt.finish_grid : 8 * q->cus;
   if (g_opt.finish_algo == 0)
-    hipLaunchKernelGGL((k_finish<DT, false, true>), dim3(fgrid), dim3(kFinNT), G.geo.fin_lds, G.s, c, d);
+    hipLaunchKernelGGL((k_finish<DT, false, 0>), dim3(fgrid), dim3(kFinNT), G.geo.fin_lds, G.s, c, d);
+  else if (g_opt.finish_algo == 1)
+    hipLaunchKernelGGL((k_finish<DT, false, 1>), dim3(fgrid), dim3(kFinNT), G.geo.fin_lds, G.s, c, d);
+  else if (g_opt.finish_algo == 2)
+    hipLaunchKernelGGL((k_finish<DT, false, 2>), dim3(fgrid), dim3(kFinNT), G.geo.fin_lds, G.s, c, d);
   else
-    hipLaunchKernelGGL((k_finish<DT, false, false>), dim3(fgrid), dim3(kFinNT), G.geo.fin_lds, G.s, c, d);
+    hipLaunchKernelGGL((k_finish<DT, false, 3>), dim3(fgrid), dim3(kFinNT), G.geo.fin_lds, G.s, c, d);
   HIPCHK(hipGetLastError());
   HIPCHK(hipMemcpyAsync(&G.h_err[slot], c.err, sizeof(unsigned int), hipMemcpyDeviceToHost, G.s));
   HIPCHK(hipEventRecord(G.ev[slot], G.s));
@@ -352,9 +356,13 @@ int tick_dt(tsqs_queue *q, int dt) {
 template <int DT>
 int set_fin_lds(const FinGeom &geo) {
   if (geo.fin_lds > 65536) {
-    HIPCHK(hipFuncSetAttribute((const void *)k_finish<DT, false, false>,
+    HIPCHK(hipFuncSetAttribute((const void *)k_finish<DT, false, 0>,
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)geo.fin_lds));
-    HIPCHK(hipFuncSetAttribute((const void *)k_finish<DT, false, true>,
+    HIPCHK(hipFuncSetAttribute((const void *)k_finish<DT, false, 1>,
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)geo.fin_lds));
+    HIPCHK(hipFuncSetAttribute((const void *)k_finish<DT, false, 2>,
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)geo.fin_lds));
+    HIPCHK(hipFuncSetAttribute((const void *)k_finish<DT, false, 3>,
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)geo.fin_lds));
   }
   return TSQS_OK;

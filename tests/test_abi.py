@@ -96,8 +96,8 @@ def test_options(lib):
         assert lib.tsqs_set_option(tsqs.OPT_SAMPLES, 4) == -1          # must be odd
         assert lib.tsqs_set_option(tsqs.OPT_SAMPLES, 65) == -1
         assert lib.tsqs_set_option(tsqs.OPT_PIVOT_MODE, 2) == -1
-        assert lib.tsqs_set_option(tsqs.OPT_FINISH_ALGO, 2) == -1
-        assert tsqs.get_option(tsqs.OPT_FINISH_ALGO) == 1
+        assert lib.tsqs_set_option(tsqs.OPT_FINISH_ALGO, 4) == -1
+        assert tsqs.get_option(tsqs.OPT_FINISH_ALGO) == 3
         assert lib.tsqs_set_option(999, 1) == -4
         assert tsqs.get_option(999) == -(1 << 63)
     finally:

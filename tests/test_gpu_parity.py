@@ -22,7 +22,7 @@ def gpu():
     import paper_1505_00558_amd as tsqs
     tsqs.load_library()
     yield
-    tsqs.set_option(tsqs.OPT_FINISH_ALGO, 1)
+    tsqs.set_option(tsqs.OPT_FINISH_ALGO, 3)
     tsqs.set_option(tsqs.OPT_PART_GRID, 0)
     tsqs.set_option(tsqs.OPT_FINISH_GRID, 0)
     tsqs.set_option(tsqs.OPT_SMALL_MAX, 8192)
@@ -235,12 +235,15 @@ def test_full_size_int32_properties():
     torch.cuda.empty_cache()
 
 
+@pytest.mark.parametrize("algo", [0, 1, 2])
 @pytest.mark.parametrize("dtype", list(ti.DTYPES))
-def test_bitonic_finish_variant(oracle_mod, dtype):
-    """The alternative small-part sort (the bitonic network, TSQS_OPT_FINISH_ALGO
-    = 0): keys and payloads as for the default merge-path sort."""
+def test_finish_variants(oracle_mod, dtype, algo):
+    """The alternative small-part sorts (TSQS_OPT_FINISH_ALGO 0: the bitonic
+    network; 1: merge-path merging one output at a time; 2: merge-path merging
+    with register merge networks): keys and payloads as for the default
+    (cross-lane bitonic merging within a wave, then merge-path merging)."""
     import paper_1505_00558_amd as tsqs
-    tsqs.set_option(tsqs.OPT_FINISH_ALGO, 0)
+    tsqs.set_option(tsqs.OPT_FINISH_ALGO, algo)
     try:
         for fam, n in (("uniform", 300007), ("many_equals", 70001), ("organ_pipe", 8191),
                        ("reversed", 4097), ("uniform", 333), ("sorted", 65)):
