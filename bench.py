@@ -7,10 +7,13 @@ steps, organ pipe).  One step = for each family, restore the pristine keys
 keys sorted per second over the timed steps (restores included, inputs already
 resident in HBM).
 
-``roofline`` covers the dominant kernel, the partition pass: its algorithmic
-bytes (2 x keys partitioned x bytes per key, summed over every partition launch
-of the timed steps) over its summed duration, measured by the library with HIP
-events on the sorting stream (``TSQS_OPT_TIMING``), against the 8 TB/s HBM peak.
+``roofline`` covers the dominant kernel, the partition pass (the partition
+kernels of one level: a one-level kernel and, keys only, a two-level kernel that
+does two recursion levels per read and write of the keys; a "launch" below is
+one such pass): its algorithmic bytes (2 x keys partitioned x bytes per key,
+summed over every pass of the timed steps) over its summed duration, measured
+by the library with HIP events around each pass on the sorting stream
+(``TSQS_OPT_TIMING``), against the 8 TB/s HBM peak.
 ``traffic`` is the measured HBM bytes per launch from the committed rocprofv3
 counter summary when it was taken on the current kernel source, else null.
 
@@ -164,7 +167,7 @@ def run_single_arrays(args, workload, arrays, dtype, with_vals, config):
     roofline = {"bound": "hbm", "achieved": achieved, "peak": PEAK_GBS, "unit": "GB/s",
                 "frac": (achieved / PEAK_GBS) if achieved else None,
                 "traffic": measured_traffic(workload),
-                "kernel": "tsqs::k_partition",
+                "kernel": "tsqs::k_partition (one pass = the partition kernels of a level)",
                 "launches": launches,
                 "avg_launch_ms": part_ms / max(launches, 1),
                 "algorithmic_bytes_per_launch": part_bytes / max(launches, 1)}
