@@ -844,6 +844,14 @@ __global__ __launch_bounds__(kPartNT) void k_partition(Ctx c, int d) {
         if (tn < t1) prefetch(tn, pn);
       }
     };
+    // item it of every thread lies past the part's end (partial chunks; the
+    // same for the whole workgroup): skipped by a uniform branch, which saves a
+    // part smaller than a chunk most of the chunk's work
+    auto past_part = [&](auto full_tag, int it) __attribute__((always_inline)) -> bool {
+      constexpr bool FULL = decltype(full_tag)::value;
+      if constexpr (FULL) return false;
+      else return (uint32_t)((it / VEC) * NT * VEC) >= hi;
+    };
     // range mask of item it (partial chunks): the lanes whose key is in the part
     auto range_mask = [&](auto full_tag, int it, uint32_t relc) __attribute__((always_inline)) -> unsigned long long {
       constexpr bool FULL = decltype(full_tag)::value;
@@ -864,6 +872,7 @@ __global__ __launch_bounds__(kPartNT) void k_partition(Ctx c, int d) {
       uint32_t sL = 0, sG = 0, sO = 0, aLl = 0, aLe = 0, aGl = 0, aGe = 0;
       static_for<0, KPT>([&](auto I) __attribute__((always_inline)) {
         constexpr int it = decltype(I)::value;
+        if (past_part(full_tag, it)) return;
         const B u = Codec<DT>::enc(key[it]);
         const unsigned long long om = range_mask(full_tag, it, relc);
         const unsigned long long lm = wave_ballot(u < pvc) & om, gm = wave_ballot(u > pvc) & om;
@@ -946,6 +955,7 @@ __global__ __launch_bounds__(kPartNT) void k_partition(Ctx c, int d) {
       opaque_v(relc);
       static_for<0, KPT>([&](auto I) __attribute__((always_inline)) {
         constexpr int it = decltype(I)::value;
+        if (past_part(full_tag, it)) return;
         const B u = Codec<DT>::enc(key[it]);
         const unsigned long long om = range_mask(full_tag, it, relc);
         bool lt = u < pvc, gt = u > pvc;
@@ -987,6 +997,7 @@ __global__ __launch_bounds__(kPartNT) void k_partition(Ctx c, int d) {
       uint32_t n0 = 0, n1 = 0, n2 = 0, n3 = 0;
       static_for<0, KPT>([&](auto I) __attribute__((always_inline)) {
         constexpr int it = decltype(I)::value;
+        if (past_part(full_tag, it)) return;
         const B u = Codec<DT>::enc(key[it]);
         const unsigned long long om = range_mask(full_tag, it, relc);
         const bool lt0 = u < p0;
@@ -1054,6 +1065,7 @@ __global__ __launch_bounds__(kPartNT) void k_partition(Ctx c, int d) {
       opaque_v(relc);
       static_for<0, KPT>([&](auto I) __attribute__((always_inline)) {
         constexpr int it = decltype(I)::value;
+        if (past_part(full_tag, it)) return;
         const B u = Codec<DT>::enc(key[it]);
         const unsigned long long om = range_mask(full_tag, it, relc);
         const bool lt0 = u < p0, gt0 = u > p0;
