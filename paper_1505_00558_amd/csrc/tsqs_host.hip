@@ -443,7 +443,7 @@ void tsqs_free_storage(void) {
 int tsqs_set_option(int key, int64_t v) {
   std::lock_guard<std::mutex> lk(g_mu);
   switch (key) {
-    case TSQS_OPT_SMALL_MAX: if (v < 16 || v > 65536) return TSQS_EINVAL; g_opt.small_max = v; return TSQS_OK;
+    case TSQS_OPT_SMALL_MAX: if (v < 16 || v > 8192) return TSQS_EINVAL; g_opt.small_max = v; return TSQS_OK;
     case TSQS_OPT_SAMPLES: if (v < 3 || v > 63 || !(v & 1)) return TSQS_EINVAL; g_opt.samples = v; return TSQS_OK;
     case TSQS_OPT_DEPTH_FACTOR: if (v < 1 || v > 4) return TSQS_EINVAL; g_opt.depth_factor = v; return TSQS_OK;
     case TSQS_OPT_PIVOT_MODE: if (v < 0 || v > 1) return TSQS_EINVAL; g_opt.pivot_mode = v; return TSQS_OK;
