@@ -65,34 +65,53 @@ constexpr uint32_t kErrSegCap = 1, kErrFinCap = 2, kErrLevel = 4, kErrCount = 8;
 // ---- order-preserving codes (compares are done on these, never on floats) --
 
 template <int DT> struct Codec;
+// C / ckey / cpiv: what the partition pass compares.  Integers compare as
+// themselves (signed compares for signed keys, against the pivot decoded from
+// its code: the same order as the codes, without encoding every key); float32
+// keys compare as codes.
 template <> struct Codec<0> {  // int32: flip the sign bit
   using B = uint32_t;
+  using C = int32_t;
   __device__ static inline B enc(B x) { return x ^ 0x80000000u; }
   __device__ static inline B dec(B u) { return u ^ 0x80000000u; }
+  __device__ static inline C ckey(B x) { return (int32_t)x; }
+  __device__ static inline C cpiv(uint64_t code) { return (int32_t)((uint32_t)code ^ 0x80000000u); }
 };
 template <> struct Codec<1> {  // uint32
   using B = uint32_t;
+  using C = uint32_t;
   __device__ static inline B enc(B x) { return x; }
   __device__ static inline B dec(B u) { return u; }
+  __device__ static inline C ckey(B x) { return x; }
+  __device__ static inline C cpiv(uint64_t code) { return (uint32_t)code; }
 };
 template <> struct Codec<2> {  // int64
   using B = uint64_t;
+  using C = int64_t;
   __device__ static inline B enc(B x) { return x ^ 0x8000000000000000ull; }
   __device__ static inline B dec(B u) { return u ^ 0x8000000000000000ull; }
+  __device__ static inline C ckey(B x) { return (int64_t)x; }
+  __device__ static inline C cpiv(uint64_t code) { return (int64_t)(code ^ 0x8000000000000000ull); }
 };
 template <> struct Codec<3> {  // uint64
   using B = uint64_t;
+  using C = uint64_t;
   __device__ static inline B enc(B x) { return x; }
   __device__ static inline B dec(B u) { return u; }
+  __device__ static inline C ckey(B x) { return x; }
+  __device__ static inline C cpiv(uint64_t code) { return code; }
 };
 template <> struct Codec<4> {  // float32 bits, IEEE totalOrder: negatives reversed
   using B = uint32_t;
+  using C = uint32_t;
   __device__ static inline B enc(B x) {
     return x ^ ((uint32_t)((int32_t)x >> 31) | 0x80000000u);
   }
   __device__ static inline B dec(B u) {
     return u ^ (~(uint32_t)((int32_t)u >> 31) | 0x80000000u);
   }
+  __device__ static inline C ckey(B x) { return enc(x); }
+  __device__ static inline C cpiv(uint64_t code) { return (uint32_t)code; }
 };
 
 // Geometry of the partition pass per element type.
@@ -696,6 +715,7 @@ template <int DT, bool HASV, bool WIDE, bool TWO>
 __global__ __launch_bounds__(kPartNT) void k_partition(Ctx c, int d) {
   using Cfg = PartCfg<DT, HASV>;
   using B = typename Cfg::B;
+  using C = typename Codec<DT>::C;
   // keys staged through LDS (the next chunk's loads in flight during this one)
   constexpr bool STAGE = TWO ? kStageTwo : kStageOne;
   constexpr int NT = kPartNT, NW = kPartNW, VEC = Cfg::VEC, KPT = Cfg::KPT;
@@ -788,6 +808,9 @@ __global__ __launch_bounds__(kPartNT) void k_partition(Ctx c, int d) {
     }
   };
 
+  // look-ahead sums (below | equal << 32) of the current part, kept by wave 0
+  // (lane k: the k-th side / grandchild) until the part's last chunk here
+  unsigned long long look = 0;
   uint32_t t = advance(t0, pi);
   if constexpr (STAGE) {
     if (t < t1) prefetch(t, pi);
@@ -865,7 +888,7 @@ __global__ __launch_bounds__(kPartNT) void k_partition(Ctx c, int d) {
       B key[KPT];
       uint32_t val[HASV ? KPT : 1];
       load(full_tag, key, val);
-      B pvc = (B)s.piv[0], pl = (B)s.piv[1], pg = (B)s.piv[2];
+      C pvc = Codec<DT>::cpiv(s.piv[0]), pl = Codec<DT>::cpiv(s.piv[1]), pg = Codec<DT>::cpiv(s.piv[2]);
       uint32_t relc = rel0;
       // pass 1: this wave's class totals, and the look-ahead counts of each side
       // against its own pivot (scalar)
@@ -873,7 +896,7 @@ __global__ __launch_bounds__(kPartNT) void k_partition(Ctx c, int d) {
       static_for<0, KPT>([&](auto I) __attribute__((always_inline)) {
         constexpr int it = decltype(I)::value;
         if (past_part(full_tag, it)) return;
-        const B u = Codec<DT>::enc(key[it]);
+        const C u = Codec<DT>::ckey(key[it]);
         const unsigned long long om = range_mask(full_tag, it, relc);
         const unsigned long long lm = wave_ballot(u < pvc) & om, gm = wave_ballot(u > pvc) & om;
         sL += (uint32_t)__popcll(lm);
@@ -884,7 +907,7 @@ __global__ __launch_bounds__(kPartNT) void k_partition(Ctx c, int d) {
         opaque_s(sG);
         if constexpr (HASV && !FULL) opaque_s(sO);
         if constexpr (!HASV) {
-          const B pc = pick<B>(u < pvc, pl, pg);
+          const C pc = pick<C>(u < pvc, pl, pg);
           const unsigned long long m1 = wave_ballot(u < pc), e1 = wave_ballot(u == pc);
           aLl += (uint32_t)__popcll(lm & m1);
           aLe += (uint32_t)__popcll(lm & e1);
@@ -925,7 +948,7 @@ __global__ __launch_bounds__(kPartNT) void k_partition(Ctx c, int d) {
           if (lane < 2) {
             uint32_t tl = 0, te = 0;
             for (int q = 0; q < NW; q++) { tl += cnt[bf][2 + 2 * lane][q]; te += cnt[bf][3 + 2 * lane][q]; }
-            if (tl | te) atomicAdd(cp + kCtrLook + lane, ((unsigned long long)te << 32) | tl);
+            look += ((unsigned long long)te << 32) | tl;
           }
         }
         // < keys fill from the left cursor, > keys from the right cursor
@@ -956,7 +979,7 @@ __global__ __launch_bounds__(kPartNT) void k_partition(Ctx c, int d) {
       static_for<0, KPT>([&](auto I) __attribute__((always_inline)) {
         constexpr int it = decltype(I)::value;
         if (past_part(full_tag, it)) return;
-        const B u = Codec<DT>::enc(key[it]);
+        const C u = Codec<DT>::ckey(key[it]);
         const unsigned long long om = range_mask(full_tag, it, relc);
         bool lt = u < pvc, gt = u > pvc;
         if constexpr (!FULL) {
@@ -990,19 +1013,20 @@ __global__ __launch_bounds__(kPartNT) void k_partition(Ctx c, int d) {
       B key[KPT];
       uint32_t val[HASV ? KPT : 1];
       load(full_tag, key, val);
-      B p0 = (B)s.piv[0], pl = (B)s.piv[1], pg = (B)s.piv[2];
-      B pll = (B)s.piv[3], plg = (B)s.piv[4], pgl = (B)s.piv[5], pgg = (B)s.piv[6];
+      C p0 = Codec<DT>::cpiv(s.piv[0]), pl = Codec<DT>::cpiv(s.piv[1]), pg = Codec<DT>::cpiv(s.piv[2]);
+      C pll = Codec<DT>::cpiv(s.piv[3]), plg = Codec<DT>::cpiv(s.piv[4]);
+      C pgl = Codec<DT>::cpiv(s.piv[5]), pgg = Codec<DT>::cpiv(s.piv[6]);
       uint32_t relc = rel0;
       // pass 1: the four grandchild classes (<<, <>, ><, >>) (scalar)
       uint32_t n0 = 0, n1 = 0, n2 = 0, n3 = 0;
       static_for<0, KPT>([&](auto I) __attribute__((always_inline)) {
         constexpr int it = decltype(I)::value;
         if (past_part(full_tag, it)) return;
-        const B u = Codec<DT>::enc(key[it]);
+        const C u = Codec<DT>::ckey(key[it]);
         const unsigned long long om = range_mask(full_tag, it, relc);
         const bool lt0 = u < p0;
         const unsigned long long ma = wave_ballot(lt0) & om, mb = wave_ballot(u > p0) & om;
-        const B pc = pick<B>(lt0, pl, pg);
+        const C pc = pick<C>(lt0, pl, pg);
         const unsigned long long m1l = wave_ballot(u < pc), m1g = wave_ballot(u > pc);
         n0 += (uint32_t)__popcll(ma & m1l); n1 += (uint32_t)__popcll(ma & m1g);
         n2 += (uint32_t)__popcll(mb & m1l); n3 += (uint32_t)__popcll(mb & m1g);
@@ -1066,10 +1090,10 @@ __global__ __launch_bounds__(kPartNT) void k_partition(Ctx c, int d) {
       static_for<0, KPT>([&](auto I) __attribute__((always_inline)) {
         constexpr int it = decltype(I)::value;
         if (past_part(full_tag, it)) return;
-        const B u = Codec<DT>::enc(key[it]);
+        const C u = Codec<DT>::ckey(key[it]);
         const unsigned long long om = range_mask(full_tag, it, relc);
         const bool lt0 = u < p0, gt0 = u > p0;
-        const B pc = pick<B>(lt0, pl, pg);
+        const C pc = pick<C>(lt0, pl, pg);
         const bool lt1 = u < pc, gt1 = u > pc;
         const unsigned long long ma = wave_ballot(lt0) & om, mb = wave_ballot(gt0) & om;
         const unsigned long long m1l = wave_ballot(lt1), m1g = wave_ballot(gt1);
@@ -1080,7 +1104,7 @@ __global__ __launch_bounds__(kPartNT) void k_partition(Ctx c, int d) {
         r0 += (uint32_t)__popcll(q0); r1 += (uint32_t)__popcll(q1);
         r2 += (uint32_t)__popcll(q2); r3 += (uint32_t)__popcll(q3);
         const bool in = ((om >> lane) & 1ull) && (lt0 || gt0) && (lt1 || gt1);
-        const B pq = pick<B>(lt0, pick<B>(lt1, pll, plg), pick<B>(lt1, pgl, pgg));
+        const C pq = pick<C>(lt0, pick<C>(lt1, pll, plg), pick<C>(lt1, pgl, pgg));
         const uint32_t one = 1u << (pick<uint32_t>(gt0, 16u, 0u) + pick<uint32_t>(gt1, 8u, 0u));
         accL += (in && u < pq) ? one : 0u;
         accE += (in && u == pq) ? one : 0u;
@@ -1113,8 +1137,7 @@ __global__ __launch_bounds__(kPartNT) void k_partition(Ctx c, int d) {
         const int sh = (lane & 2) ? 16 : 0;
         tl = (tl >> sh) & 0xFFFFu;
         te = (te >> sh) & 0xFFFFu;
-        if (tl | te) atomicAdd(ctr + (size_t)pi * kCtrStride + kCtrLook + lane,
-                               ((unsigned long long)te << 32) | tl);
+        look += ((unsigned long long)te << 32) | tl;
       }
     };
 
@@ -1125,6 +1148,11 @@ __global__ __launch_bounds__(kPartNT) void k_partition(Ctx c, int d) {
     } else {
       if (full) body1(std::true_type{});
       else body1(std::false_type{});
+    }
+    // the look-ahead sums of a run of chunks of one part go out together
+    if (!HASV && w == 0 && (tn >= t1 || pn != pi)) {
+      if (lane < (TWO ? 4u : 2u) && look) atomicAdd(ctr + (size_t)pi * kCtrStride + kCtrLook + lane, look);
+      look = 0;
     }
     t = tn;
     pi = pn;
