@@ -275,13 +275,13 @@ int run_t(Workspace &w, void *keys, uint32_t *vals, const uint64_t *h_offs, size
       if (g_opt.timing) HIPCHK(hipEventRecord(w.ev[2 * d], s));
       if (idle) {
       } else if (wide) {
-        hipLaunchKernelGGL((k_partition<DT, HASV, true, false>), dim3(part_grid), dim3(kPartNT), 0, s, c, d);
+        hipLaunchKernelGGL((k_partition<DT, HASV, true, false>), dim3(part_grid), dim3(kPartNT1), 0, s, c, d);
         if (!HASV && d > 0)
-          hipLaunchKernelGGL((k_partition<DT, HASV, true, true>), dim3(part_grid), dim3(kPartNT), 0, s, c, d);
+          hipLaunchKernelGGL((k_partition<DT, HASV, true, true>), dim3(part_grid), dim3(kPartNT2), 0, s, c, d);
       } else {
-        hipLaunchKernelGGL((k_partition<DT, HASV, false, false>), dim3(part_grid), dim3(kPartNT), 0, s, c, d);
+        hipLaunchKernelGGL((k_partition<DT, HASV, false, false>), dim3(part_grid), dim3(kPartNT1), 0, s, c, d);
         if (!HASV && d > 0)
-          hipLaunchKernelGGL((k_partition<DT, HASV, false, true>), dim3(part_grid), dim3(kPartNT), 0, s, c, d);
+          hipLaunchKernelGGL((k_partition<DT, HASV, false, true>), dim3(part_grid), dim3(kPartNT2), 0, s, c, d);
       }
       if (g_opt.timing) HIPCHK(hipEventRecord(w.ev[2 * d + 1], s));
       if (!idle) hipLaunchKernelGGL((k_plan<DT, HASV>), dim3(plan_grid), dim3(kPlanNT), 0, s, c, d);

@@ -47,8 +47,10 @@
 namespace tsqs {
 
 constexpr int kWave = 64;
-constexpr int kPartNT = 512;
-constexpr int kPartNW = kPartNT / kWave;
+// partition workgroups: one-level passes 512 threads, two-level passes 256
+// (measured: the two-level pass, with more synchronisation per key, gains from
+// smaller workgroups, four per CU; the one-level pass from larger ones)
+constexpr int kPartNT1 = 512, kPartNT2 = 256;
 constexpr int kPlanNT = 256;
 constexpr int kPlanNW = kPlanNT / kWave;
 constexpr int kFinNT = 256;
@@ -114,16 +116,18 @@ template <> struct Codec<4> {  // float32 bits, IEEE totalOrder: negatives rever
   __device__ static inline C cpiv(uint64_t code) { return (uint32_t)code; }
 };
 
-// Geometry of the partition pass per element type.
-template <int DT, bool HASV> struct PartCfg {
+// Geometry of the partition pass per element type and pass type.
+template <int DT, bool HASV, bool TWO> struct PartCfg {
   using B = typename Codec<DT>::B;
+  static constexpr int NT = TWO ? kPartNT2 : kPartNT1;                  // threads
+  static constexpr int NW = NT / kWave;
   static constexpr int KB = (int)sizeof(B);
   static constexpr int VEC = 16 / KB;                                   // keys per 16-byte load
   static constexpr int KPT = KB == 4 ? (HASV ? 16 : 32) : (HASV ? 8 : 16);  // keys per thread
   static constexpr int NLOAD = KPT / VEC;
-  static constexpr uint64_t CH = (uint64_t)kPartNT * KPT;               // keys per chunk
+  static constexpr uint64_t CH = (uint64_t)NT * KPT;                    // keys per chunk
   static constexpr uint64_t LINE = 128 / KB;                            // keys per 128-byte line
-  static_assert(KPT % VEC == 0 && kPartNW <= kWave, "layout");
+  static_assert(KPT % VEC == 0 && NW <= kWave, "layout");
 };
 
 
@@ -416,14 +420,16 @@ __device__ inline uint32_t next_pow2(uint32_t x) {
 }
 
 // Number of chunks of a part [off, off+len) of a buffer: the part's chunks are
-// consecutive windows of CH keys from the 128-byte line holding its first key
-// (so a part of up to CH keys, less its offset in that line, is one chunk, and
-// every wave's loads cover whole lines).
+// consecutive windows of CH keys (of its pass type) from the 128-byte line
+// holding its first key (so a part of up to CH keys, less its offset in that
+// line, is one chunk, and every wave's loads cover whole lines).
 template <int DT, bool HASV>
-__device__ inline uint32_t part_chunks(const void *buf, uint64_t off, uint32_t len) {
-  using Cfg = PartCfg<DT, HASV>;
-  const uint64_t a0 = (uint64_t)(uintptr_t)buf / Cfg::KB + off;
-  return (uint32_t)((a0 % Cfg::LINE + len + Cfg::CH - 1) / Cfg::CH);
+__device__ inline uint32_t part_chunks(const void *buf, uint64_t off, uint32_t len, bool two) {
+  using C1 = PartCfg<DT, HASV, false>;
+  using C2 = PartCfg<DT, HASV, true>;
+  const uint64_t a0 = (uint64_t)(uintptr_t)buf / C1::KB + off;
+  const uint64_t ch = two ? C2::CH : C1::CH;
+  return (uint32_t)((a0 % C1::LINE + len + ch - 1) / ch);
 }
 
 
@@ -542,7 +548,7 @@ __device__ inline void child(const Ctx &c, uint32_t slot, uint64_t off, uint32_t
 #pragma unroll
     for (int k = 0; k < 7; k++) r.piv[k] = piv[k];
     r.len = len;
-    r.chunk_begin = part_chunks<DT, HASV>(in_s ? c.S : c.K, off, len);   // chunks, until flushed
+    r.chunk_begin = part_chunks<DT, HASV>(in_s ? c.S : c.K, off, len, two);   // chunks, until flushed
     r.depth = depth;
     r.dmax = dmax;
     r.req = req;
@@ -712,13 +718,13 @@ __device__ inline T *at(T *base, uint32_t i) {
 // kernel per type, so each has the registers, and the occupancy, its own work
 // needs).  WIDE: some part may span 4 GiB or more of keys or payloads.
 template <int DT, bool HASV, bool WIDE, bool TWO>
-__global__ __launch_bounds__(kPartNT) void k_partition(Ctx c, int d) {
-  using Cfg = PartCfg<DT, HASV>;
+__global__ __launch_bounds__(TWO ? kPartNT2 : kPartNT1) void k_partition(Ctx c, int d) {
+  using Cfg = PartCfg<DT, HASV, TWO>;
   using B = typename Cfg::B;
   using C = typename Codec<DT>::C;
   // keys staged through LDS (the next chunk's loads in flight during this one)
   constexpr bool STAGE = TWO ? kStageTwo : kStageOne;
-  constexpr int NT = kPartNT, NW = kPartNW, VEC = Cfg::VEC, KPT = Cfg::KPT;
+  constexpr int NT = Cfg::NT, NW = Cfg::NW, VEC = Cfg::VEC, KPT = Cfg::KPT;
   constexpr int NLOAD = Cfg::NLOAD, KB = Cfg::KB;
   constexpr uint64_t CH = Cfg::CH;
   // per-wave class counts: one-level [<, >, = (payloads) | look-ahead <<, <=, ><, >=],

@@ -317,11 +317,11 @@ int launch_tick(tsqs_queue *q, QGroup &G) {
                        dim3(kPlanNT), 0, G.s, c);
   }
   if ((uint64_t)G.max_n * G.kb > 0xFFFFFFFFull) {
-    hipLaunchKernelGGL((k_partition<DT, false, true, false>), dim3(grid), dim3(kPartNT), 0, G.s, c, d);
-    hipLaunchKernelGGL((k_partition<DT, false, true, true>), dim3(grid), dim3(kPartNT), 0, G.s, c, d);
+    hipLaunchKernelGGL((k_partition<DT, false, true, false>), dim3(grid), dim3(kPartNT1), 0, G.s, c, d);
+    hipLaunchKernelGGL((k_partition<DT, false, true, true>), dim3(grid), dim3(kPartNT2), 0, G.s, c, d);
   } else {
-    hipLaunchKernelGGL((k_partition<DT, false, false, false>), dim3(grid), dim3(kPartNT), 0, G.s, c, d);
-    hipLaunchKernelGGL((k_partition<DT, false, false, true>), dim3(grid), dim3(kPartNT), 0, G.s, c, d);
+    hipLaunchKernelGGL((k_partition<DT, false, false, false>), dim3(grid), dim3(kPartNT1), 0, G.s, c, d);
+    hipLaunchKernelGGL((k_partition<DT, false, false, true>), dim3(grid), dim3(kPartNT2), 0, G.s, c, d);
   }
   hipLaunchKernelGGL((k_plan<DT, false>), dim3(grid), dim3(kPlanNT), 0, G.s, c, d);
   const int fgrid = g_opt.finish_grid > 0 ? (int)g_opt.finish_grid : 8 * q->cus;
