@@ -1401,6 +1401,17 @@ __device__ inline void merge_regs_asc(typename R::T (&v)[E]) {
   }
 }
 
+// median of three 32-bit values (one v_med3_u32)
+__device__ inline uint32_t med3_u32(uint32_t a, uint32_t b, uint32_t c) {
+  return max(min(a, b), min(max(a, b), c));
+}
+
+// merge of a bitonic sequence held in the E registers, ascending or
+// descending (32-bit codes: each compare-exchange as two medians with the
+// direction's constants, so no reversal afterwards)
+template <typename R, int E>
+__device__ inline void merge_regs_dir(typename R::T (&v)[E], bool asc);
+
 template <typename R, int E>
 __device__ inline void reverse_if(typename R::T (&v)[E], bool cond) {
 #pragma unroll
@@ -1408,6 +1419,27 @@ __device__ inline void reverse_if(typename R::T (&v)[E], bool cond) {
     const typename R::T a = v[i], b = v[E - 1 - i];
     v[i] = R::sel(cond, b, a);
     v[E - 1 - i] = R::sel(cond, a, b);
+  }
+}
+
+template <typename R, int E>
+__device__ inline void merge_regs_dir(typename R::T (&v)[E], bool asc) {
+  using T = typename R::T;
+  if constexpr (std::is_same<T, uint32_t>::value) {
+    const uint32_t c0 = asc ? 0u : ~0u, c1 = ~c0;
+#pragma unroll
+    for (int j = E >> 1; j > 0; j >>= 1) {
+#pragma unroll
+      for (int i = 0; i < E; i++)
+        if ((i & j) == 0) {
+          const uint32_t a = v[i], b = v[i + j];
+          v[i] = med3_u32(a, b, c0);
+          v[i + j] = med3_u32(a, b, c1);
+        }
+    }
+  } else {
+    merge_regs_asc<R, E>(v);
+    reverse_if<R, E>(v, !asc);
   }
 }
 
@@ -1425,6 +1457,22 @@ template <typename R, int E, int DD>
 __device__ inline void cross_stage(typename R::T (&v)[E], bool take_min, int addr) {
   using T = typename R::T;
   constexpr int GB = E < 8 ? E : 8;
+  if constexpr (std::is_same<T, uint32_t>::value) {
+    // 32-bit codes: the median of (mine, partner's, 0) is the smaller of the
+    // two, of (mine, partner's, ~0) the larger: one instruction per record
+    const uint32_t cm = take_min ? 0u : ~0u;
+#pragma unroll
+    for (int i = 0; i < E; i++) {
+      if constexpr (DD == 16 || DD == 32) {
+        uint32_t lo, hi;
+        swap_pair<DD>(v[i], lo, hi);
+        v[i] = med3_u32(lo, hi, cm);
+      } else {
+        v[i] = med3_u32(v[i], xch<DD>(v[i], addr), cm);
+      }
+    }
+    return;
+  }
   if constexpr (DD == 16 || DD == 32) {
     // the row swap yields both values of the lane pair: no partner select
 #pragma unroll
@@ -1635,9 +1683,7 @@ __device__ __attribute__((always_inline)) void merge_group(const Ctx &c, const F
         __builtin_amdgcn_sched_barrier(0);
         cross_stage<R, E, 1>(v, ((t & 1u) == 0) == asc, 0);
         __builtin_amdgcn_sched_barrier(0);
-        merge_regs_asc<R, E>(v);
-        __builtin_amdgcn_sched_barrier(0);
-        reverse_if<R, E>(v, !asc);
+        merge_regs_dir<R, E>(v, asc);
         __builtin_amdgcn_sched_barrier(0);
       }
     });
