@@ -83,6 +83,24 @@ def cpu_baseline(families, n_sample: int, dtype="int32"):
                       "(%.1f s of CPU work)" % (len(families), n_sample, dtype, tot_s)}
 
 
+def cpu_baseline_samples(samples, note):
+    """The oracle (single-threaded) on given host arrays: (keys, payload or None)
+    each, sorted once; keys/s over all of them."""
+    import oracle
+    oracle.build(force=not os.path.exists(oracle.LIB_PATH))
+    tot_keys, tot_s = 0, 0.0
+    for k, v in samples:
+        t0 = time.perf_counter()
+        if v is None:
+            oracle.sort(k)
+        else:
+            oracle.sort_pairs(k, v)
+        tot_s += time.perf_counter() - t0
+        tot_keys += k.size
+    return {"value": tot_keys / tot_s, "unit": "keys/s", "cores": 1, "kind": "oracle",
+            "sample": "%s, one single-threaded oracle sort each (%.1f s of CPU work)" % (note, tot_s)}
+
+
 def to_dev(a):
     import torch
     sig = {4: np.int32, 8: np.int64}[a.dtype.itemsize] if a.dtype != np.float32 else np.float32
@@ -226,7 +244,15 @@ def workload_pairs64(args):
               ti.distinct10_u64(ti.seed_for(3, 1), n)]
     config = {"workload": "2^27 uint64 keys + uint32 payload (index): uniform and 10%-distinct",
               "n": n, "families": ["uniform", "distinct10"], "key": "uint64", "payload": "uint32"}
-    return run_single_arrays(args, "pairs64", arrays, "uint64", True, config)
+    out = run_single_arrays(args, "pairs64", arrays, "uint64", True, config)
+    if not args.no_cpu_baseline:
+        m = 1 << (args.cpu_log2n - 2)
+        idx = np.arange(m, dtype=np.uint32)
+        out["cpu_baseline"] = cpu_baseline_samples(
+            [(ti.family("uniform", m, "uint64", seed=ti.seed_for(3, 0)), idx.copy()),
+             (ti.distinct10_u64(ti.seed_for(3, 1), m), idx.copy())],
+            "uniform and 10%%-distinct, %d uint64 keys + uint32 payload each" % m)
+    return out
 
 
 def workload_float32(args):
@@ -235,7 +261,13 @@ def workload_float32(args):
     arrays = [ti.special_float32(ti.seed_for(3, 2), n)]
     config = {"workload": "2^27 float32 N(0,1) keys with 0.1% each of -0.0, +0.0, +inf, -inf, NaN",
               "n": n, "families": ["normal_specials"], "key": "float32", "payload": None}
-    return run_single_arrays(args, "float32", arrays, "float32", False, config)
+    out = run_single_arrays(args, "float32", arrays, "float32", False, config)
+    if not args.no_cpu_baseline:
+        m = 1 << (args.cpu_log2n - 1)
+        out["cpu_baseline"] = cpu_baseline_samples(
+            [(ti.special_float32(ti.seed_for(3, 2), m), None)],
+            "%d float32 N(0,1) keys with the same specials" % m)
+    return out
 
 
 def device_sorted_check(keys, offs) -> bool:
