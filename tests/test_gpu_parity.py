@@ -243,6 +243,7 @@ def test_finish_variants(oracle_mod, dtype, algo):
     with register merge networks): keys and payloads as for the default
     (cross-lane bitonic merging within a wave, then merge-path merging)."""
     import paper_1505_00558_amd as tsqs
+    before = tsqs.get_option(tsqs.OPT_FINISH_ALGO)
     tsqs.set_option(tsqs.OPT_FINISH_ALGO, algo)
     try:
         for fam, n in (("uniform", 300007), ("many_equals", 70001), ("organ_pipe", 8191),
@@ -253,7 +254,7 @@ def test_finish_variants(oracle_mod, dtype, algo):
             gk, gv = gpu_sort_pairs(k, v)
             assert same_bits(gk, oracle_mod.sort(k)) and payload_valid(k, gk, gv), (fam, n)
     finally:
-        tsqs.set_option(tsqs.OPT_FINISH_ALGO, 1)
+        tsqs.set_option(tsqs.OPT_FINISH_ALGO, before)
 
 
 def test_autotune_chooses_valid_options_and_sorts(oracle_mod):
