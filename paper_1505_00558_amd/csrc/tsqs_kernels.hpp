@@ -9,12 +9,14 @@
 // read and write of the keys:
 //
 //   k_partition  every chunk of every part at this level.  A chunk is a
-//                window of 16384 keys (8192 / 4096 for wider elements) from the
-//                128-byte line of the part's first key, read with 16-byte loads
-//                by a 512-thread workgroup (one-level passes: loaded straight
-//                into LDS while the previous chunk is processed); compares on an
-//                order-preserving unsigned code; ranks from 64-lane ballots +
-//                mbcnt; per-wave scalar cursors and one reservation per chunk.
+//                window of 32 keys per thread (16 / 8 for wider elements) from
+//                the 128-byte line of the part's first key, read with 16-byte
+//                loads by a 512-thread workgroup for one-level passes (loaded
+//                straight into LDS while the previous chunk is processed) and a
+//                256-thread one for two-level passes; integer keys compared as
+//                themselves, float32 keys as order-preserving codes; ranks from
+//                64-lane ballots + mbcnt; per-wave scalar cursors and one
+//                reservation per chunk.
 //                One-level parts are split by their pivot with a left and a
 //                right cursor, and the keys of each side are counted against
 //                that side's pivot; two-level parts (whose class sizes that
