@@ -262,11 +262,11 @@ int run_t(Workspace &w, void *keys, uint32_t *vals, const uint64_t *h_offs, size
   // 32-bit byte offsets within a part suffice unless a part reaches 4 GiB
   const bool wide = (uint64_t)max_root * sizeof(typename Codec<DT>::B) > 0xFFFFFFFFull;
   const uint32_t lv = ceil_log2((max_root + small_max - 1) / small_max);
-  // every root small: level 0 has no parts, only its finish work.  Without
-  // payloads the first pass is one level and the rest two levels each.
+  // every root small: level 0 has no parts, only its finish work.  The first
+  // pass is one level and the rest two levels each (with payloads too).
   const bool roots_small = max_root <= small_max;
   const uint32_t lv_all = lv + (lv + 4) / 5 + 2;
-  uint32_t expected = roots_small ? 1u : (HASV ? lv_all : 2 + lv_all / 2);
+  uint32_t expected = roots_small ? 1u : 2 + lv_all / 2;
   int d = 0, target = (int)expected;
   if (target > kMaxLevels - 1) target = kMaxLevels - 1;
   for (;;) {
@@ -276,11 +276,11 @@ int run_t(Workspace &w, void *keys, uint32_t *vals, const uint64_t *h_offs, size
       if (idle) {
       } else if (wide) {
         hipLaunchKernelGGL((k_partition<DT, HASV, true, false>), dim3(part_grid), dim3(kPartNT1), 0, s, c, d);
-        if (!HASV && d > 0)
+        if (d > 0)
           hipLaunchKernelGGL((k_partition<DT, HASV, true, true>), dim3(part_grid), dim3(kPartNT2), 0, s, c, d);
       } else {
         hipLaunchKernelGGL((k_partition<DT, HASV, false, false>), dim3(part_grid), dim3(kPartNT1), 0, s, c, d);
-        if (!HASV && d > 0)
+        if (d > 0)
           hipLaunchKernelGGL((k_partition<DT, HASV, false, true>), dim3(part_grid), dim3(kPartNT2), 0, s, c, d);
       }
       if (g_opt.timing) HIPCHK(hipEventRecord(w.ev[2 * d + 1], s));

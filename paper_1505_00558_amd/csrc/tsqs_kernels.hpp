@@ -22,8 +22,9 @@
 //                that side's pivot; two-level parts (whose class sizes that
 //                counting gave) get their < and > regions placed exactly and
 //                each region split by its own pivot with two cursors, so one
-//                pass does two levels (keys only).  The keys move to the other
-//                buffer (ping-pong K <-> S).
+//                pass does two levels (with payloads, the payloads of the
+//                three bands' keys are staged for the band fills).  The keys
+//                move to the other buffer (ping-pong K <-> S).
 //   k_plan       one wave per part just partitioned: reads the final counters,
 //                writes the equal bands and the small children into fixed
 //                slots (no list atomics), and for large children picks the
@@ -163,10 +164,11 @@ struct Seg {
 
 // Counters of a part (kCtrStride words, one 128-byte line): [0] left | right
 // cursor (one-level: < | >; two-level: << | <>), [1] keys equal to piv[0]
-// (staged payloads), [2] two-level: >< | >> cursors, [4..7] look-ahead counts
+// (staged payloads), [2] two-level: >< | >> cursors, [3] two-level: keys equal
+// to piv[1] | to piv[2] (staged payloads), [4..7] look-ahead counts
 // (below | equal << 32): one-level [4] < side vs piv[1], [5] > side vs piv[2];
 // two-level [4..7] the four grandchildren vs piv[3..6].
-constexpr int kCtrA = 0, kCtrE = 1, kCtrB = 2, kCtrLook = 4;
+constexpr int kCtrA = 0, kCtrE = 1, kCtrB = 2, kCtrE12 = 3, kCtrLook = 4;
 
 struct FinItem {             // work of the finish kernel (len 0 = empty slot)
   uint64_t off;              // small part: first key; band: first band slot
@@ -532,8 +534,8 @@ __device__ inline void child(const Ctx &c, uint32_t slot, uint64_t off, uint32_t
   if (S > len) S = (len & 1) ? len : len - 1;
   const bool exact = c.pivot_mode == 1 || depth >= dmax;
   const bool fits = (uint64_t)nlt + neq <= len;
-  if (!HASV && own_known && !fits && lane == 0) atomicOr(c.err, kErrCount);
-  const bool two = !HASV && own_known && !exact && fits;
+  if (own_known && !fits && lane == 0) atomicOr(c.err, kErrCount);
+  const bool two = own_known && !exact && fits;
   B p0 = (B)own;
   if (exact) {
     const uint32_t k = (c.pivot_mode == 1 && depth < dmax) ? 0u : len / 2;
@@ -600,6 +602,7 @@ __device__ inline void flush_parts(const Ctx &c, int lvl_next, PendLds &pend) {
       cp[kCtrA] = 0ull;
       cp[kCtrE] = 0ull;
       cp[kCtrB] = 0ull;
+      cp[kCtrE12] = 0ull;
 #pragma unroll
       for (int k = 0; k < 4; k++) cp[kCtrLook + k] = 0ull;
       cb += nch;
@@ -716,7 +719,7 @@ __device__ inline T *at(T *base, uint32_t i) {
 }
 
 // One partition level: every chunk of every part of level d whose pass type is
-// TWO (two-level parts: keys only); the parts of the other type are skipped (a
+// TWO (two-level parts); the parts of the other type are skipped (a
 // kernel per type, so each has the registers, and the occupancy, its own work
 // needs).  WIDE: some part may span 4 GiB or more of keys or payloads.
 template <int DT, bool HASV, bool WIDE, bool TWO>
@@ -729,9 +732,10 @@ __global__ __launch_bounds__(TWO ? kPartNT2 : kPartNT1) void k_partition(Ctx c, 
   constexpr int NT = Cfg::NT, NW = Cfg::NW, VEC = Cfg::VEC, KPT = Cfg::KPT;
   constexpr int NLOAD = Cfg::NLOAD, KB = Cfg::KB;
   constexpr uint64_t CH = Cfg::CH;
-  // per-wave class counts: one-level [<, >, = (payloads) | look-ahead <<, <=, ><, >=],
-  // two-level [<<, <>, ><, >>, then the look-ahead sums as packed 16-bit fields]
-  constexpr int NCLS = HASV ? 3 : 8;
+  // per-wave class counts: one-level [<, >, look-ahead <<, <=, ><, >=, = (payloads)],
+  // two-level [<<, <>, ><, >>, = of each pivot (payloads), then the look-ahead
+  // sums as packed 16-bit fields]
+  constexpr int NCLS = 8;
   __shared__ uint32_t cnt[2][NCLS][NW];
   __shared__ uint32_t sh_part;
   // the keys of the next chunk, loaded from HBM straight into LDS while the
@@ -914,25 +918,20 @@ __global__ __launch_bounds__(TWO ? kPartNT2 : kPartNT1) void k_partition(Ctx c, 
         opaque_s(sL);
         opaque_s(sG);
         if constexpr (HASV && !FULL) opaque_s(sO);
-        if constexpr (!HASV) {
-          const C pc = pick<C>(u < pvc, pl, pg);
-          const unsigned long long m1 = wave_ballot(u < pc), e1 = wave_ballot(u == pc);
-          aLl += (uint32_t)__popcll(lm & m1);
-          aLe += (uint32_t)__popcll(lm & e1);
-          aGl += (uint32_t)__popcll(gm & m1);
-          aGe += (uint32_t)__popcll(gm & e1);
-          opaque_s(aLl); opaque_s(aLe); opaque_s(aGl); opaque_s(aGe);
-        }
+        const C pc = pick<C>(u < pvc, pl, pg);
+        const unsigned long long m1 = wave_ballot(u < pc), e1 = wave_ballot(u == pc);
+        aLl += (uint32_t)__popcll(lm & m1);
+        aLe += (uint32_t)__popcll(lm & e1);
+        aGl += (uint32_t)__popcll(gm & m1);
+        aGe += (uint32_t)__popcll(gm & e1);
+        opaque_s(aLl); opaque_s(aLe); opaque_s(aGl); opaque_s(aGe);
       });
       if constexpr (HASV && FULL) sO = (uint32_t)(kWave * KPT);
       if (lane == 0) {
         cnt[bf][0][w] = sL;
         cnt[bf][1][w] = sG;
-        if constexpr (HASV) {
-          cnt[bf][2][w] = sO - sL - sG;
-        } else {
-          cnt[bf][2][w] = aLl; cnt[bf][3][w] = aLe; cnt[bf][4][w] = aGl; cnt[bf][5][w] = aGe;
-        }
+        cnt[bf][2][w] = aLl; cnt[bf][3][w] = aLe; cnt[bf][4][w] = aGl; cnt[bf][5][w] = aGe;
+        if constexpr (HASV) cnt[bf][6][w] = sO - sL - sG;
       }
       __syncthreads();
       // exclusive prefix over the waves of each class; one reservation per chunk
@@ -940,7 +939,7 @@ __global__ __launch_bounds__(TWO ? kPartNT2 : kPartNT1) void k_partition(Ctx c, 
         const uint32_t a = lane < (uint32_t)NW ? cnt[bf][0][lane] : 0u;
         const uint32_t b = lane < (uint32_t)NW ? cnt[bf][1][lane] : 0u;
         uint32_t e = 0;
-        if constexpr (HASV) e = lane < (uint32_t)NW ? cnt[bf][2][lane] : 0u;
+        if constexpr (HASV) e = lane < (uint32_t)NW ? cnt[bf][6][lane] : 0u;
         const uint32_t ia = wave_incl_scan(a), ib = wave_incl_scan(b);
         uint32_t ie = 0;
         if constexpr (HASV) ie = wave_incl_scan(e);
@@ -951,13 +950,11 @@ __global__ __launch_bounds__(TWO ? kPartNT2 : kPartNT1) void k_partition(Ctx c, 
           rb = atomicAdd(cp + kCtrA, ((unsigned long long)ib << 32) | ia);
           if constexpr (HASV) re = (uint32_t)atomicAdd(cp + kCtrE, (unsigned long long)ie);
         }
-        if constexpr (!HASV) {
-          // look-ahead totals: lane 0 the < side, lane 1 the > side
-          if (lane < 2) {
-            uint32_t tl = 0, te = 0;
-            for (int q = 0; q < NW; q++) { tl += cnt[bf][2 + 2 * lane][q]; te += cnt[bf][3 + 2 * lane][q]; }
-            look += ((unsigned long long)te << 32) | tl;
-          }
+        // look-ahead totals: lane 0 the < side, lane 1 the > side
+        if (lane < 2) {
+          uint32_t tl = 0, te = 0;
+          for (int q = 0; q < NW; q++) { tl += cnt[bf][2 + 2 * lane][q]; te += cnt[bf][3 + 2 * lane][q]; }
+          look += ((unsigned long long)te << 32) | tl;
         }
         // < keys fill from the left cursor, > keys from the right cursor
         // (the reserved block ends where the previous reservations began)
@@ -967,14 +964,14 @@ __global__ __launch_bounds__(TWO ? kPartNT2 : kPartNT1) void k_partition(Ctx c, 
         if (lane < (uint32_t)NW) {
           cnt[bf][0][lane] = (uint32_t)rb + ia - a;
           cnt[bf][1][lane] = s.len - (uint32_t)(rb >> 32) - totG + ib - b;
-          if constexpr (HASV) cnt[bf][2][lane] = re + ie - e;
+          if constexpr (HASV) cnt[bf][6][lane] = re + ie - e;
         }
       }
       __syncthreads();
       uint32_t runL = __builtin_amdgcn_readfirstlane(cnt[bf][0][w]);
       uint32_t runG = __builtin_amdgcn_readfirstlane(cnt[bf][1][w]);
       uint32_t runE = 0;
-      if constexpr (HASV) runE = __builtin_amdgcn_readfirstlane(cnt[bf][2][w]);
+      if constexpr (HASV) runE = __builtin_amdgcn_readfirstlane(cnt[bf][6][w]);
       uint32_t *VYp = VY + s.off;
       uint32_t *VEp = c.VE + s.off;
       // codes are recomputed from the keys (no second register copy)
@@ -1016,7 +1013,10 @@ __global__ __launch_bounds__(TWO ? kPartNT2 : kPartNT1) void k_partition(Ctx c, 
     };
 
     // ---- two-level pass: regions of piv[0] placed exactly, each split by its
-    // own pivot with two cursors (keys only) ----
+    // own pivot with two cursors; payloads move with their keys, and those of
+    // the keys equal to piv[0], piv[1], piv[2] are staged in VE at [nlt, ...),
+    // [0, ...) and [nlt + neq, ...) of the part (disjoint: the band of piv[1]
+    // lies inside the < region) for the band fills ----
     auto body2 = [&](auto full_tag) __attribute__((always_inline)) {
       B key[KPT];
       uint32_t val[HASV ? KPT : 1];
@@ -1025,8 +1025,9 @@ __global__ __launch_bounds__(TWO ? kPartNT2 : kPartNT1) void k_partition(Ctx c, 
       C pll = Codec<DT>::cpiv(s.piv[3]), plg = Codec<DT>::cpiv(s.piv[4]);
       C pgl = Codec<DT>::cpiv(s.piv[5]), pgg = Codec<DT>::cpiv(s.piv[6]);
       uint32_t relc = rel0;
-      // pass 1: the four grandchild classes (<<, <>, ><, >>) (scalar)
-      uint32_t n0 = 0, n1 = 0, n2 = 0, n3 = 0;
+      // pass 1: the four grandchild classes (<<, <>, ><, >>) and, with payloads,
+      // the three equal classes (= piv[0], = piv[1], = piv[2]) (scalar)
+      uint32_t n0 = 0, n1 = 0, n2 = 0, n3 = 0, z0 = 0, z1 = 0, z2 = 0;
       static_for<0, KPT>([&](auto I) __attribute__((always_inline)) {
         constexpr int it = decltype(I)::value;
         if (past_part(full_tag, it)) return;
@@ -1039,41 +1040,67 @@ __global__ __launch_bounds__(TWO ? kPartNT2 : kPartNT1) void k_partition(Ctx c, 
         n0 += (uint32_t)__popcll(ma & m1l); n1 += (uint32_t)__popcll(ma & m1g);
         n2 += (uint32_t)__popcll(mb & m1l); n3 += (uint32_t)__popcll(mb & m1g);
         opaque_s(n0); opaque_s(n1); opaque_s(n2); opaque_s(n3);
+        if constexpr (HASV) {
+          const unsigned long long mn = ~(m1l | m1g);
+          z0 += (uint32_t)__popcll(om & ~(ma | mb));
+          z1 += (uint32_t)__popcll(ma & mn);
+          z2 += (uint32_t)__popcll(mb & mn);
+          opaque_s(z0); opaque_s(z1); opaque_s(z2);
+        }
       });
       if (lane == 0) {
         cnt[bf][0][w] = n0; cnt[bf][1][w] = n1; cnt[bf][2][w] = n2; cnt[bf][3][w] = n3;
+        if constexpr (HASV) { cnt[bf][4][w] = z0; cnt[bf][5][w] = z1; cnt[bf][6][w] = z2; }
       }
       __syncthreads();
       if (w == 0) {
-        uint32_t x[4], ix[4];
+        constexpr int K = HASV ? 7 : 4;
+        uint32_t x[K], ix[K], tt[K];
 #pragma unroll
-        for (int k = 0; k < 4; k++) {
+        for (int k = 0; k < K; k++) {
           x[k] = lane < (uint32_t)NW ? cnt[bf][k][lane] : 0u;
           ix[k] = wave_incl_scan(x[k]);
+          tt[k] = __shfl(ix[k], NW - 1);
         }
         unsigned long long *cp = ctr + (size_t)pi * kCtrStride;
-        unsigned long long ra = 0, rb = 0;
+        unsigned long long ra = 0, rb = 0, re0 = 0, re12 = 0;
         if (lane == (uint32_t)NW - 1) {
           ra = atomicAdd(cp + kCtrA, ((unsigned long long)ix[1] << 32) | ix[0]);
           rb = atomicAdd(cp + kCtrB, ((unsigned long long)ix[3] << 32) | ix[2]);
+          if constexpr (HASV) {
+            re0 = atomicAdd(cp + kCtrE, (unsigned long long)ix[4]);
+            re12 = atomicAdd(cp + kCtrE12, ((unsigned long long)ix[6] << 32) | ix[5]);
+          }
         }
         ra = __shfl(ra, NW - 1);
         rb = __shfl(rb, NW - 1);
-        const uint32_t t0 = __shfl(ix[0], NW - 1), t2 = __shfl(ix[2], NW - 1);
-        const uint32_t t1 = __shfl(ix[1], NW - 1), t3 = __shfl(ix[3], NW - 1);
+        if constexpr (HASV) {
+          re0 = __shfl(re0, NW - 1);
+          re12 = __shfl(re12, NW - 1);
+        }
         const uint32_t g0 = s.nlt + s.neq;
         // the regions come from the previous pass's counts: a chunk that would
         // overfill one reports an internal error (its stores are also bounded)
-        if (lane == 0 && ((uint64_t)(uint32_t)ra + t0 + (uint32_t)(ra >> 32) + t1 > s.nlt ||
-                          (uint64_t)(uint32_t)rb + t2 + (uint32_t)(rb >> 32) + t3 + g0 > s.len))
-          atomicOr(c.err, kErrCount);
+        bool bad = (uint64_t)(uint32_t)ra + tt[0] + (uint32_t)(ra >> 32) + tt[1] > s.nlt ||
+                   (uint64_t)(uint32_t)rb + tt[2] + (uint32_t)(rb >> 32) + tt[3] + g0 > s.len;
+        if constexpr (HASV)
+          bad = bad || (uint64_t)(uint32_t)re0 + tt[4] > s.neq ||
+                (uint64_t)(uint32_t)re12 + tt[5] > s.nlt ||
+                (uint64_t)(uint32_t)(re12 >> 32) + tt[6] + g0 > s.len;
+        if (lane == 0 && bad) atomicOr(c.err, kErrCount);
         if (lane < (uint32_t)NW) {
           // << from the start of the < region, <> as blocks from its end, ><
           // from the start of the > region, >> as blocks from the part's end
           cnt[bf][0][lane] = (uint32_t)ra + ix[0] - x[0];
-          cnt[bf][1][lane] = s.nlt - (uint32_t)(ra >> 32) - t1 + ix[1] - x[1];
+          cnt[bf][1][lane] = s.nlt - (uint32_t)(ra >> 32) - tt[1] + ix[1] - x[1];
           cnt[bf][2][lane] = g0 + (uint32_t)rb + ix[2] - x[2];
-          cnt[bf][3][lane] = s.len - (uint32_t)(rb >> 32) - t3 + ix[3] - x[3];
+          cnt[bf][3][lane] = s.len - (uint32_t)(rb >> 32) - tt[3] + ix[3] - x[3];
+          if constexpr (HASV) {
+            // staging offsets (from the part's start) of the equal classes
+            cnt[bf][4][lane] = s.nlt + (uint32_t)re0 + ix[4] - x[4];
+            cnt[bf][5][lane] = (uint32_t)re12 + ix[5] - x[5];
+            cnt[bf][6][lane] = g0 + (uint32_t)(re12 >> 32) + ix[6] - x[6];
+          }
         }
       }
       __syncthreads();
@@ -1081,6 +1108,14 @@ __global__ __launch_bounds__(TWO ? kPartNT2 : kPartNT1) void k_partition(Ctx c, 
       uint32_t r1 = __builtin_amdgcn_readfirstlane(cnt[bf][1][w]);
       uint32_t r2 = __builtin_amdgcn_readfirstlane(cnt[bf][2][w]);
       uint32_t r3 = __builtin_amdgcn_readfirstlane(cnt[bf][3][w]);
+      uint32_t y0 = 0, y1 = 0, y2 = 0;
+      if constexpr (HASV) {
+        y0 = __builtin_amdgcn_readfirstlane(cnt[bf][4][w]);
+        y1 = __builtin_amdgcn_readfirstlane(cnt[bf][5][w]);
+        y2 = __builtin_amdgcn_readfirstlane(cnt[bf][6][w]);
+      }
+      uint32_t *VYp = VY + s.off;
+      uint32_t *VEp = c.VE + s.off;
       // codes are recomputed from the keys (no second register copy)
       static_for<0, KPT>([&](auto I) __attribute__((always_inline)) { opaque_v(key[decltype(I)::value]); });
       // pass 2: stores, and the look-ahead counts of the grandchildren against
@@ -1118,11 +1153,26 @@ __global__ __launch_bounds__(TWO ? kPartNT2 : kPartNT1) void k_partition(Ctx c, 
         accE += (in && u == pq) ? one : 0u;
         // counted before the store: the masks of this item end here
         opaque_v(accL); opaque_v(accE);
-        if (in && pos < s.len) *at<WIDE>(Yp, pos) = key[it];
+        if constexpr (HASV) {
+          // equal classes: payloads staged for the band fills
+          const unsigned long long mn = ~(m1l | m1g);
+          const unsigned long long e0 = om & ~(ma | mb), e1 = ma & mn, e2 = mb & mn;
+          uint32_t w0 = y0 + mbcnt(e0), w1 = y1 + mbcnt(e1), w2 = y2 + mbcnt(e2);
+          opaque_v(w0); opaque_v(w1); opaque_v(w2);
+          const uint32_t epos = pick<uint32_t>(lt0, w1, pick<uint32_t>(gt0, w2, w0));
+          y0 += (uint32_t)__popcll(e0); y1 += (uint32_t)__popcll(e1); y2 += (uint32_t)__popcll(e2);
+          if ((((e0 | e1 | e2) >> lane) & 1ull) && epos < s.len) *at<WIDE>(VEp, epos) = val[it];
+          opaque_s(y0); opaque_s(y1); opaque_s(y2);
+        }
+        if (in && pos < s.len) {
+          *at<WIDE>(Yp, pos) = key[it];
+          if constexpr (HASV) *at<WIDE>(VYp, pos) = val[it];
+        }
         opaque_s(r0); opaque_s(r1); opaque_s(r2); opaque_s(r3);
-        // four items at a time: enough overlap to hide the compare-to-mask
-        // latency, few enough masks live to stay in scalar registers
-        if constexpr (it % 4 == 3) __builtin_amdgcn_sched_barrier(0);
+        // four items at a time (keys only; with payloads one): enough overlap to
+        // hide the compare-to-mask latency, few enough masks live to stay in
+        // scalar registers
+        if constexpr (HASV || it % 4 == 3) __builtin_amdgcn_sched_barrier(0);
       });
       // widen to 16-bit fields (grandchildren 0 and 2 | 1 and 3; a chunk has at
       // most 2^16 - 1 keys) and sum over the wave
@@ -1150,7 +1200,7 @@ __global__ __launch_bounds__(TWO ? kPartNT2 : kPartNT1) void k_partition(Ctx c, 
     };
 
     const bool full = lo == 0u && hi == (uint32_t)CH;
-    if constexpr (TWO && !HASV) {
+    if constexpr (TWO) {
       if (full) body2(std::true_type{});
       else body2(std::false_type{});
     } else {
@@ -1158,7 +1208,7 @@ __global__ __launch_bounds__(TWO ? kPartNT2 : kPartNT1) void k_partition(Ctx c, 
       else body1(std::false_type{});
     }
     // the look-ahead sums of a run of chunks of one part go out together
-    if (!HASV && w == 0 && (tn >= t1 || pn != pi)) {
+    if (w == 0 && (tn >= t1 || pn != pi)) {
       if (lane < (TWO ? 4u : 2u) && look) atomicAdd(ctr + (size_t)pi * kCtrStride + kCtrLook + lane, look);
       look = 0;
     }
@@ -1210,9 +1260,10 @@ __global__ __launch_bounds__(kPlanNT) void k_plan(Ctx c, int d) {
           }
         } else {
         if (lane == 0) {
+          // payloads of each band were staged at [0, ...), [nlt, ...), [g0, ...)
           put_band(c, d, 3 * si + 0, s.off + nll, s.off, ele, s.piv[1], s.req);
-          put_band(c, d, 3 * si + 1, s.off + nlt, s.off, neq, s.piv[0], s.req);
-          put_band(c, d, 3 * si + 2, s.off + g0 + ngl, s.off, egt, s.piv[2], s.req);
+          put_band(c, d, 3 * si + 1, s.off + nlt, s.off + nlt, neq, s.piv[0], s.req);
+          put_band(c, d, 3 * si + 2, s.off + g0 + ngl, s.off + g0, egt, s.piv[2], s.req);
           band_keys += (unsigned long long)ele + neq + egt;
         }
         const uint64_t coff[4] = {s.off, s.off + nlt - nlg, s.off + g0, s.off + s.len - ngg};
