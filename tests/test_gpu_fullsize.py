@@ -103,3 +103,42 @@ def test_full_size_float32_specials():
     assert np.array_equal(got, np.partition(hc, r)[r])
     del t
     torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("fam", ["uniform", "many_equals"])
+def test_wide_int32_part(fam):
+    """A single array of more than 4 GiB of keys (the partition's 64-bit
+    addressing variant, and bands longer than a band chunk for many equals)."""
+    import paper_1505_00558_amd as tsqs
+    import torch
+    n = (1 << 30) + 4097
+    print("case: wide int32", fam, n, flush=True)
+    t = ti.device_family(fam, n, "int32", seed=ti.seed_for(2, fam) + 5)
+    ref = torch.sort(t).values
+    tsqs.sort(t)
+    torch.cuda.synchronize()
+    assert bool(torch.equal(t, ref))
+    del t, ref
+    torch.cuda.empty_cache()
+
+
+def test_wide_uint64_pairs():
+    """More than 4 GiB of uint64 keys with a uint32 payload in one array."""
+    import paper_1505_00558_amd as tsqs
+    import torch
+    n = (1 << 29) + 333
+    print("case: wide uint64 pairs", n, flush=True)
+    orig = ti.device_family("uniform", n, "uint64", seed=ti.seed_for(3, 0) + 9)
+    t = orig.clone()
+    v = torch.arange(n, dtype=torch.int32, device=t.device)
+    tsqs.sort_pairs(t, v, tsqs.UINT64)
+    torch.cuda.synchronize()
+    flip = torch.tensor(-(1 << 63), dtype=torch.int64, device=t.device)
+    ref = torch.sort(orig ^ flip).values ^ flip
+    assert bool(torch.equal(t, ref))
+    del ref
+    vv = v.to(torch.int64)
+    assert bool(torch.equal(torch.sort(vv).values, torch.arange(n, dtype=torch.int64, device=t.device)))
+    assert bool(torch.equal(orig[vv], t))
+    del orig, t, v, vv
+    torch.cuda.empty_cache()
