@@ -280,3 +280,32 @@ def test_autotune_chooses_valid_options_and_sorts(oracle_mod):
     finally:
         for k, v in before.items():
             tsqs.set_option(k, v)
+
+
+@pytest.mark.parametrize("dtype", ["int32", "uint64"])
+def test_batch_empty_and_one_key_arrays(oracle_mod, dtype):
+    """Batches whose arrays include empty and one-key arrays between larger
+    ones, keys only and with payloads: each array equals the oracle's sort and
+    payloads stay within their array."""
+    import paper_1505_00558_amd as tsqs
+    import torch
+    sizes = [0, 1, 0, 2, 5000, 0, 1, 70001, 0, 8193, 1]
+    arrs = [ti.family("uniform" if j % 2 else "many_equals", n, dtype, seed=300 + j)
+            for j, n in enumerate(sizes)]
+    keys = np.concatenate(arrs)
+    offs = np.cumsum([0] + sizes).astype(np.uint64)
+    for with_vals in (False, True):
+        print("case: batch with empty arrays", dtype, with_vals, flush=True)
+        t = to_dev(keys)
+        tv = to_dev(np.arange(keys.size, dtype=np.uint32)) if with_vals else None
+        tsqs.sort_batch(t, offs, tv, CODES[keys.dtype])
+        torch.cuda.synchronize()
+        got = from_dev(t, keys.dtype)
+        gv = from_dev(tv, np.uint32) if with_vals else None
+        for j, a in enumerate(arrs):
+            lo, hi = int(offs[j]), int(offs[j + 1])
+            assert same_bits(got[lo:hi], oracle_mod.sort(a)), (j, sizes[j])
+            if with_vals:
+                assert np.all((gv[lo:hi] >= lo) & (gv[lo:hi] < hi)), j
+        if with_vals:
+            assert payload_valid(keys, got, gv)
