@@ -605,7 +605,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU only; --gpus %d is not supported "
+        print("bench.py: the sort runs on one GPU; --gpus %d is not supported "
               "(run with --gpus 1)" % args.gpus, file=sys.stderr)
         sys.exit(2)
     import torch
