@@ -16,6 +16,9 @@ by the library with HIP events around each pass on the sorting stream
 (``TSQS_OPT_TIMING``), against the 8 TB/s HBM peak.
 ``traffic`` is the measured HBM bytes per launch from the committed rocprofv3
 counter summary when it was taken on the current kernel source, else null.
+``large_passes`` gives, over the passes that partition at least a quarter of the
+largest array's keys, the lowest per-pass fraction of the peak and the
+bytes-weighted mean.
 
 ``cpu_baseline`` times the CPU oracle (single-threaded Triple State QuickSort)
 on a bounded sample of the same workload.
@@ -165,6 +168,7 @@ def run_single_arrays(args, workload, arrays, dtype, with_vals, config):
     launches = 0
     sort_ms_total = 0.0
     levels = []
+    passes = []
     for i, e0, e1, st in acc:
         ms = e0.elapsed_time(e1)
         sort_ms_total += ms
@@ -176,6 +180,10 @@ def run_single_arrays(args, workload, arrays, dtype, with_vals, config):
         part_bytes += st["partition_bytes"]
         launches += st["partition_launches"]
         levels.append(st["levels"])
+        # per pass of every timed sort: (keys, ms), for the per-pass fractions
+        for k, t in zip(st["level_keys"], st["level_ms"]):
+            if k and t > 0:
+                passes.append((k, t))
     for name, d in per.items():
         ms = float(np.median(d["sort_ms"]))
         n = arrays[config["families"].index(name)].size if "families" in config else arrays[int(name)].size
@@ -189,6 +197,15 @@ def run_single_arrays(args, workload, arrays, dtype, with_vals, config):
                 "launches": launches,
                 "avg_launch_ms": part_ms / max(launches, 1),
                 "algorithmic_bytes_per_launch": part_bytes / max(launches, 1)}
+    # passes over at least a quarter of the largest array: their lowest fraction
+    # and their bytes-weighted mean (2 x keys x bytes per key each)
+    kb = {"int32": 4, "uint32": 4, "float32": 4, "int64": 8, "uint64": 8}.get(dtype, 4) + (4 if with_vals else 0)
+    big = max((a.size for a in arrays), default=0) // 4
+    fr = [(2 * k * kb / (t / 1e3) / 1e9 / PEAK_GBS, 2 * k * kb) for k, t in passes if k >= big]
+    if fr:
+        roofline["large_passes"] = {"min_keys": big, "count": len(fr),
+                                    "min_frac": min(f for f, _ in fr),
+                                    "weighted_frac": sum(f * b for f, b in fr) / sum(b for _, b in fr)}
     out = {
         "metric": METRIC,
         "value": total_keys / wall,
