@@ -75,12 +75,18 @@ enum {
   TSQS_OPT_TIMING = 6,       /* 1 = time every partition launch with HIP events */
   TSQS_OPT_PART_GRID = 7,    /* workgroups of the partition kernel (0 = auto) */
   TSQS_OPT_FINISH_GRID = 8,  /* workgroups of the finish kernel (0 = auto: 8 per CU) */
-  TSQS_OPT_FINISH_ALGO = 9   /* small parts: 0 = bitonic sorting network, 1 = per-thread
+  TSQS_OPT_FINISH_ALGO = 9,  /* small parts: 0 = bitonic sorting network, 1 = per-thread
                                 sorting network + merge-path merging in LDS, one output
                                 at a time, 2 = the same with each thread's outputs
                                 merged by a register network, 3 = runs of up to one
                                 wave merged by cross-lane bitonic stages in registers
                                 first, then as 1 (default) */
+  TSQS_OPT_PRESORT = 10      /* 1 (default) = before the first pass of a single array
+                                (tsqs_sort, tsqs_sort_pairs) that needs one, check
+                                whether it is already non-decreasing, or non-increasing
+                                (then reverse it in place, payloads too): such an array
+                                needs no pass (the sorted / reversed handlers, SIII.I);
+                                0 = off.  Batches and the serving queue do not check */
 };
 
 #define TSQS_MAX_LEVELS 192
@@ -101,7 +107,8 @@ typedef struct {
   double partition_ms;           /* sum of level_ms */
   uint64_t partition_bytes;      /* algorithmic bytes: 2 * keys * (key+payload bytes) */
   uint32_t partition_launches;   /* partition kernel launches (one per level with parts) */
-  uint32_t reserved;
+  uint32_t presorted;            /* 0; 1 = found non-decreasing, 2 = found non-increasing
+                                    and reversed (TSQS_OPT_PRESORT): no pass was needed */
 } tsqs_stats_t;
 
 /* Sort nmemb keys of type dt at device pointer d_keys, in place.

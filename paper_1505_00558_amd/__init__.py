@@ -21,6 +21,7 @@ INT32, UINT32, INT64, UINT64, FLOAT32 = 0, 1, 2, 3, 4
 OK, EINVAL, ENOMEM, EDEVICE, EUNSUPPORTED, EINTERNAL, EAGAIN = 0, -1, -2, -3, -4, -5, -6
 OPT_SMALL_MAX, OPT_SAMPLES, OPT_DEPTH_FACTOR, OPT_PIVOT_MODE = 1, 2, 3, 4
 OPT_SEED, OPT_TIMING, OPT_PART_GRID, OPT_FINISH_GRID, OPT_FINISH_ALGO = 5, 6, 7, 8, 9
+OPT_PRESORT = 10
 MAX_LEVELS = 192
 
 SYMBOLS = ["tsqs_sort", "tsqs_sort_pairs", "tsqs_sort_batch", "tsqs_autotune",
@@ -48,7 +49,7 @@ class Stats(ctypes.Structure):
         ("partition_ms", ctypes.c_double),
         ("partition_bytes", ctypes.c_uint64),
         ("partition_launches", ctypes.c_uint32),
-        ("reserved", ctypes.c_uint32),
+        ("presorted", ctypes.c_uint32),
     ]
 
     def as_dict(self) -> dict:
@@ -64,6 +65,7 @@ class Stats(ctypes.Structure):
             "partition_ms": float(self.partition_ms),
             "partition_bytes": int(self.partition_bytes),
             "partition_launches": int(self.partition_launches),
+            "presorted": int(self.presorted),
         }
 
 

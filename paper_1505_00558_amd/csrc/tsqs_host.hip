@@ -38,6 +38,7 @@ struct Options {
   int64_t part_grid = 0;
   int64_t finish_grid = 0;
   int64_t finish_algo = 3;
+  int64_t presort = 1;
 };
 
 struct Workspace {
@@ -213,6 +214,9 @@ int run_t(Workspace &w, void *keys, uint32_t *vals, const uint64_t *h_offs, size
   c.fin = w.fin; c.finw = w.finw; c.band = w.band; c.big = w.big; c.lvl = w.lvl;
   c.stats = w.stats;
   c.err = (unsigned int *)(w.stats + kStripes * kStatWords);
+  // the presortedness check of a single array that needs a pass
+  c.pre = (g_opt.presort && !h_offs && n > small_max)
+              ? (unsigned int *)(w.stats + kStripes * kStatWords + 8) : nullptr;
   c.roots = h_offs ? w.offs : nullptr;
   c.root_recs = nullptr;
   c.req_left = nullptr;
@@ -254,6 +258,12 @@ int run_t(Workspace &w, void *keys, uint32_t *vals, const uint64_t *h_offs, size
   if (init_grid < 1) init_grid = 1;
 
   hipLaunchKernelGGL(k_reset, dim3(1), dim3(256), 0, s, c);
+  if (c.pre) {
+    const uint64_t pre_chunks = (n + (uint64_t)kPreNT * kPreRows - 1) / ((uint64_t)kPreNT * kPreRows);
+    const int scan_grid = (int)(pre_chunks < (uint64_t)(8 * w.cus) ? pre_chunks : (uint64_t)(8 * w.cus));
+    hipLaunchKernelGGL((k_presort_scan<DT>), dim3(scan_grid), dim3(kPreNT), 0, s, c);
+    hipLaunchKernelGGL((k_presort_reverse<DT, HASV>), dim3(8 * w.cus), dim3(kPreNT), 0, s, c);
+  }
   hipLaunchKernelGGL((k_init<DT, HASV>), dim3(init_grid), dim3(kPlanNT), 0, s, c);
   HIPCHK(hipGetLastError());
 
@@ -317,6 +327,7 @@ int run_t(Workspace &w, void *keys, uint32_t *vals, const uint64_t *h_offs, size
     st.small_parts += sp[kStSmallParts];
     st.small_keys += sp[kStSmallKeys];
     st.band_keys += sp[kStBandKeys];
+    st.presorted += (uint32_t)sp[kStPresorted];
   }
   for (int i = 0; i < d; i++)
     if (w.h_lvl[i].packed >> 40) st.max_depth = (uint32_t)i;
@@ -452,6 +463,7 @@ int tsqs_set_option(int key, int64_t v) {
     case TSQS_OPT_PART_GRID: if (v < 0 || v > 65536) return TSQS_EINVAL; g_opt.part_grid = v; return TSQS_OK;
     case TSQS_OPT_FINISH_GRID: if (v < 0 || v > 65536) return TSQS_EINVAL; g_opt.finish_grid = v; return TSQS_OK;
     case TSQS_OPT_FINISH_ALGO: if (v < 0 || v > 3) return TSQS_EINVAL; g_opt.finish_algo = v; return TSQS_OK;
+    case TSQS_OPT_PRESORT: g_opt.presort = v ? 1 : 0; return TSQS_OK;
     default: return TSQS_EUNSUPPORTED;
   }
 }
@@ -468,6 +480,7 @@ int64_t tsqs_get_option(int key) {
     case TSQS_OPT_PART_GRID: return g_opt.part_grid;
     case TSQS_OPT_FINISH_GRID: return g_opt.finish_grid;
     case TSQS_OPT_FINISH_ALGO: return g_opt.finish_algo;
+    case TSQS_OPT_PRESORT: return g_opt.presort;
     default: return INT64_MIN;
   }
 }

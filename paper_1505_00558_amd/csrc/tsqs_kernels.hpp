@@ -64,7 +64,7 @@ constexpr unsigned long long kTileMask = (1ull << 40) - 1;
 constexpr int kCtrStride = 16;   // u64 words between part counters: one 128-byte line each
 constexpr int kStripes = 64;     // statistics counters are spread over this many lines
 constexpr int kStatWords = 16;
-enum { kStFallback = 0, kStSmallParts = 1, kStSmallKeys = 2, kStBandKeys = 3 };
+enum { kStFallback = 0, kStSmallParts = 1, kStSmallKeys = 2, kStBandKeys = 3, kStPresorted = 4 };
 constexpr uint32_t kErrSegCap = 1, kErrFinCap = 2, kErrLevel = 4, kErrCount = 8;
 
 // ---- order-preserving codes (compares are done on these, never on floats) --
@@ -203,6 +203,7 @@ struct Ctx {
   LevelCtl *lvl;
   unsigned long long *stats;         // kStripes x kStatWords
   unsigned int *err;
+  unsigned int *pre;                 // presortedness words of a single array, or null (check off)
   const uint64_t *roots;             // nroots+1 offsets, or null: one root [0, n)
   const RootRec *root_recs;          // or the roots one by one (then roots is ignored)
   unsigned long long *req_left;      // keys not yet final, per request (null: not tracked)
@@ -256,6 +257,13 @@ __device__ inline uint64_t shfl_u64(uint64_t v, int src) {
 template <typename U> __device__ inline U shfl_xor_any(U v, int m);
 template <> __device__ inline uint32_t shfl_xor_any<uint32_t>(uint32_t v, int m) { return shfl_xor_u32(v, m); }
 template <> __device__ inline uint64_t shfl_xor_any<uint64_t>(uint64_t v, int m) { return shfl_xor_u64(v, m); }
+// v of the next lane (lane 63 keeps its own)
+template <typename U> __device__ inline U shfl_any_down1(U v) {
+  const uint32_t l = lane_id();
+  const int src = (int)(l < 63u ? l + 1u : l);
+  if constexpr (sizeof(U) == 8) return (U)shfl_u64((uint64_t)v, src);
+  else return (U)shfl_u32((uint32_t)v, src);
+}
 
 // LDS ordering between the lanes of one wave (a wave-scope barrier).
 __device__ inline void wave_lds_sync() {
@@ -621,6 +629,7 @@ __global__ void k_reset(Ctx c) {
   }
   for (int i = threadIdx.x; i < kStripes * kStatWords; i += blockDim.x) c.stats[i] = 0ull;
   if (threadIdx.x == 0) *c.err = 0u;
+  if (c.pre && threadIdx.x < 2) c.pre[threadIdx.x] = 0u;
 }
 
 // Clears the counters of level `lvl` (a serving tick reuses level indices
@@ -628,6 +637,90 @@ __global__ void k_reset(Ctx c) {
 __global__ void k_level_clear(Ctx c, int lvl) {
   if (threadIdx.x == 0) {
     c.lvl[lvl].packed = 0ull; c.lvl[lvl].keys = 0ull; c.lvl[lvl].nbig = 0u;
+  }
+}
+
+// ---- presortedness check (SIII.I) -------------------------------------------------
+//
+// The paper guesses a possibly sorted or possibly reversed part from the order of
+// its pivot samples and then runs a handler that either confirms the guess or
+// falls back to the partition.  For a single array this is done before the first
+// pass: pre[0] is the guess from 64 evenly spaced keys (first and last included):
+// 1 = non-decreasing, 2 = non-increasing, 0 = neither; pre[1] is set when a scan
+// of every adjacent pair finds one against the guess.  A confirmed
+// non-increasing array is reversed in place (keys and payloads), and a confirmed
+// array then needs no pass at all.  Both words are cleared by k_reset.
+__device__ inline bool presorted(const Ctx &c) {
+  return c.pre != nullptr && c.pre[0] != 0u && c.pre[1] == 0u;
+}
+
+constexpr int kPreNT = 256;       // threads of the presortedness kernels
+constexpr int kPreRows = 16;      // keys per thread per chunk (one row = kPreNT keys)
+
+template <int DT>
+__global__ __launch_bounds__(kPreNT) void k_presort_scan(Ctx c) {
+  using B = typename Codec<DT>::B;
+  using Cm = typename Codec<DT>::C;
+  __shared__ uint32_t mode_s, stop_s;
+  const B *K = (const B *)c.K;
+  const uint64_t n = c.n;
+  const uint32_t lane = threadIdx.x & 63u;
+  if (threadIdx.x < kWave) {
+    // the guess: 64 evenly spaced keys in non-decreasing or non-increasing order
+    const uint64_t pos = (uint64_t)lane * (n - 1) / (kWave - 1);
+    const B x = K[pos];
+    const B z = shfl_any_down1<B>(x);         // x of the next lane (lane 63: itself)
+    const Cm a = Codec<DT>::ckey(x), b = Codec<DT>::ckey(z);
+    const bool up = wave_ballot(a > b) == 0ull, down = wave_ballot(a < b) == 0ull;
+    if (lane == 0) {
+      const uint32_t m = up ? 1u : (down ? 2u : 0u);
+      mode_s = m;
+      if (blockIdx.x == 0) c.pre[0] = m;
+    }
+  }
+  __syncthreads();
+  const uint32_t mode = mode_s;
+  if (mode == 0u) return;
+  const uint64_t chunk = (uint64_t)kPreNT * kPreRows;
+  const uint64_t nch = (n + chunk - 1) / chunk;
+  for (uint64_t ch = blockIdx.x; ch < nch; ch += gridDim.x) {
+    if (threadIdx.x == 0) stop_s = __hip_atomic_load(&c.pre[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __syncthreads();
+    const uint32_t stop = stop_s;
+    __syncthreads();
+    if (stop) return;
+    bool bad = false;
+#pragma unroll 4
+    for (int r = 0; r < kPreRows; r++) {
+      const uint64_t i = ch * chunk + (uint64_t)r * kPreNT + threadIdx.x;
+      const B x = i < n ? K[i] : B(0);
+      B nb = shfl_any_down1<B>(x);
+      if (lane == 63u) nb = i + 1 < n ? K[i + 1] : x;
+      if (i + 1 < n) {
+        const Cm a = Codec<DT>::ckey(x), b = Codec<DT>::ckey(nb);
+        bad |= mode == 1u ? a > b : a < b;
+      }
+    }
+    if (wave_ballot(bad) != 0ull && lane == 0) atomicOr(&c.pre[1], 1u);
+  }
+}
+
+// Reverses a confirmed non-increasing array (and its payloads) in place.
+template <int DT, bool HASV>
+__global__ __launch_bounds__(kPreNT) void k_presort_reverse(Ctx c) {
+  using B = typename Codec<DT>::B;
+  if (c.pre[0] != 2u || c.pre[1] != 0u) return;
+  B *K = (B *)c.K;
+  const uint64_t n = c.n, half = n / 2;
+  const uint64_t step = (uint64_t)gridDim.x * kPreNT;
+  for (uint64_t i = (uint64_t)blockIdx.x * kPreNT + threadIdx.x; i < half; i += step) {
+    const uint64_t j = n - 1 - i;
+    const B a = K[i], b = K[j];
+    K[i] = b; K[j] = a;
+    if (HASV) {
+      const uint32_t va = c.V[i], vb = c.V[j];
+      c.V[i] = vb; c.V[j] = va;
+    }
   }
 }
 
@@ -657,6 +750,13 @@ __global__ __launch_bounds__(kPlanNT) void k_init(Ctx c) {
       }
       uint32_t lg = 0;
       while (lg < 32 && (1ull << lg) < (unsigned long long)len) lg++;
+      if (presorted(c)) {
+        // already in order (or reversed into order): no pass and no finish work
+        if (lane_id() == 0) {
+          put_small(c, 4 * c.seg_cap + j, off, 0u, false, req);
+          stat_add(c, kStPresorted, (unsigned long long)c.pre[0]);
+        }
+      } else
       child<DT, HASV>(c, 4 * c.seg_cap + j, off, len, 0u, c.depth_factor * lg, req, false, false, 0ull,
                       0u, 0u, hist[wv], pend, wv, small_parts, small_keys);
     }

@@ -283,6 +283,7 @@ int launch_tick(tsqs_queue *q, QGroup &G) {
   c.fin = G.fin; c.finw = G.finw; c.band = G.band; c.big = G.big; c.lvl = G.lvl;
   c.stats = G.stats;
   c.err = (unsigned int *)(G.stats + kStripes * kStatWords);
+  c.pre = nullptr;
   c.roots = nullptr;
   c.root_recs = G.d_roots[slot];
   c.req_left = q->req_left;

@@ -98,6 +98,10 @@ def test_options(lib):
         assert lib.tsqs_set_option(tsqs.OPT_PIVOT_MODE, 2) == -1
         assert lib.tsqs_set_option(tsqs.OPT_FINISH_ALGO, 4) == -1
         assert tsqs.get_option(tsqs.OPT_FINISH_ALGO) == 3
+        assert tsqs.get_option(tsqs.OPT_PRESORT) == 1
+        assert lib.tsqs_set_option(tsqs.OPT_PRESORT, 0) == 0
+        assert tsqs.get_option(tsqs.OPT_PRESORT) == 0
+        assert lib.tsqs_set_option(tsqs.OPT_PRESORT, 1) == 0
         assert lib.tsqs_set_option(999, 1) == -4
         assert tsqs.get_option(999) == -(1 << 63)
     finally:

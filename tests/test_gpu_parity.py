@@ -28,6 +28,7 @@ def gpu():
     tsqs.set_option(tsqs.OPT_SMALL_MAX, 8192)
     tsqs.set_option(tsqs.OPT_SAMPLES, 63)
     tsqs.set_option(tsqs.OPT_PIVOT_MODE, 0)
+    tsqs.set_option(tsqs.OPT_PRESORT, 1)
 
 
 def test_config1_one_million_int32(oracle_mod):
@@ -42,7 +43,16 @@ def test_families_dtypes(oracle_mod, dtype, fam):
     n = (1 << 20) + 37
     print("case:", dtype, fam, n, flush=True)
     k = ti.family(fam, n, dtype, seed=ti.seed_for(2, fam) + 5)
-    assert same_bits(gpu_sort(k), oracle_mod.sort(k))
+    ref = oracle_mod.sort(k)
+    assert same_bits(gpu_sort(k), ref)
+    if fam in ("sorted", "reversed", "stair_steps"):
+        # found in order by the presortedness check: also through the passes
+        import paper_1505_00558_amd as tsqs
+        tsqs.set_option(tsqs.OPT_PRESORT, 0)
+        try:
+            assert same_bits(gpu_sort(k), ref)
+        finally:
+            tsqs.set_option(tsqs.OPT_PRESORT, 1)
 
 
 @pytest.mark.parametrize("dtype", list(ti.DTYPES))
@@ -146,11 +156,13 @@ def test_min_pivot_forces_depth_fallback(oracle_mod, fam):
     n = 60001
     k = ti.family(fam, n, "int32", seed=3)
     tsqs.set_option(tsqs.OPT_PIVOT_MODE, 1)
+    tsqs.set_option(tsqs.OPT_PRESORT, 0)     # a sorted array must take the passes here
     try:
         got = gpu_sort(k)
         st = tsqs.get_stats()
     finally:
         tsqs.set_option(tsqs.OPT_PIVOT_MODE, 0)
+        tsqs.set_option(tsqs.OPT_PRESORT, 1)
     assert same_bits(got, oracle_mod.sort(k))
     lg = int(np.ceil(np.log2(n)))
     if fam != "many_equals":

@@ -1,0 +1,162 @@
+"""GPU parity of the presortedness check (the sorted / reversed handlers of
+SIII.I, done once per single array before its first pass).
+
+Keys must be bit-identical to the oracle's output.  Which way the check
+decided is read from the call's statistics (presorted: 0 = partitioned as
+usual, 1 = found non-decreasing, 2 = found non-increasing and reversed): a
+single adjacent pair out of order anywhere (at a wave, chunk or array edge,
+or between two of the probe's sampled keys) must send the array to the
+partition passes, and the answer must be the oracle's either way.
+"""
+import numpy as np
+import pytest
+
+import tsqs_inputs as ti
+from gpu_util import gpu_sort, gpu_sort_pairs, payload_valid, same_bits
+
+pytestmark = pytest.mark.gpu
+
+N = (1 << 20) + 37          # a ragged last chunk (4096 keys per chunk)
+
+
+@pytest.fixture(scope="module", autouse=True)
+def gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1505_00558_amd as tsqs
+    tsqs.load_library()
+    yield
+    tsqs.set_option(tsqs.OPT_PRESORT, 1)
+
+
+def _check(oracle_mod, k, want):
+    import paper_1505_00558_amd as tsqs
+    got = gpu_sort(k)
+    st = tsqs.get_stats()
+    assert same_bits(got, oracle_mod.sort(k))
+    assert st["presorted"] == want
+    if want:
+        assert sum(st["level_keys"]) == 0 and st["small_keys"] == 0
+
+
+def _oracle_sorted(oracle_mod, fam, n, dtype, seed):
+    return oracle_mod.sort(ti.family(fam, n, dtype, seed=seed))
+
+
+@pytest.mark.parametrize("dtype", list(ti.DTYPES))
+def test_sorted_and_reversed(oracle_mod, dtype):
+    print("case: presort sorted/reversed", dtype, flush=True)
+    asc = _oracle_sorted(oracle_mod, "uniform", N, dtype, 11)
+    _check(oracle_mod, asc, 1)
+    _check(oracle_mod, np.ascontiguousarray(asc[::-1]), 2)
+
+
+@pytest.mark.parametrize("dtype", ["int32", "uint64", "float32"])
+def test_ties(oracle_mod, dtype):
+    """Runs of equal keys: non-decreasing / non-increasing, and all keys equal."""
+    print("case: presort ties", dtype, flush=True)
+    asc = _oracle_sorted(oracle_mod, "many_equals", N, dtype, 12)
+    _check(oracle_mod, asc, 1)
+    _check(oracle_mod, np.ascontiguousarray(asc[::-1]), 2)
+    _check(oracle_mod, np.full(N, asc[N // 2], dtype=asc.dtype), 1)
+
+
+def test_float32_specials_reversed(oracle_mod):
+    """NaNs of both signs, infinities, -0.0 and +0.0 under totalOrder, reversed."""
+    print("case: presort float32 specials", flush=True)
+    asc = oracle_mod.sort(ti.special_float32(13, N))
+    _check(oracle_mod, asc, 1)
+    _check(oracle_mod, np.ascontiguousarray(asc[::-1]), 2)
+
+
+# one adjacent pair out of order: first pair, a wave edge (lane 63 / 64), a chunk
+# edge (4095 / 4096), between two probe samples, the last pair
+BREAKS = [0, 63, 4095, N // 126, N // 2, N - 2]
+
+
+@pytest.mark.parametrize("where", BREAKS)
+@pytest.mark.parametrize("direction", ["ascending", "descending"])
+def test_one_pair_out_of_order(oracle_mod, where, direction):
+    print("case: presort one pair out of order", direction, where, flush=True)
+    k = (np.arange(N, dtype=np.int64) * 3 - 3 * (N // 2)).astype(np.int32)   # strictly increasing
+    if direction == "descending":
+        k = np.ascontiguousarray(k[::-1])
+    k = k.copy()
+    k[where], k[where + 1] = k[where + 1], k[where]
+    _check(oracle_mod, k, 0)
+
+
+def _order(k):
+    """1 if non-decreasing, 2 if non-increasing (and not constant), else 0."""
+    if np.all(k[1:] >= k[:-1]):
+        return 1
+    return 2 if np.all(k[1:] <= k[:-1]) else 0
+
+
+@pytest.mark.parametrize("fam", ti.FAMILIES)
+def test_families(oracle_mod, fam):
+    """Every input family: the check decides exactly as the input's order says
+    (nearly sorted: a probe that may pass and a scan that must fail)."""
+    print("case: presort family", fam, flush=True)
+    k = ti.family(fam, N, "int32", seed=15)
+    _check(oracle_mod, k, _order(k))
+
+
+@pytest.mark.parametrize("n", [8193, 8194, 65537])
+def test_small_edges(oracle_mod, n):
+    """The smallest arrays that get a pass (at most small_max keys never do)."""
+    print("case: presort small", n, flush=True)
+    asc = _oracle_sorted(oracle_mod, "uniform", n, "uint32", 16)
+    _check(oracle_mod, asc, 1)
+    _check(oracle_mod, np.ascontiguousarray(asc[::-1]), 2)
+
+
+@pytest.mark.parametrize("dtype", ["int32", "uint64"])
+def test_pairs(oracle_mod, dtype):
+    """Payloads: untouched for a sorted array, reversed with a reversed one."""
+    print("case: presort pairs", dtype, flush=True)
+    import paper_1505_00558_amd as tsqs
+    asc = np.unique(_oracle_sorted(oracle_mod, "uniform", N, dtype, 17))
+    n = asc.size
+    v = np.arange(n, dtype=np.uint32)
+    gk, gv = gpu_sort_pairs(asc, v)
+    assert tsqs.get_stats()["presorted"] == 1
+    assert same_bits(gk, asc) and np.array_equal(gv, v)
+    desc = np.ascontiguousarray(asc[::-1])
+    gk, gv = gpu_sort_pairs(desc, v)
+    assert tsqs.get_stats()["presorted"] == 2
+    assert same_bits(gk, asc) and np.array_equal(gv, v[::-1])
+    ties = np.ascontiguousarray(_oracle_sorted(oracle_mod, "many_equals", N, dtype, 18)[::-1])
+    v = np.arange(N, dtype=np.uint32)
+    gk, gv = gpu_sort_pairs(ties, v)
+    assert tsqs.get_stats()["presorted"] == 2
+    assert same_bits(gk, oracle_mod.sort(ties)) and payload_valid(ties, gk, gv)
+
+
+def test_option_off(oracle_mod):
+    """TSQS_OPT_PRESORT 0: sorted and reversed arrays take the partition passes."""
+    import paper_1505_00558_amd as tsqs
+    asc = _oracle_sorted(oracle_mod, "uniform", N, "int32", 19)
+    tsqs.set_option(tsqs.OPT_PRESORT, 0)
+    try:
+        for k in (asc, np.ascontiguousarray(asc[::-1])):
+            got = gpu_sort(k)
+            st = tsqs.get_stats()
+            assert same_bits(got, asc)
+            assert st["presorted"] == 0 and st["level_keys"][0] == k.size
+    finally:
+        tsqs.set_option(tsqs.OPT_PRESORT, 1)
+
+
+def test_batch_does_not_check(oracle_mod):
+    """Batches sort sorted arrays through the passes (the check is per single array)."""
+    import paper_1505_00558_amd as tsqs
+    import torch
+    asc = _oracle_sorted(oracle_mod, "uniform", N, "int32", 20)
+    t = torch.from_numpy(asc.copy()).to("cuda:0")
+    tsqs.sort_batch(t, [0, N // 3, N])
+    torch.cuda.synchronize()
+    got = t.cpu().numpy()
+    assert tsqs.get_stats()["presorted"] == 0
+    assert np.array_equal(got[: N // 3], asc[: N // 3]) and np.array_equal(got[N // 3:], asc[N // 3:])
