@@ -119,6 +119,8 @@ def run_single_arrays(args, workload, arrays, dtype, with_vals, config):
     import paper_1505_00558_amd as tsqs
     tsqs.load_library()
     dt = CODES[dtype]
+    tsqs.set_option(tsqs.OPT_PRESORT, 1 if args.presort else 0)
+    config["presort"] = bool(args.presort)
     if args.autotune:
         log("autotune: %s, %d keys" % (dtype, max(a.size for a in arrays)))
         config["tuned"] = tsqs.autotune(dt, max(a.size for a in arrays), with_payload=with_vals)
@@ -174,8 +176,11 @@ def run_single_arrays(args, workload, arrays, dtype, with_vals, config):
         sort_ms_total += ms
         name = config["families"][i] if "families" in config else str(i)
         d = per.setdefault(name, {"sort_ms": [], "levels": st["levels"],
-                                  "fallback_parts": st["fallback_parts"]})
+                                  "fallback_parts": st["fallback_parts"],
+                                  "presorted": st["presorted"]})
         d["sort_ms"].append(ms)
+        if st["presorted"]:
+            continue        # found in order by the presortedness check: no partition pass
         part_ms += st["partition_ms"]
         part_bytes += st["partition_bytes"]
         launches += st["partition_launches"]
@@ -189,11 +194,18 @@ def run_single_arrays(args, workload, arrays, dtype, with_vals, config):
         n = arrays[config["families"].index(name)].size if "families" in config else arrays[int(name)].size
         d["sort_ms"] = round(ms, 3)
         d["keys_per_s"] = n / (ms / 1e3)
+        if d["presorted"]:
+            # the check's bytes: one read of the keys (found in order), plus a read
+            # and a write of keys and payloads (reversed)
+            kbp = arrays[0].dtype.itemsize + (4 if with_vals else 0)
+            byt = n * arrays[0].dtype.itemsize + (2 * n * kbp if d["presorted"] == 2 else 0)
+            d["check_GBps"] = byt / (ms / 1e3) / 1e9
     achieved = (part_bytes / (part_ms / 1e3)) / 1e9 if part_ms > 0 else None
     roofline = {"bound": "hbm", "achieved": achieved, "peak": PEAK_GBS, "unit": "GB/s",
                 "frac": (achieved / PEAK_GBS) if achieved else None,
                 "traffic": measured_traffic(workload),
-                "kernel": "tsqs::k_partition (one pass = the partition kernels of a level)",
+                "kernel": "tsqs::k_partition (one pass = the partition kernels of a level; "
+                          "arrays found in order by the presortedness check have none)",
                 "launches": launches,
                 "avg_launch_ms": part_ms / max(launches, 1),
                 "algorithmic_bytes_per_launch": part_bytes / max(launches, 1)}
@@ -620,6 +632,8 @@ def main():
     ap.add_argument("--serve-rates", type=lambda v: [float(x) for x in v.split(",")],
                     default=[0.7, 1.0, 1.25, 1.5, 2.0, 3.0, 6.0])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-presort", dest="presort", action="store_false",
+                    help="switch the presortedness check off (every array takes the passes)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: the sort runs on one GPU; --gpus %d is not supported "

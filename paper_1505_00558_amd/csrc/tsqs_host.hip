@@ -28,6 +28,10 @@ using namespace tsqs;
 
 namespace {
 
+// Arrays of at least this many keys synchronise once after the presortedness
+// check (about 10-20 us) so that an array found in order skips the level schedule.
+constexpr uint64_t kPresortSyncMin = 1ull << 24;
+
 struct Options {
   int64_t small_max = 8192;
   int64_t samples = 63;
@@ -278,6 +282,14 @@ int run_t(Workspace &w, void *keys, uint32_t *vals, const uint64_t *h_offs, size
   const uint32_t lv_all = lv + (lv + 4) / 5 + 2;
   uint32_t expected = roots_small ? 1u : 2 + lv_all / 2;
   int d = 0, target = (int)expected;
+  if (c.pre && n >= kPresortSyncMin) {
+    // a large array found in order needs none of the levels: read the two words
+    // of the check once instead of launching the whole schedule empty
+    unsigned int *hp = (unsigned int *)(w.h_stats + kStripes * kStatWords + 8);
+    HIPCHK(hipMemcpyAsync(hp, c.pre, 2 * sizeof(unsigned int), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (hp[0] != 0u && hp[1] == 0u) target = 0;
+  }
   if (target > kMaxLevels - 1) target = kMaxLevels - 1;
   for (;;) {
     for (; d < target; d++) {

@@ -257,6 +257,11 @@ __device__ inline uint64_t shfl_u64(uint64_t v, int src) {
 template <typename U> __device__ inline U shfl_xor_any(U v, int m);
 template <> __device__ inline uint32_t shfl_xor_any<uint32_t>(uint32_t v, int m) { return shfl_xor_u32(v, m); }
 template <> __device__ inline uint64_t shfl_xor_any<uint64_t>(uint64_t v, int m) { return shfl_xor_u64(v, m); }
+// v of lane 0
+template <typename U> __device__ inline U shfl_first(U v) {
+  if constexpr (sizeof(U) == 8) return (U)shfl_u64((uint64_t)v, 0);
+  else return (U)shfl_u32((uint32_t)v, 0);
+}
 // v of the next lane (lane 63 keeps its own)
 template <typename U> __device__ inline U shfl_any_down1(U v) {
   const uint32_t l = lane_id();
@@ -661,43 +666,48 @@ template <int DT>
 __global__ __launch_bounds__(kPreNT) void k_presort_scan(Ctx c) {
   using B = typename Codec<DT>::B;
   using Cm = typename Codec<DT>::C;
-  __shared__ uint32_t mode_s, stop_s;
   const B *K = (const B *)c.K;
   const uint64_t n = c.n;
   const uint32_t lane = threadIdx.x & 63u;
-  if (threadIdx.x < kWave) {
-    // the guess: 64 evenly spaced keys in non-decreasing or non-increasing order
+  // the guess (every wave takes the same one): 64 evenly spaced keys in
+  // non-decreasing or in non-increasing order
+  uint32_t mode;
+  {
     const uint64_t pos = (uint64_t)lane * (n - 1) / (kWave - 1);
     const B x = K[pos];
-    const B z = shfl_any_down1<B>(x);         // x of the next lane (lane 63: itself)
+    const B z = shfl_any_down1<B>(x);          // x of the next lane (lane 63: itself)
     const Cm a = Codec<DT>::ckey(x), b = Codec<DT>::ckey(z);
     const bool up = wave_ballot(a > b) == 0ull, down = wave_ballot(a < b) == 0ull;
-    if (lane == 0) {
-      const uint32_t m = up ? 1u : (down ? 2u : 0u);
-      mode_s = m;
-      if (blockIdx.x == 0) c.pre[0] = m;
-    }
+    mode = up ? 1u : (down ? 2u : 0u);
+    if (blockIdx.x == 0 && threadIdx.x == 0) c.pre[0] = mode;
+    if (mode == 0u) return;
   }
-  __syncthreads();
-  const uint32_t mode = mode_s;
-  if (mode == 0u) return;
-  const uint64_t chunk = (uint64_t)kPreNT * kPreRows;
-  const uint64_t nch = (n + chunk - 1) / chunk;
-  for (uint64_t ch = blockIdx.x; ch < nch; ch += gridDim.x) {
-    if (threadIdx.x == 0) stop_s = __hip_atomic_load(&c.pre[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    __syncthreads();
-    const uint32_t stop = stop_s;
-    __syncthreads();
+  // every adjacent pair, one wave per step of kWave * kPreRows keys (rows of kWave
+  // consecutive keys; the pair that leaves a row is closed by the next row's lane 0)
+  const uint64_t wkeys = (uint64_t)kWave * kPreRows;
+  const uint64_t steps = (n + wkeys - 1) / wkeys;
+  const uint64_t nw = (uint64_t)gridDim.x * (kPreNT / kWave);
+  for (uint64_t st = (uint64_t)blockIdx.x * (kPreNT / kWave) + threadIdx.x / kWave; st < steps; st += nw) {
+    const uint32_t stop = __builtin_amdgcn_readfirstlane(
+        __hip_atomic_load(&c.pre[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
     if (stop) return;
-    bool bad = false;
-#pragma unroll 4
+    const uint64_t base = st * wkeys;
+    B x[kPreRows];
+#pragma unroll
     for (int r = 0; r < kPreRows; r++) {
-      const uint64_t i = ch * chunk + (uint64_t)r * kPreNT + threadIdx.x;
-      const B x = i < n ? K[i] : B(0);
-      B nb = shfl_any_down1<B>(x);
-      if (lane == 63u) nb = i + 1 < n ? K[i + 1] : x;
+      const uint64_t i = base + (uint64_t)r * kWave + lane;
+      x[r] = i < n ? K[i] : B(0);
+    }
+    const B after = base + wkeys < n ? K[base + wkeys] : B(0);
+    bool bad = false;
+#pragma unroll
+    for (int r = 0; r < kPreRows; r++) {
+      const uint64_t i = base + (uint64_t)r * kWave + lane;
+      B nb = shfl_any_down1<B>(x[r]);
+      const B first_next = r + 1 < kPreRows ? shfl_first<B>(x[r + 1 < kPreRows ? r + 1 : r]) : after;
+      if (lane == 63u) nb = first_next;
       if (i + 1 < n) {
-        const Cm a = Codec<DT>::ckey(x), b = Codec<DT>::ckey(nb);
+        const Cm a = Codec<DT>::ckey(x[r]), b = Codec<DT>::ckey(nb);
         bad |= mode == 1u ? a > b : a < b;
       }
     }

@@ -160,3 +160,23 @@ def test_batch_does_not_check(oracle_mod):
     got = t.cpu().numpy()
     assert tsqs.get_stats()["presorted"] == 0
     assert np.array_equal(got[: N // 3], asc[: N // 3]) and np.array_equal(got[N // 3:], asc[N // 3:])
+
+
+def test_large_arrays_skip_the_schedule(oracle_mod):
+    """From 2^24 keys the host reads the check's answer and launches no level for an
+    array found in order; one pair out of order still takes every pass."""
+    import paper_1505_00558_amd as tsqs
+    n = (1 << 24) + 5
+    print("case: presort large", n, flush=True)
+    asc = (np.arange(n, dtype=np.int64) * 7 - 7 * (n // 2)).astype(np.int32)
+    for k, want in ((asc, 1), (np.ascontiguousarray(asc[::-1]), 2)):
+        got = gpu_sort(k)
+        st = tsqs.get_stats()
+        assert np.array_equal(got, asc)
+        assert st["presorted"] == want and st["levels"] == 0
+    k = asc.copy()
+    k[n - 3], k[n - 2] = k[n - 2], k[n - 3]
+    got = gpu_sort(k)
+    st = tsqs.get_stats()
+    assert same_bits(got, oracle_mod.sort(k))
+    assert st["presorted"] == 0 and st["levels"] > 0
