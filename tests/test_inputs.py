@@ -96,3 +96,47 @@ def test_device_generator_library_exports():
     lib.tsqs_inputs_generate.restype = ctypes.c_int
     # argument errors are reported before any device work
     assert lib.tsqs_inputs_generate(None, 0, None, None, None, 1, None) == -1
+
+
+def test_paper_types_closed_forms():
+    """SVI input types at n = 10, m = 3 (hill from its definition; sawtooth,
+    stagger and plateau from their published definitions)."""
+    assert ti.paper_type("hill", 10, 3).tolist() == [0, 1, 2, 3, 3, 3, 3, 3, 2, 1]
+    assert ti.paper_type("hill", 9, 100).tolist() == [0, 1, 2, 3, 5, 4, 3, 2, 1]
+    assert ti.paper_type("sawtooth", 10, 3).tolist() == [0, 1, 2, 0, 1, 2, 0, 1, 2, 0]
+    assert ti.paper_type("stagger", 10, 3).tolist() == [0, 4, 8, 2, 6, 0, 4, 8, 2, 6]
+    assert ti.paper_type("plateau", 10, 3).tolist() == [0, 1, 2, 3, 3, 3, 3, 3, 3, 3]
+    r = ti.paper_type("random", 100000, 50, seed=4)
+    assert r.min() == 0 and r.max() == 49
+    s = ti.paper_type("shuffle", 100000, 4, seed=5)
+    ev, od = s[s % 2 == 0], s[s % 2 == 1]
+    # two interleaved runs: the evens 0, 2, 4, ... and the odds 1, 3, 5, ... in order
+    assert np.array_equal(ev, 2 * np.arange(ev.size)) and np.array_equal(od, 2 * np.arange(od.size) + 1)
+    assert 0.2 < od.size / s.size < 0.3                   # one in m = 4 picks the odd run
+    o = ti.paper_type("organ_pipes", 200000, 1000, seed=6)
+    assert o.min() >= 1 and o.max() <= 1000
+    assert np.abs(np.diff(o)).max() <= 1000
+
+
+def test_paper_fort_by_hand():
+    """Fort of 0..7 with ranges longer than 2 split: reverse all, then each half, then
+    each quarter (worked out by hand)."""
+    assert ti.fort(np.arange(8), 2).tolist() == [5, 4, 7, 6, 1, 0, 3, 2]
+    assert ti.fort(np.arange(5), 100).tolist() == [4, 3, 2, 1, 0]        # one reversal
+    # 0..6, ranges longer than 1 split: [0,6] reversed: 6 5 4 3 2 1 0; [0,3] reversed:
+    # 3 4 5 6, then [0,1] and [2,3]: 4 3 6 5; [4,6] reversed: 0 1 2, then [4,5]: 1 0
+    assert ti.fort(np.arange(7), 1).tolist() == [4, 3, 6, 5, 1, 0, 2]
+
+
+def test_paper_orders():
+    n, m = 11, 1000
+    v = ti.paper_type("random", n, m, seed=9)
+    get = lambda o: ti.paper_input("random", o, n, m, dtype="int64", seed=9)
+    assert np.array_equal(get("as_is"), v)
+    assert np.array_equal(get("sorted"), np.sort(v))
+    assert np.array_equal(get("reversed"), v[::-1])
+    assert np.array_equal(get("front_half_reversed"), np.r_[v[:5][::-1], v[5:]])
+    assert np.array_equal(get("back_half_reversed"), np.r_[v[:5], v[5:][::-1]])
+    assert np.array_equal(get("dither"), v + np.arange(n) % 5)
+    f = ti.paper_input("random", "fort", 4096, m, dtype="int64", seed=9)
+    assert np.array_equal(np.sort(f), np.sort(ti.paper_type("random", 4096, m, seed=9)))

@@ -255,3 +255,118 @@ def device_batch(seed: int, count: int, lo_log2: int = 4, hi_log2: int = 20, dty
     t = torch.empty(int(offs[-1]), dtype=getattr(torch, TORCH_DTYPE[dtype]), device=device)
     device_generate(t, dtype, offs, fams, seeds)
     return t, offs, fams
+
+
+# ---- the input types and reorderings of the paper's comparison tests (SVI) -------------
+#
+# Input types (values before the cast to a dtype), with m the value range / period:
+#   random    uniform in [0, m)                     sawtooth  i mod m
+#   stagger   (i*m + i) mod n                      plateau   min(i, m)
+#   shuffle   two interleaved increasing runs, the run chosen at random (one in m
+#             picks the odd run)
+#   hill      rises from 0 by 1 to the middle and falls back, clipped at m (SVI)
+#   organ_pipes  straight ramps between random levels in [1, m] (plus op_add), each over a
+#             random length of 1..op_max_distance keys (SVI)
+# Reorderings: as generated, sorted, reversed, front half reversed, back half reversed,
+# dither (key + i mod 5), and fort: the sorted keys, reversed as a whole, then each half
+# again, recursively, while a range is longer than fort_min (SVI).
+PAPER_TYPES = ["random", "sawtooth", "stagger", "plateau", "shuffle", "hill", "organ_pipes"]
+PAPER_ORDERS = ["as_is", "sorted", "reversed", "front_half_reversed", "back_half_reversed",
+                "dither", "fort"]
+
+
+def _uniform_int(seed: int, n: int, lo: int, hi: int) -> np.ndarray:
+    """Integers uniform in [lo, hi] (64-bit draws reduced modulo the range)."""
+    return lo + (splitmix64(seed, n) % np.uint64(hi - lo + 1)).astype(np.int64)
+
+
+def paper_type(kind: str, n: int, m: int, seed: int = 1, op_max_distance: int = 1000,
+               op_add: int = 0) -> np.ndarray:
+    """One of the SVI input types as int64 values."""
+    i = np.arange(n, dtype=np.int64)
+    m = max(1, int(m))
+    if kind == "random":
+        return _uniform_int(seed, n, 0, m - 1)
+    if kind == "sawtooth":
+        return i % m
+    if kind == "stagger":
+        return (i * m + i) % max(n, 1)
+    if kind == "plateau":
+        return np.minimum(i, m)
+    if kind == "shuffle":
+        odd = (splitmix64(seed, n) % np.uint64(m)) == 0      # one in m: the odd run
+        out = np.empty(n, dtype=np.int64)
+        ko = np.cumsum(odd) - 1                               # index within each run
+        ke = np.cumsum(~odd) - 1
+        out[odd] = 2 * ko[odd] + 1
+        out[~odd] = 2 * ke[~odd]
+        return out
+    if kind == "hill":
+        return np.minimum(np.where(i < (n >> 1), i, n - i), m)
+    if kind == "organ_pipes":
+        out = np.empty(n, dtype=np.float64)
+        pos, k = 0, 0
+        lv = _uniform_int(seed, 1, 1, m)[0]
+        while pos < n:
+            # the levels and lengths of the next 4096 ramps at once
+            draws = splitmix64(seed + 1, 2 * 4096, start=2 * 4096 * k)
+            lvl = 1 + (draws[0::2] % np.uint64(m)).astype(np.int64) + op_add
+            dist = 1 + (draws[1::2] % np.uint64(max(1, op_max_distance))).astype(np.int64)
+            for v, d in zip(lvl.tolist(), dist.tolist()):
+                e = min(n, pos + d)
+                step = (v - lv) / d
+                out[pos:e] = lv + step * np.arange(e - pos)
+                pos = e
+                lv = v
+                if pos >= n:
+                    break
+            k += 1
+        return np.floor(out).astype(np.int64)
+    raise KeyError(kind)
+
+
+def fort(a: np.ndarray, fort_min: int) -> np.ndarray:
+    """The ranges of a recursive halving, each reversed in turn from the whole array
+    down: a range [lo, hi] is reversed, then, if it holds more than fort_min keys,
+    [lo, mid] and [mid+1, hi] (mid = floor((lo+hi)/2)) are treated the same way."""
+    out = np.array(a, copy=True)
+    n = out.size
+    lo = np.zeros(1, dtype=np.int64)
+    hi = np.full(1, n - 1, dtype=np.int64)
+    fort_min = max(1, int(fort_min))
+    while lo.size and n:
+        ln = hi - lo + 1
+        idx = np.arange(n, dtype=np.int64)
+        # every range of this depth reversed at once: position p -> lo + hi - p
+        starts = np.repeat(lo, ln)
+        ends = np.repeat(hi, ln)
+        pos = starts + (np.arange(int(ln.sum()), dtype=np.int64) - np.repeat(np.cumsum(ln) - ln, ln))
+        idx[pos] = starts + ends - pos
+        out = out[idx]
+        go = ln > fort_min
+        mid = (lo + hi) >> 1
+        lo, hi = np.concatenate([lo[go], mid[go] + 1]), np.concatenate([mid[go], hi[go]])
+    return out
+
+
+def paper_input(kind: str, order: str, n: int, m: int, dtype="int32", seed: int = 1,
+                fort_min: int = 16) -> np.ndarray:
+    """An SVI input type under one of the SVI reorderings, cast to dtype."""
+    v = paper_type(kind, n, m, seed)
+    h = n // 2
+    if order == "sorted":
+        v = np.sort(v)
+    elif order == "reversed":
+        v = v[::-1]
+    elif order == "front_half_reversed":
+        v = np.concatenate([v[:h][::-1], v[h:]])
+    elif order == "back_half_reversed":
+        v = np.concatenate([v[:h], v[h:][::-1]])
+    elif order == "dither":
+        v = v + np.arange(n, dtype=np.int64) % 5
+    elif order == "fort":
+        v = fort(np.sort(v), fort_min)
+    elif order != "as_is":
+        raise KeyError(order)
+    dt = np.dtype(DTYPES[dtype] if isinstance(dtype, str) else dtype)
+    return np.ascontiguousarray(v).astype(dt)
