@@ -177,7 +177,11 @@ def run_single_arrays(args, workload, arrays, dtype, with_vals, config):
         name = config["families"][i] if "families" in config else str(i)
         d = per.setdefault(name, {"sort_ms": [], "levels": st["levels"],
                                   "fallback_parts": st["fallback_parts"],
-                                  "presorted": st["presorted"]})
+                                  "presorted": st["presorted"],
+                                  # partition passes that moved keys, and key moves per
+                                  # key: passes + small-part finish + equal bands
+                                  "passes": sum(1 for x in st["level_keys"] if x),
+                                  "moves": sum(st["level_keys"]) + st["small_keys"] + st["band_keys"]})
         d["sort_ms"].append(ms)
         if st["presorted"]:
             continue        # found in order by the presortedness check: no partition pass
@@ -194,6 +198,7 @@ def run_single_arrays(args, workload, arrays, dtype, with_vals, config):
         n = arrays[config["families"].index(name)].size if "families" in config else arrays[int(name)].size
         d["sort_ms"] = round(ms, 3)
         d["keys_per_s"] = n / (ms / 1e3)
+        d["moves_per_key"] = d.pop("moves") / n if n else 0.0
         if d["presorted"]:
             # the check's bytes: one read of the keys (found in order), plus a read
             # and a write of keys and payloads (reversed)
@@ -281,6 +286,39 @@ def workload_pairs64(args):
             [(ti.family("uniform", m, "uint64", seed=ti.seed_for(3, 0)), idx.copy()),
              (ti.distinct10_u64(ti.seed_for(3, 1), m), idx.copy())],
             "uniform and 10%%-distinct, %d uint64 keys + uint32 payload each" % m)
+    return out
+
+
+def workload_paper(args):
+    """The input types and reorderings of the paper's comparison tests (SVI)."""
+    import tsqs_inputs as ti
+    n, m = 1 << args.paper_log2n, 1 << 16
+    names = ["%s/%s" % (k, o) for k in ti.PAPER_TYPES for o in ti.PAPER_ORDERS]
+    log("generating %d inputs x %d int32 keys" % (len(names), n))
+    arrays = [ti.paper_input(k, o, n, m, "int32", seed=ti.seed_for(4, 0))
+              for k in ti.PAPER_TYPES for o in ti.PAPER_ORDERS]
+    config = {"workload": "SVI inputs: %d types x %d reorderings, 2^%d int32 keys each, values "
+                          "in [0, 2^16) (random) or the type's own range; one in-place sort per "
+                          "input per step" % (len(ti.PAPER_TYPES), len(ti.PAPER_ORDERS),
+                                               args.paper_log2n),
+              "n": n, "families": names, "key": "int32", "payload": None}
+    out = run_single_arrays(args, "paper_2^%d_int32" % args.paper_log2n, arrays, "int32", False,
+                            config)
+    if not args.no_cpu_baseline:
+        # the oracle on the same inputs, with its comparison and copy counters (SV.A)
+        import oracle
+        oracle.build(force=not os.path.exists(oracle.LIB_PATH))
+        tot_s, counts = 0.0, {}
+        for name, k in zip(names, arrays):
+            t0 = time.perf_counter()
+            _, c = oracle.sort(k, counters=True)
+            tot_s += time.perf_counter() - t0
+            counts[name] = {"comparisons_per_key": c.comparisons / n, "copies_per_key": c.copies / n}
+        out["cpu_baseline"] = {
+            "value": len(arrays) * n / tot_s, "unit": "keys/s", "cores": 1, "kind": "oracle",
+            "sample": "the same %d inputs of %d keys, one single-threaded oracle sort each with "
+                      "its counters (%.1f s of CPU work)" % (len(arrays), n, tot_s),
+            "counts": counts}
     return out
 
 
@@ -617,7 +655,8 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="large",
-                    choices=["large", "plain1m", "pairs64", "float32", "batch", "serve"])
+                    choices=["large", "plain1m", "pairs64", "float32", "batch", "serve", "paper"])
+    ap.add_argument("--paper-log2n", type=int, default=20)
     ap.add_argument("--log2n", type=int, default=28)
     ap.add_argument("--families", default="all")
     ap.add_argument("--cpu-log2n", type=int, default=26)
@@ -645,7 +684,7 @@ def main():
         sys.exit(1)
     fn = {"large": workload_large, "plain1m": workload_plain1m, "pairs64": workload_pairs64,
           "float32": workload_float32, "batch": workload_batch,
-          "serve": workload_serve}.get(args.workload)
+          "serve": workload_serve, "paper": workload_paper}.get(args.workload)
     if fn is None:
         print("bench.py: workload %s is not available" % args.workload, file=sys.stderr)
         sys.exit(2)
