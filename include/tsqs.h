@@ -119,6 +119,24 @@ int tsqs_sort(void *d_keys, size_t nmemb, int dt, void *stream);
 /* As tsqs_sort, moving the uint32 payload d_vals[i] with key d_keys[i]. */
 int tsqs_sort_pairs(void *d_keys, uint32_t *d_vals, size_t nmemb, int dt, void *stream);
 
+/* Sort records of any size by their keys (late swapping, SVIII.H): the keys
+ * are sorted in place with a uint32 index as their payload (the paper's
+ * temporary pointer array), then every record is moved once, by a gather,
+ * into its sorted place.
+ *   d_keys     nmemb keys of type dt (device), sorted in place
+ *   d_records  nmemb records of rec_bytes bytes each (device), record i
+ *              belonging to key i; 1 <= rec_bytes <= 65536
+ *   d_out      device buffer for the records in key order (d_records is then
+ *              left as it was; the two must not overlap), or NULL (or
+ *              d_records) to reorder d_records in place through a staging
+ *              buffer of nmemb * rec_bytes bytes that the library allocates and
+ *              keeps (freed by tsqs_free_storage)
+ * nmemb < 2^32.  Records with equal keys come out in no particular order.
+ * Returns TSQS_EINVAL for null pointers, bad sizes or overlapping buffers;
+ * TSQS_EINTERNAL if the sorted index was not a permutation (a bug). */
+int tsqs_sort_records(void *d_keys, void *d_records, size_t rec_bytes, void *d_out, size_t nmemb,
+                      int dt, void *stream);
+
 /* Sort nseg independent arrays stored back to back in d_keys: array j is
  * d_keys[h_offsets[j] .. h_offsets[j+1]).  h_offsets is a host array of nseg+1
  * non-decreasing values starting at 0; every array must have < 2^32 keys (the

@@ -24,7 +24,7 @@ OPT_SEED, OPT_TIMING, OPT_PART_GRID, OPT_FINISH_GRID, OPT_FINISH_ALGO = 5, 6, 7,
 OPT_PRESORT = 10
 MAX_LEVELS = 192
 
-SYMBOLS = ["tsqs_sort", "tsqs_sort_pairs", "tsqs_sort_batch", "tsqs_autotune",
+SYMBOLS = ["tsqs_sort", "tsqs_sort_pairs", "tsqs_sort_records", "tsqs_sort_batch", "tsqs_autotune",
            "tsqs_free_storage", "tsqs_set_option", "tsqs_get_option", "tsqs_get_stats",
            "tsqs_strerror", "tsqs_version"]
 QUEUE_SYMBOLS = ["tsqs_queue_open", "tsqs_queue_submit", "tsqs_queue_step", "tsqs_queue_poll",
@@ -107,6 +107,8 @@ def load_library():
     lib.tsqs_sort.restype = ctypes.c_int
     lib.tsqs_sort_pairs.argtypes = [vp, vp, sz, ctypes.c_int, vp]
     lib.tsqs_sort_pairs.restype = ctypes.c_int
+    lib.tsqs_sort_records.argtypes = [vp, vp, sz, vp, sz, ctypes.c_int, vp]
+    lib.tsqs_sort_records.restype = ctypes.c_int
     lib.tsqs_sort_batch.argtypes = [vp, vp, vp, sz, ctypes.c_int, vp]
     lib.tsqs_sort_batch.restype = ctypes.c_int
     lib.tsqs_autotune.argtypes = [ctypes.c_int, ctypes.c_int, sz, vp, sz, vp, ctypes.POINTER(Tune)]
@@ -193,6 +195,31 @@ def sort_pairs(keys, vals, dtype_code: int | None = None):
                                           ctypes.c_void_p(vals.data_ptr()), keys.numel(), dt,
                                           _stream_handle()))
     return keys, vals
+
+
+def sort_records(keys, records, out=None, dtype_code: int | None = None):
+    """Sort keys in place and put ``records`` (a contiguous tensor whose first
+    dimension is the key count; each row is one record of any size) in key order:
+    into ``out`` (same shape and byte size), or in place when ``out`` is None."""
+    _check_tensor(keys, "keys")
+    _check_tensor(records, "records")
+    n = keys.numel()
+    if records.dim() < 1 or records.shape[0] != n:
+        raise ValueError("records needs one row per key")
+    rec_bytes = records.numel() * records.element_size() // n if n else 0
+    op = None
+    if out is not None:
+        _check_tensor(out, "out")
+        if out.numel() * out.element_size() != records.numel() * records.element_size():
+            raise ValueError("out must have the byte size of records")
+        op = ctypes.c_void_p(out.data_ptr())
+    dt = _dtype_code(keys) if dtype_code is None else dtype_code
+    if n == 0:
+        return keys, (records if out is None else out)
+    _check(load_library().tsqs_sort_records(ctypes.c_void_p(keys.data_ptr()),
+                                            ctypes.c_void_p(records.data_ptr()), rec_bytes, op,
+                                            n, dt, _stream_handle()))
+    return keys, (records if out is None else out)
 
 
 def sort_batch(keys, offsets, vals=None, dtype_code: int | None = None):

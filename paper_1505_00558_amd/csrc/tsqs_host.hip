@@ -9,6 +9,7 @@
 // are launched, eight at a time.
 #include "tsqs.h"
 #include "tsqs_kernels.hpp"
+#include "tsqs_records.hpp"
 #include "tsqs_queue.h"
 
 #include <hip/hip_runtime.h>
@@ -69,6 +70,20 @@ struct Workspace {
 };
 
 std::mutex g_mu;
+
+// Buffers of tsqs_sort_records per device: the index (the sorted "pointer array"),
+// the staging buffer of an in-place gather, and an error word.
+constexpr size_t kMaxRecBytes = 65536;
+struct RecWs {
+  uint32_t *idx = nullptr;
+  size_t idx_cap = 0;
+  unsigned char *tmp = nullptr;
+  size_t tmp_cap = 0;
+  unsigned int *err = nullptr;
+  size_t err_cap = 0;
+};
+std::mutex g_rec_mu;
+std::vector<RecWs> g_rec;
 Options g_opt;
 std::vector<Workspace> g_ws;
 tsqs_stats_t g_stats;
@@ -429,6 +444,72 @@ int tsqs_sort_pairs(void *d_keys, uint32_t *d_vals, size_t nmemb, int dt, void *
                   (hipStream_t)stream);
 }
 
+int tsqs_sort_records(void *d_keys, void *d_records, size_t rec_bytes, void *d_out, size_t nmemb,
+                      int dt, void *stream) {
+  if (!dtype_ok(dt)) return TSQS_EUNSUPPORTED;
+  if (nmemb == 0) return TSQS_OK;
+  if (!d_keys || !d_records || rec_bytes == 0 || rec_bytes > kMaxRecBytes) return TSQS_EINVAL;
+  if (nmemb > 0xFFFFFFFFull) return TSQS_EINVAL;
+  const size_t total = nmemb * rec_bytes;
+  if (d_out == d_records) d_out = nullptr;
+  if (d_out) {
+    const uintptr_t a = (uintptr_t)d_records, b = (uintptr_t)d_out;
+    if (a < b + total && b < a + total) return TSQS_EINVAL;   // overlapping, not identical
+  }
+  hipStream_t s = (hipStream_t)stream;
+  if (nmemb == 1) {
+    if (d_out) HIPCHK(hipMemcpyAsync(d_out, d_records, rec_bytes, hipMemcpyDeviceToDevice, s));
+    HIPCHK(hipStreamSynchronize(s));
+    return TSQS_OK;
+  }
+  std::lock_guard<std::mutex> lk(g_rec_mu);
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  if (dev < 0) return TSQS_EDEVICE;
+  if ((size_t)dev >= g_rec.size()) g_rec.resize((size_t)dev + 1);
+  RecWs &r = g_rec[(size_t)dev];
+  int rc;
+  if ((rc = grow(&r.idx, &r.idx_cap, nmemb)) != TSQS_OK) return rc;
+  if ((rc = grow(&r.err, &r.err_cap, 1)) != TSQS_OK) return rc;
+  int cus = 256;
+  {
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, dev) == hipSuccess && prop.multiProcessorCount > 0)
+      cus = prop.multiProcessorCount;
+  }
+  const uint64_t blocks_needed = (nmemb + kRecNT - 1) / kRecNT;
+  const int grid = (int)(blocks_needed < (uint64_t)(8 * cus) ? blocks_needed : (uint64_t)(8 * cus));
+  hipLaunchKernelGGL(k_rec_iota, dim3(grid), dim3(kRecNT), 0, s, r.idx, (uint64_t)nmemb, r.err);
+  HIPCHK(hipGetLastError());
+  // the keys with the index as payload: the paper's sorted pointer array
+  if ((rc = dispatch(d_keys, r.idx, nullptr, 1, (uint64_t)nmemb, (uint64_t)nmemb, dt, s)) != TSQS_OK)
+    return rc;
+  void *dst = d_out;
+  if (!dst) {
+    if ((rc = grow(&r.tmp, &r.tmp_cap, total)) != TSQS_OK) return rc;
+    dst = r.tmp;
+  }
+  const uintptr_t al = (uintptr_t)d_records | (uintptr_t)dst | (uintptr_t)rec_bytes;
+  if ((al & 15u) == 0)
+    hipLaunchKernelGGL(k_rec_gather<uint4>, dim3(grid), dim3(kRecNT), 0, s, (const uint4 *)d_records,
+                       (uint4 *)dst, r.idx, (uint64_t)nmemb, (uint32_t)(rec_bytes / 16), r.err);
+  else if ((al & 7u) == 0)
+    hipLaunchKernelGGL(k_rec_gather<uint2>, dim3(grid), dim3(kRecNT), 0, s, (const uint2 *)d_records,
+                       (uint2 *)dst, r.idx, (uint64_t)nmemb, (uint32_t)(rec_bytes / 8), r.err);
+  else if ((al & 3u) == 0)
+    hipLaunchKernelGGL(k_rec_gather<uint32_t>, dim3(grid), dim3(kRecNT), 0, s, (const uint32_t *)d_records,
+                       (uint32_t *)dst, r.idx, (uint64_t)nmemb, (uint32_t)(rec_bytes / 4), r.err);
+  else
+    hipLaunchKernelGGL(k_rec_gather<uint8_t>, dim3(grid), dim3(kRecNT), 0, s, (const uint8_t *)d_records,
+                       (uint8_t *)dst, r.idx, (uint64_t)nmemb, (uint32_t)rec_bytes, r.err);
+  HIPCHK(hipGetLastError());
+  if (!d_out) HIPCHK(hipMemcpyAsync(d_records, r.tmp, total, hipMemcpyDeviceToDevice, s));
+  unsigned int h_err = 0;
+  HIPCHK(hipMemcpyAsync(&h_err, r.err, sizeof h_err, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  return h_err ? TSQS_EINTERNAL : TSQS_OK;
+}
+
 int tsqs_sort_batch(void *d_keys, uint32_t *d_vals, const uint64_t *h_offsets, size_t nseg,
                     int dt, void *stream) {
   if (!dtype_ok(dt)) return TSQS_EUNSUPPORTED;
@@ -450,6 +531,7 @@ int tsqs_sort_batch(void *d_keys, uint32_t *d_vals, const uint64_t *h_offsets, s
 }
 
 void tsqs_free_storage(void) {
+  std::lock_guard<std::mutex> lr(g_rec_mu);   // same order as tsqs_sort_records
   std::lock_guard<std::mutex> lk(g_mu);
   int cur = 0;
   if (hipGetDevice(&cur) != hipSuccess) cur = -1;
@@ -459,8 +541,17 @@ void tsqs_free_storage(void) {
     (void)hipDeviceSynchronize();
     free_ws(g_ws[i]);
   }
+  for (size_t i = 0; i < g_rec.size(); i++) {
+    RecWs &r = g_rec[i];
+    if (!r.idx && !r.tmp && !r.err) continue;
+    if (hipSetDevice((int)i) != hipSuccess) continue;
+    (void)hipDeviceSynchronize();
+    (void)hipFree(r.idx); (void)hipFree(r.tmp); (void)hipFree(r.err);
+    r = RecWs();
+  }
   if (cur >= 0) (void)hipSetDevice(cur);
   g_ws.clear();
+  g_rec.clear();
 }
 
 int tsqs_set_option(int key, int64_t v) {

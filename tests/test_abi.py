@@ -154,3 +154,16 @@ def test_autotune_argument_errors(lib):
     assert lib.tsqs_autotune(0, 0, 3, p, 2, None, ctypes.byref(t)) == -1     # decreasing
     p, keep = _offs([0, 5, 9])
     assert lib.tsqs_autotune(0, 0, 10, p, 2, None, ctypes.byref(t)) == -1    # n != last offset
+
+
+def test_sort_records_argument_checks(lib):
+    """Argument errors of tsqs_sort_records, all detected before any device work."""
+    fake, fake2 = ctypes.c_void_p(0x10000000), ctypes.c_void_p(0x10000100)
+    assert lib.tsqs_sort_records(fake, fake, 8, None, 0, 0, None) == 0           # nothing to do
+    assert lib.tsqs_sort_records(None, fake, 8, None, 10, 0, None) == -1         # null keys
+    assert lib.tsqs_sort_records(fake, None, 8, None, 10, 0, None) == -1         # null records
+    assert lib.tsqs_sort_records(fake, fake, 0, None, 10, 0, None) == -1         # empty records
+    assert lib.tsqs_sort_records(fake, fake, 65537, None, 10, 0, None) == -1     # too large
+    assert lib.tsqs_sort_records(fake, fake, 8, None, 1 << 32, 0, None) == -1    # n >= 2^32
+    assert lib.tsqs_sort_records(fake, fake, 64, fake2, 10, 0, None) == -1       # overlapping out
+    assert lib.tsqs_sort_records(fake, fake, 8, None, 10, 9, None) == -4         # bad dtype
