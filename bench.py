@@ -322,6 +322,75 @@ def workload_paper(args):
     return out
 
 
+def workload_records(args):
+    """Keys with 56-byte records (the paper's large elements, SIX.B), sorted out of
+    place by tsqs_sort_records; the key+index sort alone is timed beside it."""
+    import torch
+    import paper_1505_00558_amd as tsqs
+    import tsqs_inputs as ti
+    tsqs.load_library()
+    tsqs.set_option(tsqs.OPT_PRESORT, 1 if args.presort else 0)
+    n, rb = 1 << args.records_log2n, 56
+    log("generating %d int32 keys with %d-byte records" % (n, rb))
+    keys0 = to_dev(ti.family("uniform", n, "int32", seed=ti.seed_for(5, 0)))
+    rec0 = torch.empty(n * rb, dtype=torch.uint8, device="cuda:0")
+    ti.device_generate(rec0.view(torch.int32), "int32", np.array([0, n * rb // 4], dtype=np.uint64),
+                       ["uniform"], [ti.seed_for(5, 1)])
+    rec0 = rec0.view(n, rb)
+    keys = torch.empty_like(keys0)
+    out = torch.empty_like(rec0)
+    idx0 = torch.arange(n, dtype=torch.int32, device="cuda:0")
+    idx = torch.empty_like(idx0)
+
+    def timed(fn, steps):
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        tot = 0.0
+        for _ in range(steps):
+            keys.copy_(keys0)
+            idx.copy_(idx0)
+            ev0.record()
+            fn()
+            ev1.record()
+            torch.cuda.synchronize()
+            tot += ev0.elapsed_time(ev1)
+        return tot / steps
+
+    for _ in range(args.warmup):
+        keys.copy_(keys0)
+        tsqs.sort_records(keys, rec0, out=out)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ms_rec = timed(lambda: tsqs.sort_records(keys, rec0, out=out), args.steps)
+    wall = time.perf_counter() - t0
+    ms_pairs = timed(lambda: tsqs.sort_pairs(keys, idx), args.steps)
+    gather_bytes = n * (2 * rb + 4)       # read and write every record, read the index
+    out_line = {
+        "metric": "sorted records/s (56-byte records, int32 keys)",
+        "value": n / (ms_rec / 1e3),
+        "unit": "records/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms_rec,
+        "wall_ms_per_step": wall * 1e3 / args.steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "int32", "data": "synthetic",
+        "config": {"workload": "2^%d uniform int32 keys, each with a 56-byte record, sorted out of "
+                               "place by tsqs_sort_records (key+index sort, then one gather)"
+                               % args.records_log2n, "n": n, "record_bytes": rb},
+        "key_index_sort_ms": ms_pairs,
+        "gather_and_rest_ms": ms_rec - ms_pairs,
+        "gather_GBps_upper": gather_bytes / ((ms_rec - ms_pairs) / 1e3) / 1e9 if ms_rec > ms_pairs else None,
+        "gather_bytes": gather_bytes,
+    }
+    if not args.no_cpu_baseline:
+        m = 1 << (args.cpu_log2n - 2)
+        k = ti.family("uniform", m, "int32", seed=ti.seed_for(5, 0))
+        out_line["cpu_baseline"] = cpu_baseline_samples(
+            [(k, np.arange(m, dtype=np.uint32))],
+            "%d uniform int32 keys + uint32 index (the key+index sort of the records path; "
+            "the gather is not timed)" % m)
+    return out_line
+
+
 def workload_float32(args):
     import tsqs_inputs as ti
     n = 1 << 27
@@ -655,7 +724,9 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="large",
-                    choices=["large", "plain1m", "pairs64", "float32", "batch", "serve", "paper"])
+                    choices=["large", "plain1m", "pairs64", "float32", "batch", "serve", "paper",
+                             "records"])
+    ap.add_argument("--records-log2n", type=int, default=26)
     ap.add_argument("--paper-log2n", type=int, default=20)
     ap.add_argument("--log2n", type=int, default=28)
     ap.add_argument("--families", default="all")
@@ -684,7 +755,8 @@ def main():
         sys.exit(1)
     fn = {"large": workload_large, "plain1m": workload_plain1m, "pairs64": workload_pairs64,
           "float32": workload_float32, "batch": workload_batch,
-          "serve": workload_serve, "paper": workload_paper}.get(args.workload)
+          "serve": workload_serve, "paper": workload_paper,
+          "records": workload_records}.get(args.workload)
     if fn is None:
         print("bench.py: workload %s is not available" % args.workload, file=sys.stderr)
         sys.exit(2)

@@ -490,17 +490,20 @@ int tsqs_sort_records(void *d_keys, void *d_records, size_t rec_bytes, void *d_o
     dst = r.tmp;
   }
   const uintptr_t al = (uintptr_t)d_records | (uintptr_t)dst | (uintptr_t)rec_bytes;
+  const size_t wsz = (al & 15u) == 0 ? 16 : (al & 7u) == 0 ? 8 : (al & 3u) == 0 ? 4 : 1;
+  const uint64_t gtiles = (total / wsz + (uint64_t)kRecNT * kRecU - 1) / ((uint64_t)kRecNT * kRecU);
+  const int ggrid = (int)(gtiles < (uint64_t)(16 * cus) ? gtiles : (uint64_t)(16 * cus));
   if ((al & 15u) == 0)
-    hipLaunchKernelGGL(k_rec_gather<uint4>, dim3(grid), dim3(kRecNT), 0, s, (const uint4 *)d_records,
+    hipLaunchKernelGGL(k_rec_gather<uint4>, dim3(ggrid), dim3(kRecNT), 0, s, (const uint4 *)d_records,
                        (uint4 *)dst, r.idx, (uint64_t)nmemb, (uint32_t)(rec_bytes / 16), r.err);
   else if ((al & 7u) == 0)
-    hipLaunchKernelGGL(k_rec_gather<uint2>, dim3(grid), dim3(kRecNT), 0, s, (const uint2 *)d_records,
+    hipLaunchKernelGGL(k_rec_gather<uint2>, dim3(ggrid), dim3(kRecNT), 0, s, (const uint2 *)d_records,
                        (uint2 *)dst, r.idx, (uint64_t)nmemb, (uint32_t)(rec_bytes / 8), r.err);
   else if ((al & 3u) == 0)
-    hipLaunchKernelGGL(k_rec_gather<uint32_t>, dim3(grid), dim3(kRecNT), 0, s, (const uint32_t *)d_records,
+    hipLaunchKernelGGL(k_rec_gather<uint32_t>, dim3(ggrid), dim3(kRecNT), 0, s, (const uint32_t *)d_records,
                        (uint32_t *)dst, r.idx, (uint64_t)nmemb, (uint32_t)(rec_bytes / 4), r.err);
   else
-    hipLaunchKernelGGL(k_rec_gather<uint8_t>, dim3(grid), dim3(kRecNT), 0, s, (const uint8_t *)d_records,
+    hipLaunchKernelGGL(k_rec_gather<uint8_t>, dim3(ggrid), dim3(kRecNT), 0, s, (const uint8_t *)d_records,
                        (uint8_t *)dst, r.idx, (uint64_t)nmemb, (uint32_t)rec_bytes, r.err);
   HIPCHK(hipGetLastError());
   if (!d_out) HIPCHK(hipMemcpyAsync(d_records, r.tmp, total, hipMemcpyDeviceToDevice, s));

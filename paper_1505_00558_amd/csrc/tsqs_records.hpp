@@ -19,19 +19,44 @@ __global__ __launch_bounds__(kRecNT) void k_rec_iota(uint32_t *idx, uint64_t n, 
   if (blockIdx.x == 0 && threadIdx.x == 0) *err = 0u;
 }
 
-// dst[r] = src[idx[r]] for records of wpr words of type W; an index out of range
-// (not a permutation: a bug) is reported in *err instead of being followed.
+constexpr int kRecU = 4;            // output words per thread per tile (loads in flight)
+
+// dst[r] = src[idx[r]] for records of wpr words of type W.  The output is cut into
+// tiles of kRecNT * kRecU consecutive words; thread t copies words t, t + kRecNT,
+// ... of its tile, so every store is coalesced and the lanes that fall in one
+// record read that record's consecutive words.  An index out of range (not a
+// permutation: a bug) is reported in *err instead of being followed.
 template <typename W>
 __global__ __launch_bounds__(kRecNT) void k_rec_gather(const W *__restrict__ src, W *__restrict__ dst,
                                                       const uint32_t *__restrict__ idx, uint64_t n,
                                                       uint32_t wpr, unsigned int *err) {
-  const uint64_t step = (uint64_t)gridDim.x * kRecNT;
-  for (uint64_t r = (uint64_t)blockIdx.x * kRecNT + threadIdx.x; r < n; r += step) {
-    const uint32_t k = idx[r];
-    if (k >= n) { atomicOr(err, 1u); continue; }
-    const W *s = src + (uint64_t)k * wpr;
-    W *d = dst + r * wpr;
-    for (uint32_t j = 0; j < wpr; j++) d[j] = s[j];
+  const uint64_t total = n * wpr;
+  const uint64_t tile_words = (uint64_t)kRecNT * kRecU;
+  const uint64_t tiles = (total + tile_words - 1) / tile_words;
+  for (uint64_t t = blockIdx.x; t < tiles; t += gridDim.x) {
+    const uint64_t tb = t * tile_words;
+    const uint64_t r0 = tb / wpr;                       // record of the tile's first word
+    const uint32_t lw0 = (uint32_t)(tb - r0 * wpr);     // its word within that record
+    uint64_t w[kRecU], s[kRecU];
+    bool ok[kRecU];
+#pragma unroll
+    for (int u = 0; u < kRecU; u++) {
+      w[u] = tb + (uint64_t)u * kRecNT + threadIdx.x;
+      const uint32_t lw = lw0 + (uint32_t)u * kRecNT + threadIdx.x;
+      const uint32_t lr = lw / wpr;
+      const uint64_t r = r0 + lr;
+      ok[u] = w[u] < total;
+      const uint32_t k = ok[u] ? idx[r] : 0u;
+      if (ok[u] && k >= n) { atomicOr(err, 1u); ok[u] = false; }
+      s[u] = (uint64_t)k * wpr + (lw - lr * wpr);
+    }
+    W v[kRecU];
+#pragma unroll
+    for (int u = 0; u < kRecU; u++)
+      if (ok[u]) v[u] = src[s[u]];
+#pragma unroll
+    for (int u = 0; u < kRecU; u++)
+      if (ok[u]) dst[w[u]] = v[u];
   }
 }
 
