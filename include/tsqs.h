@@ -81,12 +81,13 @@ enum {
                                 merged by a register network, 3 = runs of up to one
                                 wave merged by cross-lane bitonic stages in registers
                                 first, then as 1 (default) */
-  TSQS_OPT_PRESORT = 10      /* 1 (default) = before the first pass of a single array
-                                (tsqs_sort, tsqs_sort_pairs) that needs one, check
-                                whether it is already non-decreasing, or non-increasing
-                                (then reverse it in place, payloads too): such an array
-                                needs no pass (the sorted / reversed handlers, SIII.I);
-                                0 = off.  Batches and the serving queue do not check */
+  TSQS_OPT_PRESORT = 10      /* 1 (default) = before the first pass of an array that
+                                needs one (tsqs_sort, tsqs_sort_pairs, each array of
+                                tsqs_sort_batch), check whether it is already
+                                non-decreasing, or non-increasing (then reverse it in
+                                place, payloads too): such an array needs no pass (the
+                                sorted / reversed handlers, SIII.I); 0 = off.  The
+                                serving queue does not check */
 };
 
 #define TSQS_MAX_LEVELS 192
@@ -107,8 +108,9 @@ typedef struct {
   double partition_ms;           /* sum of level_ms */
   uint64_t partition_bytes;      /* algorithmic bytes: 2 * keys * (key+payload bytes) */
   uint32_t partition_launches;   /* partition kernel launches (one per level with parts) */
-  uint32_t presorted;            /* 0; 1 = found non-decreasing, 2 = found non-increasing
-                                    and reversed (TSQS_OPT_PRESORT): no pass was needed */
+  uint32_t presorted;            /* single array: 0; 1 = found non-decreasing, 2 = found
+                                    non-increasing and reversed (TSQS_OPT_PRESORT): no pass
+                                    was needed.  Batch: arrays found in order */
 } tsqs_stats_t;
 
 /* Sort nmemb keys of type dt at device pointer d_keys, in place.

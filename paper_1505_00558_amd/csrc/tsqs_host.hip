@@ -250,7 +250,7 @@ int run_t(Workspace &w, void *keys, uint32_t *vals, const uint64_t *h_offs, size
   c.nroots = (uint32_t)nroots;
   c.small_max = small_max;
   c.wave_max = wave_max;
-  c.pad0 = 0;
+  c.presort_roots = (g_opt.presort && h_offs) ? 1u : 0u;   // batches: each array by its wave
   c.samples = (uint32_t)g_opt.samples;
   c.depth_factor = (uint32_t)g_opt.depth_factor;
   c.pivot_mode = (uint32_t)g_opt.pivot_mode;
@@ -354,7 +354,7 @@ int run_t(Workspace &w, void *keys, uint32_t *vals, const uint64_t *h_offs, size
     st.small_parts += sp[kStSmallParts];
     st.small_keys += sp[kStSmallKeys];
     st.band_keys += sp[kStBandKeys];
-    st.presorted += (uint32_t)sp[kStPresorted];
+    st.presorted += (uint32_t)(sp[kStPresorted] + sp[kStPresortedRoots]);
   }
   for (int i = 0; i < d; i++)
     if (w.h_lvl[i].packed >> 40) st.max_depth = (uint32_t)i;

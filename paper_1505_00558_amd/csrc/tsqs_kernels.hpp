@@ -64,7 +64,8 @@ constexpr unsigned long long kTileMask = (1ull << 40) - 1;
 constexpr int kCtrStride = 16;   // u64 words between part counters: one 128-byte line each
 constexpr int kStripes = 64;     // statistics counters are spread over this many lines
 constexpr int kStatWords = 16;
-enum { kStFallback = 0, kStSmallParts = 1, kStSmallKeys = 2, kStBandKeys = 3, kStPresorted = 4 };
+enum { kStFallback = 0, kStSmallParts = 1, kStSmallKeys = 2, kStBandKeys = 3, kStPresorted = 4,
+       kStPresortedRoots = 5 };
 constexpr uint32_t kErrSegCap = 1, kErrFinCap = 2, kErrLevel = 4, kErrCount = 8;
 
 // ---- order-preserving codes (compares are done on these, never on floats) --
@@ -224,7 +225,7 @@ struct Ctx {
   uint32_t jitter;                   // per-call sample shift
   uint32_t seg_cap;                  // part records per level; child slots are 4 * seg_cap
   uint32_t big_cap;
-  uint32_t pad0;
+  uint32_t presort_roots;            // 1: k_init checks each root for order itself (batches)
 };
 
 // ---- wave helpers ------------------------------------------------------------
@@ -660,6 +661,9 @@ __device__ inline bool presorted(const Ctx &c) {
 }
 
 constexpr int kPreNT = 256;       // threads of the presortedness kernels
+// Largest array of a batch that its wave checks (one wave streams it; a larger
+// array would hold every later level behind it).
+constexpr uint32_t kPresortRootMax = 1u << 16;
 constexpr int kPreRows = 16;      // keys per thread per chunk (one row = kPreNT keys)
 
 template <int DT>
@@ -734,6 +738,84 @@ __global__ __launch_bounds__(kPreNT) void k_presort_reverse(Ctx c) {
   }
 }
 
+// The same check for one root by one wave (batches: many arrays, one wave each):
+// the 64-key guess, then every adjacent pair until one is against it; a
+// non-increasing root is reversed in place.  Returns 0, 1 (non-decreasing) or 2
+// (was non-increasing, now reversed).
+template <int DT, bool HASV>
+__device__ inline uint32_t wave_presort_root(const Ctx &c, uint64_t off, uint32_t len) {
+  using B = typename Codec<DT>::B;
+  using Cm = typename Codec<DT>::C;
+  B *K = (B *)c.K + off;
+  const uint32_t lane = lane_id();
+  uint32_t mode;
+  {
+    const uint32_t pos = (uint32_t)((uint64_t)lane * (len - 1) / (kWave - 1));
+    const B x = K[pos];
+    const B z = shfl_any_down1<B>(x);
+    const Cm a = Codec<DT>::ckey(x), b = Codec<DT>::ckey(z);
+    const bool up = wave_ballot(a > b) == 0ull, down = wave_ballot(a < b) == 0ull;
+    mode = up ? 1u : (down ? 2u : 0u);
+  }
+  if (mode == 0u) return 0u;
+  const uint32_t wkeys = (uint32_t)kWave * kPreRows;
+  for (uint32_t base = 0; base < len; base += wkeys) {
+    B x[kPreRows];
+#pragma unroll
+    for (int r = 0; r < kPreRows; r++) {
+      const uint32_t i = base + (uint32_t)r * kWave + lane;
+      x[r] = i < len ? K[i] : B(0);
+    }
+    const B after = base + wkeys < len ? K[base + wkeys] : B(0);
+    bool bad = false;
+#pragma unroll
+    for (int r = 0; r < kPreRows; r++) {
+      const uint32_t i = base + (uint32_t)r * kWave + lane;
+      B nb = shfl_any_down1<B>(x[r]);
+      const B first_next = r + 1 < kPreRows ? shfl_first<B>(x[r + 1 < kPreRows ? r + 1 : r]) : after;
+      if (lane == 63u) nb = first_next;
+      if (i + 1 < len) {
+        const Cm a = Codec<DT>::ckey(x[r]), b = Codec<DT>::ckey(nb);
+        bad |= mode == 1u ? a > b : a < b;
+      }
+    }
+    if (wave_ballot(bad) != 0ull) return 0u;
+  }
+  if (mode == 2u) {
+    // kRevU pairs per lane in flight: all loads of a step before its stores
+    constexpr int kRevU = 8;
+    const uint32_t half = len / 2;
+    for (uint32_t i0 = 0; i0 < half; i0 += kWave * kRevU) {
+      B a[kRevU], b[kRevU];
+#pragma unroll
+      for (int u = 0; u < kRevU; u++) {
+        const uint32_t i = i0 + (uint32_t)u * kWave + lane;
+        if (i < half) { a[u] = K[i]; b[u] = K[len - 1 - i]; }
+      }
+#pragma unroll
+      for (int u = 0; u < kRevU; u++) {
+        const uint32_t i = i0 + (uint32_t)u * kWave + lane;
+        if (i < half) { K[i] = b[u]; K[len - 1 - i] = a[u]; }
+      }
+      if (HASV) {
+        uint32_t *V = c.V + off;
+        uint32_t va[kRevU], vb[kRevU];
+#pragma unroll
+        for (int u = 0; u < kRevU; u++) {
+          const uint32_t i = i0 + (uint32_t)u * kWave + lane;
+          if (i < half) { va[u] = V[i]; vb[u] = V[len - 1 - i]; }
+        }
+#pragma unroll
+        for (int u = 0; u < kRevU; u++) {
+          const uint32_t i = i0 + (uint32_t)u * kWave + lane;
+          if (i < half) { V[i] = vb[u]; V[len - 1 - i] = va[u]; }
+        }
+      }
+    }
+  }
+  return mode;
+}
+
 // Roots: one wave per array (workgroup-uniform iterations).  A root is depth 0,
 // lives in K, gets a one-level pass, and its small-part slot is 4 * seg_cap +
 // root index.
@@ -765,6 +847,12 @@ __global__ __launch_bounds__(kPlanNT) void k_init(Ctx c) {
         if (lane_id() == 0) {
           put_small(c, 4 * c.seg_cap + j, off, 0u, false, req);
           stat_add(c, kStPresorted, (unsigned long long)c.pre[0]);
+        }
+      } else if (c.presort_roots && len > c.small_max && len <= kPresortRootMax &&
+                 wave_presort_root<DT, HASV>(c, off, len) != 0u) {
+        if (lane_id() == 0) {
+          put_small(c, 4 * c.seg_cap + j, off, 0u, false, req);
+          stat_add(c, kStPresortedRoots, 1ull);
         }
       } else
       child<DT, HASV>(c, 4 * c.seg_cap + j, off, len, 0u, c.depth_factor * lg, req, false, false, 0ull,

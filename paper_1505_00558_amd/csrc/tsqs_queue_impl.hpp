@@ -298,7 +298,7 @@ int launch_tick(tsqs_queue *q, QGroup &G) {
   c.nroots = nroots;
   c.small_max = G.geo.small_max;
   c.wave_max = G.geo.wave_max;
-  c.pad0 = 0;
+  c.presort_roots = 0;
   c.samples = (uint32_t)g_opt.samples;
   c.depth_factor = (uint32_t)g_opt.depth_factor;
   c.pivot_mode = (uint32_t)g_opt.pivot_mode;

@@ -26,8 +26,13 @@ def gpu():
         pytest.skip("no GPU")
     import paper_1505_00558_amd as tsqs
     tsqs.load_library()
+    # the cases are sized around the default small-part size (an earlier test may
+    # have left the autotuner's choice in place)
+    before = tsqs.get_option(tsqs.OPT_SMALL_MAX)
+    tsqs.set_option(tsqs.OPT_SMALL_MAX, 8192)
     yield
     tsqs.set_option(tsqs.OPT_PRESORT, 1)
+    tsqs.set_option(tsqs.OPT_SMALL_MAX, before)
 
 
 def _check(oracle_mod, k, want):
@@ -149,17 +154,39 @@ def test_option_off(oracle_mod):
         tsqs.set_option(tsqs.OPT_PRESORT, 1)
 
 
-def test_batch_does_not_check(oracle_mod):
-    """Batches sort sorted arrays through the passes (the check is per single array)."""
+def test_batch_arrays(oracle_mod):
+    """Batches: each array that needs a pass, up to 2^16 keys, is checked by its own
+    wave; arrays found in order (here: sorted, reversed, all equal) take no pass, the
+    others do."""
     import paper_1505_00558_amd as tsqs
     import torch
-    asc = _oracle_sorted(oracle_mod, "uniform", N, "int32", 20)
-    t = torch.from_numpy(asc.copy()).to("cuda:0")
-    tsqs.sort_batch(t, [0, N // 3, N])
-    torch.cuda.synchronize()
-    got = t.cpu().numpy()
-    assert tsqs.get_stats()["presorted"] == 0
-    assert np.array_equal(got[: N // 3], asc[: N // 3]) and np.array_equal(got[N // 3:], asc[N // 3:])
+    asc = (np.arange(N, dtype=np.int64) * 5 - 5 * (N // 2)).astype(np.int32)
+    uni = ti.family("uniform", N, "int32", seed=40)
+    near = asc.copy()
+    near[1000], near[1001] = near[1001], near[1000]
+    parts = [asc[:60000], asc[60000:120000][::-1], np.full(20000, 7, np.int32), uni[:200000],
+             near[:50000], asc[:3000][::-1], uni[:9000][::-1].copy(), asc[200000:400000]]
+    offs = np.cumsum([0] + [p.size for p in parts]).astype(np.uint64)
+    keys = np.concatenate(parts)
+    for presort, want in ((1, 3), (0, 0)):
+        tsqs.set_option(tsqs.OPT_PRESORT, presort)
+        try:
+            t = torch.from_numpy(keys.copy()).to("cuda:0")
+            v = torch.arange(keys.size, dtype=torch.int32, device="cuda:0")
+            tsqs.sort_batch(t, offs, vals=v)
+            torch.cuda.synchronize()
+            st = tsqs.get_stats()
+        finally:
+            tsqs.set_option(tsqs.OPT_PRESORT, 1)
+        got, gv = t.cpu().numpy(), v.cpu().numpy().astype(np.int64)
+        # found in order: 60000 sorted, 60000 reversed, 20000 equal keys (the 3000
+        # reversed keys are one small part: no pass, no check; the 200000 sorted
+        # keys are above the size a wave checks: they take the passes)
+        assert st["presorted"] == want
+        for a, b in zip(offs[:-1].tolist(), offs[1:].tolist()):
+            assert same_bits(got[a:b], oracle_mod.sort(keys[a:b]))
+            assert np.all((gv[a:b] >= a) & (gv[a:b] < b))
+        assert np.array_equal(np.sort(gv), np.arange(keys.size)) and np.array_equal(keys[gv], got)
 
 
 def test_large_arrays_skip_the_schedule(oracle_mod):
