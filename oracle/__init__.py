@@ -68,27 +68,38 @@ class Counters(ctypes.Structure):
         ("hole_errors", ctypes.c_uint64),
         ("revisit_errors", ctypes.c_uint64),
         ("internal_errors", ctypes.c_uint64),
-        ("label_hits", ctypes.c_uint64 * 64),
+        ("post_errors", ctypes.c_uint64),
+        ("events", ctypes.c_uint64 * 32),
     ]
 
     def as_dict(self) -> dict:
-        d = {f: int(getattr(self, f)) for f, _ in self._fields_ if f != "label_hits"}
-        d["label_hits"] = [int(x) for x in self.label_hits]
+        d = {f: int(getattr(self, f)) for f, _ in self._fields_ if f != "events"}
+        d["events"] = [int(x) for x in self.events]
         return d
 
 
-# label indices of oracle_counters_t.label_hits (tsqs_oracle.h)
-LABELS = [
-    "MAIN_INIT", "MAIN_R_AT_MID", "L_SCAN1", "L_EQ1", "L_GT1", "R_SCAN1", "R_EQ1",
-    "R_LT1", "MR_SCAN1", "MR_FOUND1", "ML_SCAN1", "ML_FOUND1", "CLOSE_LEFT_CHECKM",
-    "CLOSE_LEFT", "CLOSE_LEFT_NOSCAN", "CLOSE_RIGHT_CHECKM", "CLOSE_RIGHT",
-    "CLOSE_RIGHT_NOSCAN", "M_SCAN2L", "M_FOUND2L", "L_SCAN2L", "M_SCAN2R", "M_FOUND2R",
-    "R_SCAN2R", "M_SCAN3L", "M_EQ3L", "M_FOUND3L", "M_LT3L", "L_SCAN3L", "M_SCAN3R",
-    "M_EQ3R", "M_FOUND3R", "M_GT3R", "R_SCAN3R", "EXIT3L", "EXIT3R", "EXIT2", "BYPASS",
-    "SORTED", "SORTED_EQ", "SORTED_GT", "REVERSED", "REV_SWAP", "REV_GT_GT",
-    "REV_GT_EQ", "REV_LT", "REV_EQ", "REV_LEFT_DONE", "RUN3L_LONG", "RUN3R_LONG",
-    "REV_FALLBACK",
+# indices of oracle_counters_t.events (OE_* of tsqs_oracle.h): the states of
+# SIII.B-F and the outcomes of the handlers of SIII.I
+EVENTS = [
+    "STATE1", "CLOSE_BY_SIDE", "CLOSE_BY_ZONE", "STATE2L", "STATE2R", "STATE3L",
+    "STATE3R", "ROLL", "RUN_FITS", "RUN_FILLS", "COPY_BACK", "EXIT2", "BYPASS",
+    "R_AT_MID", "SORTED", "SORTED_CONFIRMED", "SORTED_FALLBACK", "REVERSED",
+    "REV_SWAP", "REV_CONFIRMED", "REV_FALLBACK",
 ]
+
+
+class Entry(ctypes.Structure):
+    """oracle_entry_t: a stage entered in the middle (States 2/3, exit2)."""
+    _fields_ = [
+        ("a", ctypes.c_int64), ("b", ctypes.c_int64), ("l", ctypes.c_int64),
+        ("r", ctypes.c_int64), ("m", ctypes.c_int64), ("ml", ctypes.c_int64),
+        ("mr", ctypes.c_int64), ("hole0", ctypes.c_int64), ("hole1", ctypes.c_int64),
+        ("entry", ctypes.c_int32), ("open_side", ctypes.c_int32), ("lc", ctypes.c_int32),
+        ("p", ctypes.c_int32), ("temp", ctypes.c_int32), ("reserved", ctypes.c_int32),
+    ]
+
+
+ENTRY_STATE2, ENTRY_STATE3, ENTRY_EXIT2 = 0, 1, 2
 
 _lib = None
 _SUFFIX = {
@@ -126,6 +137,17 @@ def _load():
     lib.oracle_insertion_i32.argtypes = [ctypes.c_void_p, ctypes.c_size_t,
                                          ctypes.POINTER(Counters)]
     lib.oracle_insertion_i32.restype = ctypes.c_int
+    lib.oracle_median5_i32.argtypes = [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32),
+                                       ctypes.POINTER(Counters)]
+    lib.oracle_median5_i32.restype = ctypes.c_int
+    lib.oracle_choose_pivot_i32.argtypes = [ctypes.c_void_p, ctypes.c_size_t,
+                                            ctypes.POINTER(Params),
+                                            ctypes.POINTER(ctypes.c_int32),
+                                            ctypes.POINTER(Counters)]
+    lib.oracle_choose_pivot_i32.restype = ctypes.c_int
+    lib.oracle_run_entry_i32.argtypes = [ctypes.c_void_p, ctypes.c_size_t,
+                                         ctypes.POINTER(Entry), ctypes.POINTER(Counters)]
+    lib.oracle_run_entry_i32.restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -207,6 +229,45 @@ def insertion(arr) -> tuple:
     c = Counters()
     _load().oracle_insertion_i32(a.ctypes.data, a.size, ctypes.byref(c))
     return a.tolist(), c
+
+
+def median5(five) -> tuple:
+    """Median of five (SIII.H, reading R4) on five int32 keys.
+
+    Returns (flag, result_list, pivot, Counters)."""
+    a = np.array(five, dtype=np.int32)
+    piv = ctypes.c_int32(0)
+    c = Counters()
+    flag = _load().oracle_median5_i32(a.ctypes.data, ctypes.byref(piv), ctypes.byref(c))
+    return flag, a.tolist(), int(piv.value), c
+
+
+def choose_pivot(arr, params: Params | None = None) -> tuple:
+    """The size-tiered pivot choice (SIII.H, SV.C) on int32 ar[0..n-1].
+
+    Returns (flag, array_after, pivot, Counters)."""
+    a = np.array(arr, dtype=np.int32)
+    piv = ctypes.c_int32(0)
+    c = Counters()
+    p = params if params is not None else default_params()
+    flag = _load().oracle_choose_pivot_i32(a.ctypes.data, a.size, ctypes.byref(p),
+                                           ctypes.byref(piv), ctypes.byref(c))
+    if flag == -2:
+        raise ValueError("choose_pivot needs n >= 3")
+    return flag, a.tolist(), int(piv.value), c
+
+
+def run_entry(arr, **fields) -> tuple:
+    """Run a stage from an entry state (oracle_entry_t fields as keywords) on
+    int32 keys.  Returns (array_after, Entry_after, Counters)."""
+    a = np.array(arr, dtype=np.int32)
+    e = Entry()
+    for k, v in fields.items():
+        setattr(e, k, v)
+    c = Counters()
+    rc = _load().oracle_run_entry_i32(a.ctypes.data, a.size, ctypes.byref(e), ctypes.byref(c))
+    _check_rc(rc)
+    return a.tolist(), e, c
 
 
 def total_order_key(bits: np.ndarray) -> np.ndarray:

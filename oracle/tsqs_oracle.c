@@ -17,8 +17,17 @@
  *        SIII.I (tests/golden/median3_counts.txt).
  *   oracle_insertion_i32 pinned: comparisons and copies equal the closed form
  *        in the inversion table that the SIV listing implies.
- *   median of five, ninther, fifteenther: parity unpinned beyond exactness of
- *        the median (their code is not printed in the paper).
+ *   oracle_median5_i32   pinned: for every permutation and every weak ordering
+ *        of five keys, the samples end sorted in place, the pivot is the third
+ *        smallest and the flag follows the order of the input.  Its comparison
+ *        and copy counts: parity unpinned (the paper's generated tree is not
+ *        printed, reading R4).
+ *   oracle_choose_pivot_i32  pinned: sample positions of the ninther and the
+ *        fifteenther worked out by hand (with and without the jitter of SV.C)
+ *        on arrays that hold distinct values only there; the pivot is the
+ *        median of the medians and the flag follows reading R5.
+ *   oracle_run_entry_i32 pinned: hand-traced entry states of States 2L/2R,
+ *        3L/3R and exit2 (tests/golden/stage_traces.txt).
  */
 #include "tsqs_oracle.h"
 
@@ -305,4 +314,87 @@ int oracle_insertion_i32(int32_t *ar, size_t n, oracle_counters_t *cnt) {
   c.n = n;
   insertion_i32(&c, 0, (ptrdiff_t)n - 1);
   return 0;
+}
+
+int oracle_median5_i32(int32_t *ar5, int32_t *piv, oracle_counters_t *cnt) {
+  ctx_i32 c;
+  oracle_params_t q;
+  ptrdiff_t pos[5] = {0, 1, 2, 3, 4};
+  int flag;
+  oracle_default_params(&q);
+  memset(&c, 0, sizeof c);
+  memset(cnt, 0, sizeof *cnt);
+  c.ar = ar5;
+  c.prm = &q;
+  c.cnt = cnt;
+  c.n = 5;
+  flag = median5_i32(&c, pos, 1);
+  *piv = c.p;
+  return flag;
+}
+
+int oracle_choose_pivot_i32(int32_t *ar, size_t n, const oracle_params_t *prm, int32_t *piv,
+                            oracle_counters_t *cnt) {
+  ctx_i32 c;
+  int flag;
+  memset(&c, 0, sizeof c);
+  memset(cnt, 0, sizeof *cnt);
+  if (!ar || !prm || n < 3) return -2;
+  c.ar = ar;
+  c.prm = prm;
+  c.cnt = cnt;
+  c.n = n;
+  c.zgen = prm->seed & 0x7FFFFFFFu;
+  if (c.zgen == 0) c.zgen = 1;
+  c.zgen = pm_step_i32(c.zgen);
+  c.dran = 0.5 + (double)c.zgen / 2147483648.0;
+  flag = choose_pivot_i32(&c, 0, (ptrdiff_t)n - 1, ((ptrdiff_t)n - 1) >> 1);
+  *piv = c.p;
+  return flag;
+}
+
+int oracle_run_entry_i32(int32_t *ar, size_t n, oracle_entry_t *e, oracle_counters_t *cnt) {
+  ctx_i32 c;
+  frm_i32 f;
+  oracle_params_t q;
+  int32_t *tar;
+  int rc = 0;
+  memset(cnt, 0, sizeof *cnt);
+  if (!ar || !e || n < 2 || e->a < 0 || e->b >= (int64_t)n || e->a > e->b) return -1;
+  oracle_default_params(&q);
+  memset(&c, 0, sizeof c);
+  tar = (int32_t *)malloc((n / 2 + 1) * sizeof(int32_t));
+  c.hole = (unsigned char *)calloc(n, 1);
+  if (!tar || !c.hole) { free(tar); free(c.hole); return -3; }
+  c.ar = ar;
+  c.tar = tar;
+  c.tar_cap = (ptrdiff_t)(n / 2 + 1);
+  c.prm = &q;
+  c.cnt = cnt;
+  c.n = n;
+  c.p = e->p;
+  c.temp = e->temp;
+  c.hole[e->hole0] = 1;
+  c.hole[e->hole1] = 1;
+  f.a = e->a; f.b = e->b; f.mid = e->a + ((e->b - e->a) >> 1);
+  f.l = e->l; f.r = e->r; f.m = e->m; f.ml = e->ml; f.mr = e->mr;
+  f.lc = e->lc;
+  f.pivot_at_mid = 0;
+  c.lo = e->a; c.hi = e->b;
+  c.budget = 64 * (int64_t)(e->b - e->a + 1) + 256;
+  if (setjmp(c.bail)) {
+    rc = -2;
+  } else {
+    c.armed = 1;
+    if (e->entry == OR_STATE2) state2_i32(&c, &f, e->open_side ? HI : LO);
+    else if (e->entry == OR_STATE3) state3_i32(&c, &f, e->open_side ? HI : LO);
+    if (e->entry == OR_STATE2 || e->entry == OR_STATE3 || e->entry == OR_EXIT2) exit2_i32(&c, &f);
+    else rc = -1;
+    c.armed = 0;
+  }
+  e->l = f.l; e->r = f.r; e->m = f.m; e->ml = f.ml; e->mr = f.mr;
+  for (int64_t x = 0; x < (int64_t)n; x++) if (c.hole[x]) cnt->hole_errors++;
+  free(tar);
+  free(c.hole);
+  return rc;
 }

@@ -50,18 +50,23 @@ typedef struct {
   int32_t reserved;
 } oracle_params_t;
 
-/* Indices into oracle_counters_t.label_hits (one per state / handler branch). */
+/* Indices into oracle_counters_t.events: coverage of the states of SIII.B-F
+ * and of the outcomes of the handlers of SIII.I. */
 enum {
-  OL_MAIN_INIT = 0, OL_MAIN_R_AT_MID, OL_L_SCAN1, OL_L_EQ1, OL_L_GT1, OL_R_SCAN1,
-  OL_R_EQ1, OL_R_LT1, OL_MR_SCAN1, OL_MR_FOUND1, OL_ML_SCAN1, OL_ML_FOUND1,
-  OL_CLOSE_LEFT_CHECKM, OL_CLOSE_LEFT, OL_CLOSE_LEFT_NOSCAN, OL_CLOSE_RIGHT_CHECKM,
-  OL_CLOSE_RIGHT, OL_CLOSE_RIGHT_NOSCAN, OL_M_SCAN2L, OL_M_FOUND2L, OL_L_SCAN2L,
-  OL_M_SCAN2R, OL_M_FOUND2R, OL_R_SCAN2R, OL_M_SCAN3L, OL_M_EQ3L, OL_M_FOUND3L,
-  OL_M_LT3L, OL_L_SCAN3L, OL_M_SCAN3R, OL_M_EQ3R, OL_M_FOUND3R, OL_M_GT3R,
-  OL_R_SCAN3R, OL_EXIT3L, OL_EXIT3R, OL_EXIT2, OL_BYPASS, OL_SORTED, OL_SORTED_EQ,
-  OL_SORTED_GT, OL_REVERSED, OL_REV_SWAP, OL_REV_GT_GT, OL_REV_GT_EQ, OL_REV_LT,
-  OL_REV_EQ, OL_REV_LEFT_DONE, OL_RUN3L_LONG, OL_RUN3R_LONG, OL_REV_FALLBACK,
-  OL_COUNT
+  OE_STATE1 = 0,        /* State 1 entered (SIII.B) */
+  OE_CLOSE_BY_SIDE,     /* l or r met the zone (State 1's empty zone slot moved there) */
+  OE_CLOSE_BY_ZONE,     /* the zone met l or r */
+  OE_STATE2L, OE_STATE2R, OE_STATE3L, OE_STATE3R,   /* SIII.C choices */
+  OE_ROLL,              /* State 2: the zone rolled by one slot (SIII.D) */
+  OE_RUN_FITS,          /* State 3: a run of keys copied whole into the gap (SIII.E) */
+  OE_RUN_FILLS,         /* State 3: the gap closed before the run ended */
+  OE_COPY_BACK,         /* tar[] copied back (SIII.F) */
+  OE_EXIT2,             /* temp and p put back (SIII.F) */
+  OE_BYPASS,            /* stage ended with temp unused */
+  OE_R_AT_MID,          /* initialization: every key right of mid above p (R7) */
+  OE_SORTED, OE_SORTED_CONFIRMED, OE_SORTED_FALLBACK,             /* SIII.I */
+  OE_REVERSED, OE_REV_SWAP, OE_REV_CONFIRMED, OE_REV_FALLBACK,    /* SIII.I */
+  OE_COUNT
 };
 
 typedef struct {
@@ -75,8 +80,10 @@ typedef struct {
   uint64_t tar_peak;        /* largest fill of tar[] in one stage */
   uint64_t hole_errors;     /* debug: read of an empty slot / overwrite of a live slot */
   uint64_t revisit_errors;  /* debug: comparison touching a finalized element */
-  uint64_t internal_errors; /* watchdog or invariant failure */
-  uint64_t label_hits[64];
+  uint64_t internal_errors; /* watchdog: a slot outside the stage, too many comparisons, tar[] overflow */
+  uint64_t post_errors;     /* debug: a stage whose result is not a three-way partition
+                               around its pivot of the multiset it was given */
+  uint64_t events[32];      /* OE_* */
 } oracle_counters_t;
 
 void oracle_default_params(oracle_params_t *prm);
@@ -106,6 +113,34 @@ int oracle_tsqs_sort_pairs_f32(uint32_t *keys, uint32_t *vals, size_t n, const o
 int oracle_median3_i32(int32_t *ar3, int32_t *piv, oracle_counters_t *cnt);
 /* Insertion sort with direct copies (SIV) on ar[0..n-1]. */
 int oracle_insertion_i32(int32_t *ar, size_t n, oracle_counters_t *cnt);
+
+/* Median of five (SIII.H; reading R4) on ar5[0..4]: sorts them in place,
+ * stores the median (ar5[2]) in *piv; returns 1 / -1 / 0 as MedianOf3S. */
+int oracle_median5_i32(int32_t *ar5, int32_t *piv, oracle_counters_t *cnt);
+/* The size-tiered pivot choice of SIII.H / SV.C on ar[0..n-1] (n >= 3) with
+ * the tiers and jitter of prm (one generator step from prm->seed, as at the
+ * start of a sort call): permutes the samples in place, stores the pivot in
+ * *piv and returns the sorted / reversed flag. */
+int oracle_choose_pivot_i32(int32_t *ar, size_t n, const oracle_params_t *prm, int32_t *piv,
+                            oracle_counters_t *cnt);
+
+/* Entry into the middle of a stage, for hand-traced checks of States 2L/2R,
+ * 3L/3R and exit2 (SIII.D-F).  The caller gives the array, the pointers, the
+ * pivot p, temp, the two empty slots, and for States 2 / 3 the comparison lc
+ * of the key m stands on (m_scan..._2 of the paper: the entry after SIII.C).
+ * The state runs to its end, then exit2; l and r come back as the bounds of
+ * the children [a..l] and [r..b].  Empty slots are checked (hole_errors). */
+enum { OR_STATE2 = 0, OR_STATE3 = 1, OR_EXIT2 = 2 };
+typedef struct {
+  int64_t a, b, l, r, m, ml, mr;
+  int64_t hole0, hole1;     /* the two empty slots at entry */
+  int32_t entry;            /* OR_* */
+  int32_t open_side;        /* 0: m moves toward l (2L, 3L); 1: toward r (2R, 3R) */
+  int32_t lc;               /* cmp(ar[m], p) at entry (States 2 and 3) */
+  int32_t p, temp;
+  int32_t reserved;
+} oracle_entry_t;
+int oracle_run_entry_i32(int32_t *ar, size_t n, oracle_entry_t *e, oracle_counters_t *cnt);
 
 #ifdef __cplusplus
 }

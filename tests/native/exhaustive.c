@@ -9,9 +9,11 @@
  *   - the ids form a permutation and key_in[id_out[i]] == key_out[i];
  *   - no empty-slot misuse (hole_errors == 0), no comparison touching an
  *     element of a finished equal band (revisit_errors == 0, the paper's
- *     "never compared again", SIII), tar[] never above n/2 (SIII.G), and no
- *     internal error.
- * Prints one JSON line with totals and per-label hit counts (coverage).
+ *     "never compared again", SIII), tar[] never above n/2 (SIII.G), every
+ *     stage's result a three-way partition of its own keys (post_errors ==
+ *     0), and no internal error.
+ * Prints one JSON line with totals and per-event counts (coverage of the
+ * states and handler outcomes).
  *
  * Usage: exhaustive NMAX INS_MAX MED3_BELOW MEDOF3_SMALL HANDLERS TOL SEED [KEYS_ONLY]
  */
@@ -25,7 +27,7 @@ int main(int argc, char **argv) {
   oracle_params_t q;
   oracle_counters_t c;
   uint64_t arrays = 0, bad_keys = 0, bad_ids = 0, hole = 0, revisit = 0, internal = 0,
-           tar_over = 0, rc_bad = 0, comps = 0, copies = 0;
+           tar_over = 0, rc_bad = 0, comps = 0, copies = 0, post = 0;
   uint64_t hits[64];
   int keys_only = 0;
   if (argc < 8) {
@@ -91,7 +93,8 @@ int main(int argc, char **argv) {
       if (c.tar_peak > (uint64_t)(n / 2)) tar_over++;
       comps += c.comparisons;
       copies += c.copies;
-      for (i = 0; i < 64; i++) hits[i] += c.label_hits[i];
+      post += c.post_errors;
+      for (i = 0; i < OE_COUNT; i++) hits[i] += c.events[i];
       if ((hole || revisit || internal) && (hole + revisit + internal) < 4 && c.hole_errors + c.revisit_errors + c.internal_errors) {
         fprintf(stderr, "CHECK FAIL n=%d hole=%llu rev=%llu int=%llu in:", n,
                 (unsigned long long)c.hole_errors, (unsigned long long)c.revisit_errors,
@@ -109,12 +112,14 @@ int main(int argc, char **argv) {
   }
   printf("{\"arrays\": %llu, \"bad_keys\": %llu, \"bad_ids\": %llu, \"hole_errors\": %llu, "
          "\"revisit_errors\": %llu, \"internal_errors\": %llu, \"tar_over\": %llu, "
-         "\"rc_bad\": %llu, \"comparisons\": %llu, \"copies\": %llu, \"hits\": [",
+         "\"rc_bad\": %llu, \"post_errors\": %llu, \"comparisons\": %llu, \"copies\": %llu, "
+         "\"hits\": [",
          (unsigned long long)arrays, (unsigned long long)bad_keys, (unsigned long long)bad_ids,
          (unsigned long long)hole, (unsigned long long)revisit, (unsigned long long)internal,
-         (unsigned long long)tar_over, (unsigned long long)rc_bad, (unsigned long long)comps,
+         (unsigned long long)tar_over, (unsigned long long)rc_bad, (unsigned long long)post,
+         (unsigned long long)comps,
          (unsigned long long)copies);
-  for (i = 0; i < OL_COUNT; i++) printf("%s%llu", i ? ", " : "", (unsigned long long)hits[i]);
+  for (i = 0; i < OE_COUNT; i++) printf("%s%llu", i ? ", " : "", (unsigned long long)hits[i]);
   printf("]}\n");
   oracle_free_storage();
   return 0;

@@ -34,18 +34,37 @@ def exhaustive_bin(tmp_path_factory, oracle_mod):
     return out
 
 
+_RESULTS = {}
+
+
+def _run(exhaustive_bin, prof):
+    """One run per profile, shared by the tests of this module."""
+    if prof not in _RESULTS:
+        res = subprocess.run([exhaustive_bin] + [str(x) for x in prof], check=True,
+                             capture_output=True, text=True, timeout=300)
+        _RESULTS[prof] = (json.loads(res.stdout.strip().splitlines()[-1]), res.stderr)
+    return _RESULTS[prof]
+
+
 @pytest.mark.parametrize("prof", PROFILES, ids=lambda p: "n%d-ins%d-m3b%d-m3s%d-h%d-tol%d-s%d-k%d" % p)
 def test_exhaustive(exhaustive_bin, prof):
-    res = subprocess.run([exhaustive_bin] + [str(x) for x in prof], check=True,
-                         capture_output=True, text=True, timeout=300)
-    r = json.loads(res.stdout.strip().splitlines()[-1])
+    r, err = _run(exhaustive_bin, prof)
     expected_arrays = sum(n ** n for n in range(1, prof[0] + 1))
     assert r["arrays"] == expected_arrays
     for key in ("bad_keys", "bad_ids", "hole_errors", "revisit_errors", "internal_errors",
-                "tar_over", "rc_bad"):
-        assert r[key] == 0, (key, r[key], res.stderr[:2000])
+                "tar_over", "rc_bad", "post_errors"):
+        assert r[key] == 0, (key, r[key], err[:2000])
 
 
 def test_exhaustive_sum_is_known():
     # sum_{n=1..8} n^n, the count of arrays the full profile checks
     assert sum(n ** n for n in range(1, 9)) == 17650828
+
+
+def test_exhaustive_reaches_every_state(exhaustive_bin):
+    """The full profile reaches every state and handler outcome on n <= 8."""
+    import oracle
+    hits = _run(exhaustive_bin, PROFILES[0])[0]["hits"]
+    hits2 = _run(exhaustive_bin, PROFILES[3])[0]["hits"]
+    missing = [nm for i, nm in enumerate(oracle.EVENTS) if hits[i] + hits2[i] == 0]
+    assert not missing, missing

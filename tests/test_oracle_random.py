@@ -4,8 +4,9 @@ numpy's sort is the reference for the integer orders; for float32 the
 reference is numpy's stable argsort of a totalOrder key, itself pinned by the
 hand-written fixture tests/golden/float32_total_order.txt.  Each run also
 checks the payload permutation, the n/2 bound on tar[] (SIII.G), the empty-slot
-shadow and the never-revisited tags (SIII), and across the whole module that
-every state of the partition and both handlers were reached.
+shadow, the never-revisited tags (SIII) and the three-way partition of every
+stage, and across the whole module that every state of the partition and
+every handler outcome was reached.
 """
 import os
 
@@ -41,6 +42,7 @@ def test_random_pairs(oracle_mod, dtype, fam, n):
     assert np.array_equal(np.sort(vo), v)
     assert np.array_equal(_bits(k)[vo], _bits(ko))
     assert c.hole_errors == 0 and c.revisit_errors == 0 and c.internal_errors == 0
+    assert c.post_errors == 0
     assert c.tar_peak <= n // 2
 
 
@@ -52,24 +54,24 @@ def test_keys_only_large(oracle_mod, dtype):
     assert np.array_equal(_bits(out), _bits(_reference(oracle_mod, k)))
 
 
-def test_all_labels_reached(oracle_mod):
-    """Every state of the partition and every handler branch is exercised."""
-    hits = np.zeros(64, dtype=np.int64)
+def test_all_states_reached(oracle_mod):
+    """Every state of the partition and every handler outcome is exercised."""
+    hits = np.zeros(32, dtype=np.int64)
     for dtype in ("int32", "float32"):
         for fam in ti.FAMILIES:
             for n in (13, 70, 801, 30001, 65537):
                 k = ti.family(fam, n, dtype, seed=ti.seed_for(0, fam) + 31 * n)
                 p = oracle_mod.default_params(seed=n)
                 _, c = oracle_mod.sort(k, p, counters=True)
-                hits += np.array(c.label_hits, dtype=np.int64)
+                hits += np.array(c.events, dtype=np.int64)
     for tol in (0, 1):
         for n in (9, 10, 11, 12, 100, 1000):
             k = ti.family("reversed", n, "int32")
             k[[0, n // 3]] = k[[n // 3, 0]]
             p = oracle_mod.default_params(ins_max=2, reverse_tolerance=tol)
             _, c = oracle_mod.sort(k, p, counters=True)
-            hits += np.array(c.label_hits, dtype=np.int64)
-    missing = [nm for i, nm in enumerate(oracle_mod.LABELS) if hits[i] == 0]
+            hits += np.array(c.events, dtype=np.int64)
+    missing = [nm for i, nm in enumerate(oracle_mod.EVENTS) if hits[i] == 0]
     assert not missing, missing
 
 
