@@ -1,16 +1,10 @@
-// tsqs_host.hip -- host driver and C ABI of libtsqs (see include/tsqs.h).
-//
-// One call = one schedule on the caller's stream:
-//   k_reset, [upload of batch offsets], k_init (roots: pivot or small item),
-//   then per level d: k_partition(d), k_plan(d), k_finish(d),
-// launched without host synchronisation for the number of levels a median
-// split needs (ceil(log2(n / small_max)) + 2); the stream is then synchronised
-// once, and only if parts remain (bad pivots, the depth-limit path) more levels
-// are launched, eight at a time.
-#include "tsqs.h"
-#include "tsqs_kernels.hpp"
+// tsqs_host.hip -- C ABI of libtsqs (include/tsqs.h, include/tsqs_queue.h):
+// argument checks, options, the per-device workspace, statistics, the records
+// entry point, the autotuner and the serving queue.  The launch schedule of
+// each key type is in tsqs_dt.hip.
+#include "tsqs_host.hpp"
+#include "tsqs_queue_state.hpp"
 #include "tsqs_records.hpp"
-#include "tsqs_queue.h"
 
 #include <hip/hip_runtime.h>
 
@@ -25,51 +19,20 @@
 #include <unordered_map>
 #include <vector>
 
+namespace tsqs {
+namespace host {
+Options g_opt;
+std::mutex g_mu;
+tsqs_stats_t g_stats;
+bool g_have_stats = false;
+uint64_t g_calls = 0;
+}  // namespace host
+}  // namespace tsqs
+
 using namespace tsqs;
+using namespace tsqs::host;
 
 namespace {
-
-// Arrays of at least this many keys synchronise once after the presortedness
-// check (about 10-20 us) so that an array found in order skips the level schedule.
-constexpr uint64_t kPresortSyncMin = 1ull << 24;
-
-struct Options {
-  int64_t small_max = 8192;
-  int64_t samples = 63;
-  int64_t depth_factor = 2;
-  int64_t pivot_mode = 0;
-  int64_t seed = 0x5EED1505;
-  int64_t timing = 0;
-  int64_t part_grid = 0;
-  int64_t finish_grid = 0;
-  int64_t finish_algo = 3;
-  int64_t presort = 1;
-};
-
-struct Workspace {
-  bool init = false;
-  int cus = 0;
-  size_t s_bytes = 0;
-  void *S = nullptr;
-  size_t v_cap = 0;
-  uint32_t *VS = nullptr, *VE = nullptr;
-  size_t lds_budget = 0;
-  size_t seg_cap = 0;
-  Seg *seg[2] = {nullptr, nullptr};
-  unsigned long long *ctr[2] = {nullptr, nullptr};
-  size_t slot_cap = 0, band_cap = 0, big_cap = 0;
-  FinItem *fin = nullptr, *finw = nullptr, *band = nullptr, *big = nullptr;
-  LevelCtl *lvl = nullptr;
-  unsigned long long *stats = nullptr;   // kStripes x kStatWords, then one word of error flags
-  size_t off_cap = 0;
-  uint64_t *offs = nullptr;
-  LevelCtl *h_lvl = nullptr;             // pinned
-  unsigned long long *h_stats = nullptr; // pinned
-  hipEvent_t ev[2 * kMaxLevels];
-  bool ev_ok = false;
-};
-
-std::mutex g_mu;
 
 // Buffers of tsqs_sort_records per device: the index (the sorted "pointer array"),
 // the staging buffer of an in-place gather, and an error word.
@@ -84,28 +47,7 @@ struct RecWs {
 };
 std::mutex g_rec_mu;
 std::vector<RecWs> g_rec;
-Options g_opt;
 std::vector<Workspace> g_ws;
-tsqs_stats_t g_stats;
-bool g_have_stats = false;
-uint64_t g_calls = 0;
-
-#define HIPCHK(expr)                                   \
-  do {                                                 \
-    hipError_t e_ = (expr);                            \
-    if (e_ != hipSuccess) return TSQS_EDEVICE;         \
-  } while (0)
-
-template <typename T>
-int grow(T **p, size_t *cap, size_t need, size_t elem = sizeof(T)) {
-  if (*cap >= need) return TSQS_OK;
-  if (*p) { (void)hipFree(*p); *p = nullptr; *cap = 0; }
-  void *q = nullptr;
-  if (hipMalloc(&q, need * elem) != hipSuccess) { (void)hipGetLastError(); return TSQS_ENOMEM; }
-  *p = static_cast<T *>(q);
-  *cap = need;
-  return TSQS_OK;
-}
 
 void free_ws(Workspace &w) {
   (void)hipFree(w.S); (void)hipFree(w.VS); (void)hipFree(w.VE);
@@ -132,246 +74,70 @@ int ensure_static(Workspace &w, int dev) {
   return TSQS_OK;
 }
 
-size_t lds_pad_host(size_t x) { return x + (x >> 5); }
-
-uint32_t ceil_log2(uint64_t x) {
-  uint32_t l = 0;
-  while (l < 64 && (1ull << l) < x) l++;
-  return l;
-}
-
-uint32_t mix32(uint64_t z) {
-  z += 0x9E3779B97F4A7C15ull;
-  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
-  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
-  return (uint32_t)(z ^ (z >> 31));
-}
-
-// Small-part geometry of a key type: one wave sorts up to wave_max keys, the
-// workgroup up to small_max (the option, clipped to what registers and LDS
-// hold); fin_lds is the dynamic LDS of the finish kernel.
-struct FinGeom {
-  uint32_t small_max, wave_max;
-  size_t fin_lds;
-};
-
-template <int DT, bool HASV>
-FinGeom fin_geom(size_t lds_budget, int64_t small_opt) {
-  using B = typename Codec<DT>::B;
-  using RT = typename Rec<B, HASV>::T;
-  const uint32_t me = (uint32_t)max_e<RT>();
-  uint32_t wave_max = 64 * me;
-  while (wave_max > 64 && kFinNW * lds_pad_host(wave_max) * sizeof(RT) > lds_budget) wave_max >>= 1;
-  uint32_t wg_max = kFinNT * me;
-  while (wg_max > wave_max && lds_pad_host(wg_max) * sizeof(RT) > lds_budget) wg_max >>= 1;
-  uint32_t small_max = (uint32_t)small_opt;
-  if (small_max > wg_max) small_max = wg_max;
-  if (small_max < 16) small_max = 16;
-  uint32_t P = 1;
-  while (P < small_max) P <<= 1;
-  size_t fin_lds = lds_pad_host(P) * sizeof(RT);
-  if (kFinNW * lds_pad_host(wave_max) * sizeof(RT) > fin_lds) fin_lds = kFinNW * lds_pad_host(wave_max) * sizeof(RT);
-  return FinGeom{small_max, wave_max, fin_lds};
-}
-
-template <int DT, bool HASV>
-int run_t(Workspace &w, void *keys, uint32_t *vals, const uint64_t *h_offs, size_t nroots,
-          uint64_t n, uint64_t max_root, hipStream_t s) {
-  using B = typename Codec<DT>::B;
-  const size_t kb = sizeof(B);
-  if (((uintptr_t)keys % kb) != 0 || ((uintptr_t)vals % 4) != 0) return TSQS_EINVAL;
-  const FinGeom geo = fin_geom<DT, HASV>(w.lds_budget, g_opt.small_max);
-  const uint32_t small_max = geo.small_max, wave_max = geo.wave_max;
-
-  // workspace sizes
-  const size_t seg_cap = (size_t)(n / (small_max + 1)) + 2;
-  const size_t slot_cap = 4 * seg_cap + nroots;   // 4 child slots per part, then the roots
-  const size_t big_cap = 2 * (size_t)(n / kBandChunk) + 16;
+// Workspace buffers of the allocating entry points, grown to what the call needs.
+int ws_grow(Workspace &w, const WsNeed &nd, bool hasv, WsView *v) {
   int rc;
   {
     size_t cap_bytes = w.s_bytes;
     void *S = w.S;
-    if ((rc = grow<unsigned char>((unsigned char **)&S, &cap_bytes, (size_t)n * kb)) != TSQS_OK) return rc;
+    if ((rc = grow<unsigned char>((unsigned char **)&S, &cap_bytes, nd.s_bytes)) != TSQS_OK) return rc;
     w.S = S; w.s_bytes = cap_bytes;
   }
-  if (HASV) {
+  if (hasv) {
     size_t c1 = w.v_cap, c2 = w.v_cap;
-    if ((rc = grow(&w.VS, &c1, (size_t)n)) != TSQS_OK) return rc;
-    if ((rc = grow(&w.VE, &c2, (size_t)n)) != TSQS_OK) return rc;
+    if ((rc = grow(&w.VS, &c1, nd.v_elems)) != TSQS_OK) return rc;
+    if ((rc = grow(&w.VE, &c2, nd.v_elems)) != TSQS_OK) return rc;
     w.v_cap = c1 < c2 ? c1 : c2;
   }
-  if (w.seg_cap < seg_cap) {
+  if (w.seg_cap < nd.seg_cap) {
     for (int i = 0; i < 2; i++) {
       size_t a = w.seg_cap, b = w.seg_cap * kCtrStride;
-      if ((rc = grow(&w.seg[i], &a, seg_cap)) != TSQS_OK) return rc;
-      if ((rc = grow(&w.ctr[i], &b, seg_cap * kCtrStride)) != TSQS_OK) return rc;
+      if ((rc = grow(&w.seg[i], &a, nd.seg_cap)) != TSQS_OK) return rc;
+      if ((rc = grow(&w.ctr[i], &b, nd.seg_cap * kCtrStride)) != TSQS_OK) return rc;
     }
-    w.seg_cap = seg_cap;
+    w.seg_cap = nd.seg_cap;
   }
-  if (w.slot_cap < slot_cap) {
+  if (w.slot_cap < nd.slot_cap) {
     size_t a = w.slot_cap, b = w.slot_cap;
-    if ((rc = grow(&w.fin, &a, slot_cap)) != TSQS_OK) return rc;
-    if ((rc = grow(&w.finw, &b, slot_cap)) != TSQS_OK) return rc;
-    w.slot_cap = slot_cap;
+    if ((rc = grow(&w.fin, &a, nd.slot_cap)) != TSQS_OK) return rc;
+    if ((rc = grow(&w.finw, &b, nd.slot_cap)) != TSQS_OK) return rc;
+    w.slot_cap = nd.slot_cap;
   }
-  if ((rc = grow(&w.band, &w.band_cap, 3 * seg_cap)) != TSQS_OK) return rc;
-  if ((rc = grow(&w.big, &w.big_cap, big_cap)) != TSQS_OK) return rc;
-  if (h_offs) {
-    if ((rc = grow(&w.offs, &w.off_cap, nroots + 1)) != TSQS_OK) return rc;
-    HIPCHK(hipMemcpyAsync(w.offs, h_offs, (nroots + 1) * sizeof(uint64_t), hipMemcpyHostToDevice, s));
-  }
+  if ((rc = grow(&w.band, &w.band_cap, nd.band_cap)) != TSQS_OK) return rc;
+  if ((rc = grow(&w.big, &w.big_cap, nd.big_cap)) != TSQS_OK) return rc;
+  if (nd.offs && (rc = grow(&w.offs, &w.off_cap, nd.offs)) != TSQS_OK) return rc;
   if (g_opt.timing && !w.ev_ok) {
     for (int i = 0; i < 2 * kMaxLevels; i++) HIPCHK(hipEventCreate(&w.ev[i]));
     w.ev_ok = true;
   }
-
-  Ctx c;
-  c.K = keys; c.S = w.S;
-  c.V = vals; c.VS = w.VS; c.VE = w.VE;
-  c.seg0 = w.seg[0]; c.seg1 = w.seg[1];
-  c.ctr0 = w.ctr[0]; c.ctr1 = w.ctr[1];
-  c.fin = w.fin; c.finw = w.finw; c.band = w.band; c.big = w.big; c.lvl = w.lvl;
-  c.stats = w.stats;
-  c.err = (unsigned int *)(w.stats + kStripes * kStatWords);
-  // the presortedness check of a single array that needs a pass
-  c.pre = (g_opt.presort && !h_offs && n > small_max)
-              ? (unsigned int *)(w.stats + kStripes * kStatWords + 8) : nullptr;
-  c.roots = h_offs ? w.offs : nullptr;
-  c.root_recs = nullptr;
-  c.req_left = nullptr;
-  c.req_flag = nullptr;
-  c.done_ring = nullptr;
-  c.done_pos = nullptr;
-  c.done_cap = 0;
-  c.pad1 = 0;
-  c.root_level = 0;
-  c.ring = 0;
-  c.n = n;
-  c.nroots = (uint32_t)nroots;
-  c.small_max = small_max;
-  c.wave_max = wave_max;
-  c.presort_roots = (g_opt.presort && h_offs) ? 1u : 0u;   // batches: each array by its wave
-  c.samples = (uint32_t)g_opt.samples;
-  c.depth_factor = (uint32_t)g_opt.depth_factor;
-  c.pivot_mode = (uint32_t)g_opt.pivot_mode;
-  c.jitter = mix32((uint64_t)g_opt.seed + (g_calls++));
-  c.seg_cap = (uint32_t)seg_cap;
-  c.big_cap = (uint32_t)big_cap;
-
-  const int part_grid = g_opt.part_grid > 0 ? (int)g_opt.part_grid : 4 * w.cus;
-  const int fin_grid = g_opt.finish_grid > 0 ? (int)g_opt.finish_grid : 8 * w.cus;
-  const int plan_grid = 4 * w.cus;
-  const size_t fin_lds = geo.fin_lds;
-  if (fin_lds > 65536) {
-    HIPCHK(hipFuncSetAttribute((const void *)k_finish<DT, HASV, 0>,
-                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)fin_lds));
-    HIPCHK(hipFuncSetAttribute((const void *)k_finish<DT, HASV, 1>,
-                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)fin_lds));
-    HIPCHK(hipFuncSetAttribute((const void *)k_finish<DT, HASV, 2>,
-                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)fin_lds));
-    HIPCHK(hipFuncSetAttribute((const void *)k_finish<DT, HASV, 3>,
-                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)fin_lds));
-  }
-  const size_t waves_init = (nroots + kPlanNW - 1) / kPlanNW;
-  int init_grid = (int)(waves_init < (size_t)(4 * w.cus) ? waves_init : (size_t)(4 * w.cus));
-  if (init_grid < 1) init_grid = 1;
-
-  hipLaunchKernelGGL(k_reset, dim3(1), dim3(256), 0, s, c);
-  if (c.pre) {
-    const uint64_t pre_chunks = (n + (uint64_t)kPreNT * kPreRows - 1) / ((uint64_t)kPreNT * kPreRows);
-    const int scan_grid = (int)(pre_chunks < (uint64_t)(8 * w.cus) ? pre_chunks : (uint64_t)(8 * w.cus));
-    hipLaunchKernelGGL((k_presort_scan<DT>), dim3(scan_grid), dim3(kPreNT), 0, s, c);
-    hipLaunchKernelGGL((k_presort_reverse<DT, HASV>), dim3(8 * w.cus), dim3(kPreNT), 0, s, c);
-  }
-  hipLaunchKernelGGL((k_init<DT, HASV>), dim3(init_grid), dim3(kPlanNT), 0, s, c);
-  HIPCHK(hipGetLastError());
-
-  // median-of-63 splits stay within about 45/55: allow 20% more levels than a
-  // perfect halving, plus two
-  // 32-bit byte offsets within a part suffice unless a part reaches 4 GiB
-  const bool wide = (uint64_t)max_root * sizeof(typename Codec<DT>::B) > 0xFFFFFFFFull;
-  const uint32_t lv = ceil_log2((max_root + small_max - 1) / small_max);
-  // every root small: level 0 has no parts, only its finish work.  The first
-  // pass is one level and the rest two levels each (with payloads too).
-  const bool roots_small = max_root <= small_max;
-  const uint32_t lv_all = lv + (lv + 4) / 5 + 2;
-  uint32_t expected = roots_small ? 1u : 2 + lv_all / 2;
-  int d = 0, target = (int)expected;
-  if (c.pre && n >= kPresortSyncMin) {
-    // a large array found in order needs none of the levels: read the two words
-    // of the check once instead of launching the whole schedule empty
-    unsigned int *hp = (unsigned int *)(w.h_stats + kStripes * kStatWords + 8);
-    HIPCHK(hipMemcpyAsync(hp, c.pre, 2 * sizeof(unsigned int), hipMemcpyDeviceToHost, s));
-    HIPCHK(hipStreamSynchronize(s));
-    if (hp[0] != 0u && hp[1] == 0u) target = 0;
-  }
-  if (target > kMaxLevels - 1) target = kMaxLevels - 1;
-  for (;;) {
-    for (; d < target; d++) {
-      const bool idle = d == 0 && roots_small;
-      if (g_opt.timing) HIPCHK(hipEventRecord(w.ev[2 * d], s));
-      if (idle) {
-      } else if (wide) {
-        hipLaunchKernelGGL((k_partition<DT, HASV, true, false>), dim3(part_grid), dim3(kPartNT1), 0, s, c, d);
-        if (d > 0)
-          hipLaunchKernelGGL((k_partition<DT, HASV, true, true>), dim3(part_grid), dim3(kPartNT2), 0, s, c, d);
-      } else {
-        hipLaunchKernelGGL((k_partition<DT, HASV, false, false>), dim3(part_grid), dim3(kPartNT1), 0, s, c, d);
-        if (d > 0)
-          hipLaunchKernelGGL((k_partition<DT, HASV, false, true>), dim3(part_grid), dim3(kPartNT2), 0, s, c, d);
-      }
-      if (g_opt.timing) HIPCHK(hipEventRecord(w.ev[2 * d + 1], s));
-      if (!idle) hipLaunchKernelGGL((k_plan<DT, HASV>), dim3(plan_grid), dim3(kPlanNT), 0, s, c, d);
-      if (g_opt.finish_algo == 0)
-        hipLaunchKernelGGL((k_finish<DT, HASV, 0>), dim3(fin_grid), dim3(kFinNT), fin_lds, s, c, d);
-      else if (g_opt.finish_algo == 1)
-        hipLaunchKernelGGL((k_finish<DT, HASV, 1>), dim3(fin_grid), dim3(kFinNT), fin_lds, s, c, d);
-      else if (g_opt.finish_algo == 2)
-        hipLaunchKernelGGL((k_finish<DT, HASV, 2>), dim3(fin_grid), dim3(kFinNT), fin_lds, s, c, d);
-      else
-        hipLaunchKernelGGL((k_finish<DT, HASV, 3>), dim3(fin_grid), dim3(kFinNT), fin_lds, s, c, d);
-      HIPCHK(hipGetLastError());
-    }
-    HIPCHK(hipMemcpyAsync(w.h_lvl, w.lvl, sizeof(LevelCtl) * (size_t)(d + 1), hipMemcpyDeviceToHost, s));
-    HIPCHK(hipMemcpyAsync(w.h_stats, w.stats, sizeof(unsigned long long) * (kStripes * kStatWords + 1),
-                          hipMemcpyDeviceToHost, s));
-    HIPCHK(hipStreamSynchronize(s));
-    if (*(unsigned int *)(w.h_stats + kStripes * kStatWords)) return TSQS_EINTERNAL;
-    if ((w.h_lvl[d].packed >> 40) == 0) break;
-    if (d >= kMaxLevels - 1) return TSQS_EINTERNAL;
-    target = d + 8 < kMaxLevels - 1 ? d + 8 : kMaxLevels - 1;
-  }
-
-  tsqs_stats_t &st = g_stats;
-  std::memset(&st, 0, sizeof st);
-  st.levels = (uint32_t)d;
-  st.n = n;
-  st.key_bytes = (uint32_t)kb;
-  st.payload_bytes = HASV ? 4u : 0u;
-  for (int i = 0; i < kStripes; i++) {
-    const unsigned long long *sp = w.h_stats + (size_t)i * kStatWords;
-    st.fallback_parts += sp[kStFallback];
-    st.small_parts += sp[kStSmallParts];
-    st.small_keys += sp[kStSmallKeys];
-    st.band_keys += sp[kStBandKeys];
-    st.presorted += (uint32_t)(sp[kStPresorted] + sp[kStPresortedRoots]);
-  }
-  for (int i = 0; i < d; i++)
-    if (w.h_lvl[i].packed >> 40) st.max_depth = (uint32_t)i;
-  for (int i = 0; i < d && i < TSQS_MAX_LEVELS; i++) {
-    st.level_keys[i] = w.h_lvl[i].keys;
-    st.level_parts[i] = (uint32_t)(w.h_lvl[i].packed >> 40);
-    st.partition_bytes += 2ull * w.h_lvl[i].keys * (kb + (HASV ? 4 : 0));
-    if (!(i == 0 && roots_small)) st.partition_launches++;
-    if (g_opt.timing) {
-      float ms = 0.f;
-      HIPCHK(hipEventElapsedTime(&ms, w.ev[2 * i], w.ev[2 * i + 1]));
-      st.level_ms[i] = ms;
-      st.partition_ms += ms;
-    }
-  }
-  g_have_stats = true;
+  v->S = w.S; v->VS = w.VS; v->VE = w.VE;
+  for (int i = 0; i < 2; i++) { v->seg[i] = w.seg[i]; v->ctr[i] = w.ctr[i]; }
+  v->fin = w.fin; v->finw = w.finw; v->band = w.band; v->big = w.big;
+  v->lvl = w.lvl; v->stats = w.stats; v->offs = w.offs;
+  v->seg_cap = nd.seg_cap; v->slot_cap = nd.slot_cap; v->big_cap = nd.big_cap;
   return TSQS_OK;
+}
+
+int sort_any(int dt, const CallEnv &env, const CallArgs &a) {
+  const bool hv = a.vals != nullptr;
+  switch (dt) {
+    case TSQS_INT32: return sort_dt<0>(env, a, hv);
+    case TSQS_UINT32: return sort_dt<1>(env, a, hv);
+    case TSQS_INT64: return sort_dt<2>(env, a, hv);
+    case TSQS_UINT64: return sort_dt<3>(env, a, hv);
+    case TSQS_FLOAT32: return sort_dt<4>(env, a, hv);
+    default: return TSQS_EUNSUPPORTED;
+  }
+}
+
+FinGeom geom_any(int dt, size_t lds, bool hasv) {
+  switch (dt) {
+    case TSQS_INT32: return geom_dt<0>(lds, hasv);
+    case TSQS_UINT32: return geom_dt<1>(lds, hasv);
+    case TSQS_INT64: return geom_dt<2>(lds, hasv);
+    case TSQS_UINT64: return geom_dt<3>(lds, hasv);
+    default: return geom_dt<4>(lds, hasv);
+  }
 }
 
 int dispatch(void *keys, uint32_t *vals, const uint64_t *h_offs, size_t nroots, uint64_t n,
@@ -385,23 +151,22 @@ int dispatch(void *keys, uint32_t *vals, const uint64_t *h_offs, size_t nroots, 
   int rc = ensure_static(w, dev);
   if (rc != TSQS_OK) return rc;
   g_have_stats = false;
+  if (!dtype_ok(dt)) return TSQS_EUNSUPPORTED;
   const bool hv = vals != nullptr;
-  switch (dt) {
-    case TSQS_INT32: return hv ? run_t<0, true>(w, keys, vals, h_offs, nroots, n, max_root, s)
-                               : run_t<0, false>(w, keys, vals, h_offs, nroots, n, max_root, s);
-    case TSQS_UINT32: return hv ? run_t<1, true>(w, keys, vals, h_offs, nroots, n, max_root, s)
-                                : run_t<1, false>(w, keys, vals, h_offs, nroots, n, max_root, s);
-    case TSQS_INT64: return hv ? run_t<2, true>(w, keys, vals, h_offs, nroots, n, max_root, s)
-                               : run_t<2, false>(w, keys, vals, h_offs, nroots, n, max_root, s);
-    case TSQS_UINT64: return hv ? run_t<3, true>(w, keys, vals, h_offs, nroots, n, max_root, s)
-                                : run_t<3, false>(w, keys, vals, h_offs, nroots, n, max_root, s);
-    case TSQS_FLOAT32: return hv ? run_t<4, true>(w, keys, vals, h_offs, nroots, n, max_root, s)
-                                 : run_t<4, false>(w, keys, vals, h_offs, nroots, n, max_root, s);
-    default: return TSQS_EUNSUPPORTED;
-  }
+  const FinGeom geo = geom_any(dt, w.lds_budget, hv);
+  const WsNeed nd = ws_need(n, nroots, dt_bytes(dt), hv, geo.small_max, h_offs != nullptr);
+  CallEnv env;
+  if ((rc = ws_grow(w, nd, hv, &env.v)) != TSQS_OK) return rc;
+  env.cus = w.cus;
+  env.lds_budget = w.lds_budget;
+  env.h_lvl = w.h_lvl;
+  env.h_stats = w.h_stats;
+  env.ev = w.ev_ok ? w.ev : nullptr;
+  CallArgs a;
+  a.keys = keys; a.vals = vals; a.h_offs = h_offs; a.nroots = nroots; a.n = n;
+  a.max_root = max_root; a.s = s;
+  return sort_any(dt, env, a);
 }
-
-bool dtype_ok(int dt) { return dt >= TSQS_INT32 && dt <= TSQS_FLOAT32; }
 
 // ---- autotuner inputs: seeded uniform keys (SplitMix64) and payload = index ----
 
@@ -423,6 +188,378 @@ __global__ void k_tune_iota(uint32_t *v, uint64_t n) {
 }
 
 }  // namespace
+
+namespace {
+
+// Device bytes of one group's tables for an arena of `elems` keys.
+size_t group_table_bytes(size_t elems, uint32_t small_max, size_t *seg_cap, size_t *slot_cap,
+                         size_t *big_cap) {
+  const size_t sc = elems / ((size_t)small_max + 1) + 2;
+  const size_t fc = 4 * sc + kQRootsPerTick;
+  const size_t bc = 2 * (elems / kBandChunk) + 16;
+  if (seg_cap) *seg_cap = sc;
+  if (slot_cap) *slot_cap = fc;
+  if (big_cap) *big_cap = bc;
+  return 2 * sc * (sizeof(Seg) + kCtrStride * sizeof(unsigned long long)) +
+         2 * fc * sizeof(FinItem) + 3 * sc * sizeof(FinItem) + bc * sizeof(FinItem) +
+         sizeof(LevelCtl) * kMaxLevels + sizeof(unsigned long long) * (kStripes * kStatWords + 16) +
+         kInFlight * kQRootsPerTick * sizeof(RootRec);
+}
+
+FinGeom queue_geom(int dt, size_t lds) { return geom_any(dt, lds, false); }
+
+int group_init(tsqs_queue *q, int dt) {
+  QGroup &G = q->g[dt];
+  if (G.ready) return TSQS_OK;
+  G.dt = dt;
+  G.kb = dt_bytes(dt);
+  G.geo = queue_geom(dt, q->lds_budget);
+  HIPCHK(hipStreamCreateWithFlags(&G.s, hipStreamNonBlocking));
+  const size_t elems = q->arena_bytes / G.kb;
+  group_table_bytes(elems, G.geo.small_max, &G.seg_cap, &G.slot_cap, &G.big_cap);
+  size_t c0 = 0;
+  for (int i = 0; i < 2; i++) {
+    c0 = 0; if (grow(&G.seg[i], &c0, G.seg_cap) != TSQS_OK) return TSQS_ENOMEM;
+    c0 = 0; if (grow(&G.ctr[i], &c0, G.seg_cap * kCtrStride) != TSQS_OK) return TSQS_ENOMEM;
+  }
+  c0 = 0; if (grow(&G.fin, &c0, G.slot_cap) != TSQS_OK) return TSQS_ENOMEM;
+  c0 = 0; if (grow(&G.finw, &c0, G.slot_cap) != TSQS_OK) return TSQS_ENOMEM;
+  c0 = 0; if (grow(&G.band, &c0, 3 * G.seg_cap) != TSQS_OK) return TSQS_ENOMEM;
+  c0 = 0; if (grow(&G.big, &c0, G.big_cap) != TSQS_OK) return TSQS_ENOMEM;
+  c0 = 0; if (grow(&G.lvl, &c0, (size_t)kMaxLevels) != TSQS_OK) return TSQS_ENOMEM;
+  c0 = 0; if (grow(&G.stats, &c0, (size_t)(kStripes * kStatWords + 16)) != TSQS_OK) return TSQS_ENOMEM;
+  HIPCHK(hipMemsetAsync(G.lvl, 0, sizeof(LevelCtl) * kMaxLevels, G.s));
+  HIPCHK(hipMemsetAsync(G.stats, 0, sizeof(unsigned long long) * (kStripes * kStatWords + 16), G.s));
+  for (int i = 0; i < kInFlight; i++) {
+    c0 = 0; if (grow(&G.d_roots[i], &c0, (size_t)kQRootsPerTick) != TSQS_OK) return TSQS_ENOMEM;
+    if (hipHostMalloc(&G.h_roots[i], sizeof(RootRec) * kQRootsPerTick, hipHostMallocDefault) != hipSuccess)
+      return TSQS_ENOMEM;
+  }
+  if (hipHostMalloc(&G.h_err, sizeof(unsigned int) * kInFlight, hipHostMallocDefault) != hipSuccess)
+    return TSQS_ENOMEM;
+  for (int i = 0; i < kInFlight; i++) {
+    G.h_err[i] = 0;
+    HIPCHK(hipEventCreateWithFlags(&G.ev[i], hipEventDisableTiming));
+  }
+  G.ev_made = true;
+  HIPCHK(hipStreamSynchronize(G.s));
+  G.ready = true;
+  return TSQS_OK;
+}
+
+void group_free(QGroup &G) {
+  for (int i = 0; i < 2; i++) { (void)hipFree(G.seg[i]); (void)hipFree(G.ctr[i]); }
+  (void)hipFree(G.fin); (void)hipFree(G.finw); (void)hipFree(G.band); (void)hipFree(G.big);
+  (void)hipFree(G.lvl); (void)hipFree(G.stats);
+  for (int i = 0; i < kInFlight; i++) { (void)hipFree(G.d_roots[i]); (void)hipHostFree(G.h_roots[i]); }
+  (void)hipHostFree(G.h_err);
+  if (G.ev_made) for (int i = 0; i < kInFlight; i++) (void)hipEventDestroy(G.ev[i]);
+  if (G.s) (void)hipStreamDestroy(G.s);
+  G = QGroup();
+}
+
+// First-fit reservation of `bytes` (a multiple of kArenaAlign) in the arenas.
+bool arena_take(tsqs_queue *q, uint64_t bytes, uint64_t *off) {
+  for (auto it = q->free_ranges.begin(); it != q->free_ranges.end(); ++it) {
+    if (it->second >= bytes) {
+      *off = it->first;
+      const uint64_t rest = it->second - bytes, at = it->first + bytes;
+      q->free_ranges.erase(it);
+      if (rest) q->free_ranges[at] = rest;
+      q->arena_used += bytes;
+      return true;
+    }
+  }
+  return false;
+}
+
+void arena_give(tsqs_queue *q, uint64_t off, uint64_t bytes) {
+  q->arena_used -= bytes;
+  auto it = q->free_ranges.emplace(off, bytes).first;
+  auto nx = std::next(it);
+  if (nx != q->free_ranges.end() && it->first + it->second == nx->first) {
+    it->second += nx->second;
+    q->free_ranges.erase(nx);
+  }
+  if (it != q->free_ranges.begin()) {
+    auto pv = std::prev(it);
+    if (pv->first + pv->second == it->first) {
+      pv->second += it->second;
+      q->free_ranges.erase(it);
+    }
+  }
+}
+
+// Requests the device has appended to the completion ring become done (the
+// ring is read in order up to the first entry not yet written).
+void collect_done(tsqs_queue *q) {
+  for (;;) {
+    unsigned int *e = &q->h_ring[q->ring_cur % kQMaxReq];
+    const unsigned int v = __atomic_load_n(e, __ATOMIC_ACQUIRE);
+    if (v == 0) break;
+    *e = 0u;
+    q->ring_cur++;
+    const uint64_t tk = q->id_ticket[v - 1];
+    QReq &r = q->reqs[tk];
+    r.state = 2;
+    q->n_done++;
+    q->g[r.dt].live--;
+    q->reap.push_back(tk);
+  }
+}
+
+// FIFO admission: copy the keys in, register the root with its group.
+int admit(tsqs_queue *q) {
+  while (!q->pending.empty()) {
+    const uint64_t tk = q->pending.front();
+    QReq &r = q->reqs[tk];
+    QGroup &G = q->g[r.dt];
+    if (!G.ready) {
+      const int rc = group_init(q, r.dt);
+      if (rc != TSQS_OK) return rc;
+    }
+    if (G.next_roots.size() >= kQRootsPerTick || q->free_ids.empty()) break;
+    uint64_t off = 0;
+    if (!arena_take(q, r.bytes, &off)) break;
+    r.boff = off;
+    r.id = q->free_ids.back();
+    q->free_ids.pop_back();
+    q->h_flag[r.id] = 0u;
+    q->id_ticket[r.id] = tk;
+    if (!G.waits_src) {
+      // the source was written on the caller's stream before the submit
+      HIPCHK(hipEventRecord(q->ev_src, q->s));
+      HIPCHK(hipStreamWaitEvent(G.s, q->ev_src, 0));
+      G.waits_src = true;
+    }
+    HIPCHK(hipMemcpyAsync(q->KA + off, r.src, r.n * G.kb, hipMemcpyDeviceToDevice, G.s));
+    RootRec rr;
+    rr.off = off / G.kb;
+    rr.len = (uint32_t)r.n;
+    rr.req = r.id;
+    G.next_roots.push_back(rr);
+    if (r.n > G.max_n) G.max_n = r.n;
+    G.live++;
+    r.state = 1;
+    q->pending.pop_front();
+  }
+  return TSQS_OK;
+}
+
+int tick_dt(tsqs_queue *q, int dt) {
+  QGroup &G = q->g[dt];
+  switch (dt) {
+    case TSQS_INT32: return queue_tick<0>(q, G);
+    case TSQS_UINT32: return queue_tick<1>(q, G);
+    case TSQS_INT64: return queue_tick<2>(q, G);
+    case TSQS_UINT64: return queue_tick<3>(q, G);
+    default: return queue_tick<4>(q, G);
+  }
+}
+
+void queue_free(tsqs_queue *q) {
+  for (int i = 0; i < 5; i++) group_free(q->g[i]);
+  (void)hipFree(q->KA);
+  (void)hipFree(q->SA);
+  (void)hipFree(q->req_left);
+  (void)hipFree(q->d_pos);
+  (void)hipHostFree(q->h_flag);
+  (void)hipHostFree(q->h_ring);
+  if (q->ev_src) (void)hipEventDestroy(q->ev_src);
+}
+
+}  // namespace
+
+extern "C" {
+
+int tsqs_queue_open(size_t budget_bytes, void *stream, tsqs_queue_t **out) {
+  if (!out) return TSQS_EINVAL;
+  *out = nullptr;
+  if (budget_bytes < ((size_t)64 << 20)) return TSQS_EINVAL;
+  tsqs_queue *q = new (std::nothrow) tsqs_queue();
+  if (!q) return TSQS_ENOMEM;
+  q->s = (hipStream_t)stream;
+  int rc = TSQS_OK;
+  auto fail = [&](int code) { queue_free(q); delete q; return code; };
+  if (hipGetDevice(&q->dev) != hipSuccess) return fail(TSQS_EDEVICE);
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, q->dev) != hipSuccess) return fail(TSQS_EDEVICE);
+  q->cus = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
+  q->lds_budget = prop.sharedMemPerBlock > 0 ? (size_t)prop.sharedMemPerBlock : 65536;
+  // budget = two arenas + the tables of the three key widths a server mixes
+  // (4-byte integer, 4-byte float, 8-byte integer), each sized for a full arena
+  size_t arena = budget_bytes / 2;
+  for (int it = 0; it < 4; it++) {
+    const size_t t32 = group_table_bytes(arena / 4, queue_geom(TSQS_INT32, q->lds_budget).small_max,
+                                         nullptr, nullptr, nullptr);
+    const size_t t64 = group_table_bytes(arena / 8, queue_geom(TSQS_INT64, q->lds_budget).small_max,
+                                         nullptr, nullptr, nullptr);
+    const size_t tables = 2 * t32 + t64 + kQMaxReq * (sizeof(unsigned long long) + 4);
+    if (tables >= budget_bytes / 2) return fail(TSQS_EINVAL);
+    arena = ((budget_bytes - tables) / 2) / kArenaAlign * kArenaAlign;
+  }
+  q->arena_bytes = arena;
+  size_t c0 = 0;
+  if (grow(&q->KA, &c0, arena) != TSQS_OK) return fail(TSQS_ENOMEM);
+  c0 = 0;
+  if (grow(&q->SA, &c0, arena) != TSQS_OK) return fail(TSQS_ENOMEM);
+  c0 = 0;
+  if (grow(&q->req_left, &c0, (size_t)kQMaxReq) != TSQS_OK) return fail(TSQS_ENOMEM);
+  if (hipHostMalloc(&q->h_flag, sizeof(unsigned int) * kQMaxReq,
+                    hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess)
+    return fail(TSQS_ENOMEM);
+  std::memset(q->h_flag, 0, sizeof(unsigned int) * kQMaxReq);
+  if (hipHostGetDevicePointer((void **)&q->d_flag, q->h_flag, 0) != hipSuccess) return fail(TSQS_EDEVICE);
+  if (hipHostMalloc(&q->h_ring, sizeof(unsigned int) * kQMaxReq,
+                    hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess)
+    return fail(TSQS_ENOMEM);
+  std::memset(q->h_ring, 0, sizeof(unsigned int) * kQMaxReq);
+  if (hipHostGetDevicePointer((void **)&q->d_ring, q->h_ring, 0) != hipSuccess) return fail(TSQS_EDEVICE);
+  c0 = 0;
+  if (grow(&q->d_pos, &c0, (size_t)1) != TSQS_OK) return fail(TSQS_ENOMEM);
+  if (hipMemset(q->d_pos, 0, sizeof(unsigned int)) != hipSuccess) return fail(TSQS_EDEVICE);
+  if (hipEventCreateWithFlags(&q->ev_src, hipEventDisableTiming) != hipSuccess) return fail(TSQS_EDEVICE);
+  q->id_ticket.assign(kQMaxReq, 0);
+  q->free_ranges[0] = arena;
+  q->free_ids.reserve(kQMaxReq);
+  for (uint32_t i = 0; i < kQMaxReq; i++) q->free_ids.push_back(kQMaxReq - 1 - i);
+  if ((rc = queue_fin_lds<0>(queue_geom(0, q->lds_budget))) != TSQS_OK) return fail(rc);
+  if ((rc = queue_fin_lds<1>(queue_geom(1, q->lds_budget))) != TSQS_OK) return fail(rc);
+  if ((rc = queue_fin_lds<2>(queue_geom(2, q->lds_budget))) != TSQS_OK) return fail(rc);
+  if ((rc = queue_fin_lds<3>(queue_geom(3, q->lds_budget))) != TSQS_OK) return fail(rc);
+  if ((rc = queue_fin_lds<4>(queue_geom(4, q->lds_budget))) != TSQS_OK) return fail(rc);
+  *out = q;
+  return TSQS_OK;
+}
+
+int tsqs_queue_submit(tsqs_queue_t *q, const void *d_src, size_t nmemb, int dt, uint64_t *ticket) {
+  if (!q || !ticket) return TSQS_EINVAL;
+  if (!dtype_ok(dt)) return TSQS_EUNSUPPORTED;
+  if (!d_src || nmemb == 0 || nmemb > 0xFFFFFFFFull) return TSQS_EINVAL;
+  if (((uintptr_t)d_src % dt_bytes(dt)) != 0) return TSQS_EINVAL;
+  std::lock_guard<std::mutex> lk(q->mu);
+  if (q->broken) return TSQS_EINTERNAL;
+  QReq r;
+  r.dt = dt;
+  r.src = d_src;
+  r.n = nmemb;
+  r.bytes = (nmemb * dt_bytes(dt) + kArenaAlign - 1) / kArenaAlign * kArenaAlign;
+  if (r.bytes > q->arena_bytes) return TSQS_ENOMEM;
+  const uint64_t tk = q->next_ticket++;
+  if (nmemb == 1) {
+    // one key is sorted: done without device work (its result is the source)
+    r.state = 2;
+    q->n_done++;
+    q->reap.push_back(tk);
+  }
+  q->reqs.emplace(tk, r);
+  if (nmemb > 1) q->pending.push_back(tk);
+  *ticket = tk;
+  return TSQS_OK;
+}
+
+int tsqs_queue_step(tsqs_queue_t *q) {
+  if (!q) return TSQS_EINVAL;
+  std::lock_guard<std::mutex> lk(q->mu);
+  if (q->broken) return TSQS_EINTERNAL;
+  if (hipSetDevice(q->dev) != hipSuccess) return TSQS_EDEVICE;
+  collect_done(q);
+  for (int dt = 0; dt < 5; dt++) q->g[dt].waits_src = false;
+  int rc = admit(q);
+  if (rc != TSQS_OK) return rc;
+  for (int dt = 0; dt < 5; dt++) {
+    QGroup &G = q->g[dt];
+    if (!G.ready || (G.live == 0 && G.next_roots.empty())) continue;
+    rc = tick_dt(q, dt);
+    if (rc == TSQS_EAGAIN) continue;
+    if (rc != TSQS_OK) return rc;
+  }
+  return TSQS_OK;
+}
+
+int tsqs_queue_poll(tsqs_queue_t *q, uint64_t ticket) {
+  if (!q) return TSQS_EINVAL;
+  std::lock_guard<std::mutex> lk(q->mu);
+  auto it = q->reqs.find(ticket);
+  if (it == q->reqs.end()) return TSQS_EINVAL;
+  QReq &r = it->second;
+  if (r.state == 1 && __atomic_load_n(&q->h_flag[r.id], __ATOMIC_ACQUIRE)) collect_done(q);
+  return r.state;
+}
+
+int tsqs_queue_result(tsqs_queue_t *q, uint64_t ticket, void **d_keys, size_t *nmemb) {
+  if (!q || !d_keys) return TSQS_EINVAL;
+  std::lock_guard<std::mutex> lk(q->mu);
+  auto it = q->reqs.find(ticket);
+  if (it == q->reqs.end()) return TSQS_EINVAL;
+  QReq &r = it->second;
+  if (r.state == 1 && __atomic_load_n(&q->h_flag[r.id], __ATOMIC_ACQUIRE)) collect_done(q);
+  if (r.state != 2) return TSQS_EAGAIN;
+  *d_keys = r.n == 1 ? (void *)r.src : (void *)(q->KA + r.boff);
+  if (nmemb) *nmemb = (size_t)r.n;
+  return TSQS_OK;
+}
+
+int tsqs_queue_reap(tsqs_queue_t *q, uint64_t *tickets, size_t cap, size_t *count) {
+  if (!q || !count || (cap && !tickets)) return TSQS_EINVAL;
+  std::lock_guard<std::mutex> lk(q->mu);
+  collect_done(q);
+  size_t k = 0;
+  while (k < cap && !q->reap.empty()) {
+    tickets[k++] = q->reap.front();
+    q->reap.pop_front();
+  }
+  *count = k;
+  return TSQS_OK;
+}
+
+int tsqs_queue_release(tsqs_queue_t *q, uint64_t ticket) {
+  if (!q) return TSQS_EINVAL;
+  std::lock_guard<std::mutex> lk(q->mu);
+  auto it = q->reqs.find(ticket);
+  if (it == q->reqs.end()) return TSQS_EINVAL;
+  QReq &r = it->second;
+  if (r.state == 1 && __atomic_load_n(&q->h_flag[r.id], __ATOMIC_ACQUIRE)) collect_done(q);
+  if (r.state != 2) return TSQS_EAGAIN;
+  if (r.n > 1) {
+    arena_give(q, r.boff, r.bytes);
+    q->free_ids.push_back(r.id);
+  }
+  q->n_done--;
+  q->reqs.erase(it);
+  return TSQS_OK;
+}
+
+int tsqs_queue_info(tsqs_queue_t *q, uint64_t *queued, uint64_t *running, uint64_t *done,
+                    uint64_t *arena_used, uint64_t *arena_bytes) {
+  if (!q) return TSQS_EINVAL;
+  std::lock_guard<std::mutex> lk(q->mu);
+  collect_done(q);
+  uint64_t run = 0;
+  for (int i = 0; i < 5; i++) run += q->g[i].live;
+  if (queued) *queued = q->pending.size();
+  if (running) *running = run;
+  if (done) *done = q->n_done;
+  if (arena_used) *arena_used = q->arena_used;
+  if (arena_bytes) *arena_bytes = q->arena_bytes;
+  return TSQS_OK;
+}
+
+int tsqs_queue_close(tsqs_queue_t *q) {
+  if (!q) return TSQS_EINVAL;
+  int rc = TSQS_OK;
+  {
+    std::lock_guard<std::mutex> lk(q->mu);
+    for (int i = 0; i < 5; i++)
+      if (q->g[i].s && hipStreamSynchronize(q->g[i].s) != hipSuccess) rc = TSQS_EDEVICE;
+    if (hipStreamSynchronize(q->s) != hipSuccess) rc = TSQS_EDEVICE;
+    queue_free(q);
+  }
+  delete q;
+  return rc;
+}
+
+}  // extern "C"
 
 extern "C" {
 
@@ -722,4 +859,4 @@ int tsqs_autotune(int dt, int with_payload, size_t n, const uint64_t *h_offsets,
 
 }  // extern "C"
 
-#include "tsqs_queue_impl.hpp"
+

@@ -629,7 +629,7 @@ __device__ inline void flush_parts(const Ctx &c, int lvl_next, PendLds &pend) {
 
 // ---- kernels ------------------------------------------------------------------------
 
-__global__ void k_reset(Ctx c) {
+static __global__ void k_reset(Ctx c) {
   for (int i = threadIdx.x; i < kMaxLevels; i += blockDim.x) {
     c.lvl[i].packed = 0ull; c.lvl[i].keys = 0ull; c.lvl[i].nbig = 0u;
   }
@@ -640,7 +640,7 @@ __global__ void k_reset(Ctx c) {
 
 // Clears the counters of level `lvl` (a serving tick reuses level indices
 // around a ring; the counters of the next level must start at zero).
-__global__ void k_level_clear(Ctx c, int lvl) {
+static __global__ void k_level_clear(Ctx c, int lvl) {
   if (threadIdx.x == 0) {
     c.lvl[lvl].packed = 0ull; c.lvl[lvl].keys = 0ull; c.lvl[lvl].nbig = 0u;
   }
