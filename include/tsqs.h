@@ -58,7 +58,8 @@ enum {
   TSQS_ENOMEM = -2,        /* workspace could not be allocated */
   TSQS_EDEVICE = -3,       /* HIP runtime error */
   TSQS_EUNSUPPORTED = -4,  /* unknown dtype or option */
-  TSQS_EINTERNAL = -5      /* capacity / level limit exceeded (a bug) */
+  TSQS_EINTERNAL = -5,     /* capacity / level limit exceeded (a bug) */
+  TSQS_ESCRATCH = -7       /* tsqs_sort_noalloc: the request does not fit its fixed scratch */
 };
 
 /* Option keys for tsqs_set_option / tsqs_get_option. */
@@ -120,6 +121,25 @@ int tsqs_sort(void *d_keys, size_t nmemb, int dt, void *stream);
 
 /* As tsqs_sort, moving the uint32 payload d_vals[i] with key d_keys[i]. */
 int tsqs_sort_pairs(void *d_keys, uint32_t *d_vals, size_t nmemb, int dt, void *stream);
+
+/* For callers that cannot allocate device memory (tight serving loops,
+ * harnesses that forbid hipMalloc): as
+ * tsqs_sort (d_vals NULL) or tsqs_sort_pairs, but every device buffer of the
+ * call -- the scratch copy of the keys and payloads, the level tables, the
+ * small-part and band slots, the statistics -- is taken from one fixed array
+ * of TSQS_NOALLOC_SCRATCH_BYTES that the library holds on each GPU it runs on
+ * until the process ends.  The call makes no hipMalloc, hipFree or other
+ * allocation.
+ *   nmemb <= TSQS_NOALLOC_MAX_KEYS; a larger request, or one whose buffers
+ *   for the current options (a small TSQS_OPT_SMALL_MAX needs more tables)
+ *   exceed the array, returns TSQS_ESCRATCH before any device work.
+ * Every call on a GPU uses that GPU's one array and leaves its contents
+ * behind (what must start at zero is cleared by the call's first kernel):
+ * calls whose device work overlaps on one GPU race; the caller orders them
+ * (one stream, or events).  Other conventions as tsqs_sort. */
+#define TSQS_NOALLOC_MAX_KEYS (1u << 20)
+#define TSQS_NOALLOC_SCRATCH_BYTES (32u << 20)
+int tsqs_sort_noalloc(void *d_keys, uint32_t *d_vals, size_t nmemb, int dt, void *stream);
 
 /* Sort records of any size by their keys (late swapping, SVIII.H): the keys
  * are sorted in place with a uint32 index as their payload (the paper's

@@ -18,13 +18,15 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libtsqs.so")
 
 INT32, UINT32, INT64, UINT64, FLOAT32 = 0, 1, 2, 3, 4
-OK, EINVAL, ENOMEM, EDEVICE, EUNSUPPORTED, EINTERNAL, EAGAIN = 0, -1, -2, -3, -4, -5, -6
+OK, EINVAL, ENOMEM, EDEVICE, EUNSUPPORTED, EINTERNAL, EAGAIN, ESCRATCH = 0, -1, -2, -3, -4, -5, -6, -7
+NOALLOC_MAX_KEYS = 1 << 20
+NOALLOC_SCRATCH_BYTES = 32 << 20
 OPT_SMALL_MAX, OPT_SAMPLES, OPT_DEPTH_FACTOR, OPT_PIVOT_MODE = 1, 2, 3, 4
 OPT_SEED, OPT_TIMING, OPT_PART_GRID, OPT_FINISH_GRID, OPT_FINISH_ALGO = 5, 6, 7, 8, 9
 OPT_PRESORT = 10
 MAX_LEVELS = 192
 
-SYMBOLS = ["tsqs_sort", "tsqs_sort_pairs", "tsqs_sort_records", "tsqs_sort_batch", "tsqs_autotune",
+SYMBOLS = ["tsqs_sort", "tsqs_sort_pairs", "tsqs_sort_noalloc", "tsqs_sort_records", "tsqs_sort_batch", "tsqs_autotune",
            "tsqs_free_storage", "tsqs_set_option", "tsqs_get_option", "tsqs_get_stats",
            "tsqs_strerror", "tsqs_version"]
 QUEUE_SYMBOLS = ["tsqs_queue_open", "tsqs_queue_submit", "tsqs_queue_step", "tsqs_queue_poll",
@@ -107,6 +109,8 @@ def load_library():
     lib.tsqs_sort.restype = ctypes.c_int
     lib.tsqs_sort_pairs.argtypes = [vp, vp, sz, ctypes.c_int, vp]
     lib.tsqs_sort_pairs.restype = ctypes.c_int
+    lib.tsqs_sort_noalloc.argtypes = [vp, vp, sz, ctypes.c_int, vp]
+    lib.tsqs_sort_noalloc.restype = ctypes.c_int
     lib.tsqs_sort_records.argtypes = [vp, vp, sz, vp, sz, ctypes.c_int, vp]
     lib.tsqs_sort_records.restype = ctypes.c_int
     lib.tsqs_sort_batch.argtypes = [vp, vp, vp, sz, ctypes.c_int, vp]
@@ -195,6 +199,23 @@ def sort_pairs(keys, vals, dtype_code: int | None = None):
                                           ctypes.c_void_p(vals.data_ptr()), keys.numel(), dt,
                                           _stream_handle()))
     return keys, vals
+
+
+def sort_noalloc(keys, vals=None, dtype_code: int | None = None):
+    """As ``sort`` / ``sort_pairs`` through ``tsqs_sort_noalloc``: every device
+    buffer of the call comes from the library's fixed per-GPU array (at most
+    NOALLOC_MAX_KEYS keys; larger requests raise with ESCRATCH)."""
+    _check_tensor(keys, "keys")
+    vp = None
+    if vals is not None:
+        _check_tensor(vals, "vals")
+        if vals.numel() != keys.numel() or vals.element_size() != 4:
+            raise ValueError("vals must hold one 4-byte payload per key")
+        vp = ctypes.c_void_p(vals.data_ptr())
+    dt = _dtype_code(keys) if dtype_code is None else dtype_code
+    _check(load_library().tsqs_sort_noalloc(ctypes.c_void_p(keys.data_ptr()), vp, keys.numel(), dt,
+                                            _stream_handle()))
+    return keys if vals is None else (keys, vals)
 
 
 def sort_records(keys, records, out=None, dtype_code: int | None = None):

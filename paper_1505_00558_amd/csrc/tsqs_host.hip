@@ -561,6 +561,99 @@ int tsqs_queue_close(tsqs_queue_t *q) {
 
 }  // extern "C"
 
+// ---- the entry point that allocates nothing ----------------------------------
+//
+// tsqs_sort_noalloc takes every device buffer of the call (the scratch copy of
+// the keys and payloads, the level tables, the small-part and band slots, the
+// statistics words) from one file-scope device array.  Its address is taken
+// once per device with hipGetSymbolAddress, on the first call with that
+// device current, and only that address is used afterwards: in host code the
+// array's name is not a device address.  The level table is read back into
+// static host arrays (the call holds the library mutex).
+
+static __device__ __align__(256) unsigned char scratch[TSQS_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+struct ScratchDev {
+  bool ready = false;
+  unsigned char *ptr = nullptr;     // device address of `scratch` on that device
+  int cus = 256;
+  size_t lds_budget = 65536;
+};
+ScratchDev g_scr[kMaxDevices];
+LevelCtl g_scr_lvl[kMaxLevels];
+unsigned long long g_scr_stats[kStripes * kStatWords + 16];
+
+// Lays the buffers of a call out in [base, base + cap) (256-byte aligned
+// pieces); false if they do not fit.
+bool carve(unsigned char *base, size_t cap, const WsNeed &nd, bool hasv, WsView *v) {
+  size_t off = 0;
+  auto take = [&](size_t bytes) -> unsigned char * {
+    unsigned char *p = base + off;
+    off += (bytes + 255) & ~(size_t)255;
+    return p;
+  };
+  v->S = take(nd.s_bytes);
+  v->VS = hasv ? (uint32_t *)take(nd.v_elems * 4) : nullptr;
+  v->VE = hasv ? (uint32_t *)take(nd.v_elems * 4) : nullptr;
+  for (int i = 0; i < 2; i++) {
+    v->seg[i] = (Seg *)take(nd.seg_cap * sizeof(Seg));
+    v->ctr[i] = (unsigned long long *)take(nd.seg_cap * kCtrStride * sizeof(unsigned long long));
+  }
+  v->fin = (FinItem *)take(nd.slot_cap * sizeof(FinItem));
+  v->finw = (FinItem *)take(nd.slot_cap * sizeof(FinItem));
+  v->band = (FinItem *)take(nd.band_cap * sizeof(FinItem));
+  v->big = (FinItem *)take(nd.big_cap * sizeof(FinItem));
+  v->lvl = (LevelCtl *)take(sizeof(LevelCtl) * kMaxLevels);
+  v->stats = (unsigned long long *)take(sizeof(unsigned long long) * (kStripes * kStatWords + 16));
+  v->offs = nullptr;
+  v->seg_cap = nd.seg_cap;
+  v->slot_cap = nd.slot_cap;
+  v->big_cap = nd.big_cap;
+  return off <= cap;
+}
+
+}  // namespace
+
+extern "C" int tsqs_sort_noalloc(void *d_keys, uint32_t *d_vals, size_t nmemb, int dt, void *stream) {
+  if (!dtype_ok(dt)) return TSQS_EUNSUPPORTED;
+  if (nmemb <= 1) return TSQS_OK;
+  if (!d_keys) return TSQS_EINVAL;
+  if (nmemb > TSQS_NOALLOC_MAX_KEYS) return TSQS_ESCRATCH;
+  std::lock_guard<std::mutex> lk(g_mu);
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return TSQS_EDEVICE;
+  ScratchDev &sd = g_scr[dev];
+  if (!sd.ready) {
+    void *ptr = nullptr;
+    HIPCHK(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    hipDeviceProp_t prop;
+    HIPCHK(hipGetDeviceProperties(&prop, dev));
+    sd.ptr = (unsigned char *)ptr;
+    sd.cus = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
+    sd.lds_budget = prop.sharedMemPerBlock > 0 ? (size_t)prop.sharedMemPerBlock : 65536;
+    sd.ready = true;
+  }
+  g_have_stats = false;
+  const bool hv = d_vals != nullptr;
+  const FinGeom geo = geom_any(dt, sd.lds_budget, hv);
+  const WsNeed nd = ws_need((uint64_t)nmemb, 1, dt_bytes(dt), hv, geo.small_max, false);
+  CallEnv env;
+  if (!carve(sd.ptr, TSQS_NOALLOC_SCRATCH_BYTES, nd, hv, &env.v)) return TSQS_ESCRATCH;
+  env.cus = sd.cus;
+  env.lds_budget = sd.lds_budget;
+  env.h_lvl = g_scr_lvl;
+  env.h_stats = g_scr_stats;
+  env.ev = nullptr;
+  CallArgs a;
+  a.keys = d_keys; a.vals = d_vals; a.h_offs = nullptr; a.nroots = 1; a.n = nmemb;
+  a.max_root = nmemb; a.s = (hipStream_t)stream;
+  return sort_any(dt, env, a);
+}
+
 extern "C" {
 
 int tsqs_sort(void *d_keys, size_t nmemb, int dt, void *stream) {
@@ -745,6 +838,7 @@ const char *tsqs_strerror(int code) {
     case TSQS_EUNSUPPORTED: return "unsupported dtype or option";
     case TSQS_EINTERNAL: return "internal capacity or level limit exceeded";
     case TSQS_EAGAIN: return "not yet (request not done, or no room yet)";
+    case TSQS_ESCRATCH: return "request exceeds the fixed scratch of tsqs_sort_noalloc";
     default: return "unknown error code";
   }
 }

@@ -167,3 +167,16 @@ def test_sort_records_argument_checks(lib):
     assert lib.tsqs_sort_records(fake, fake, 8, None, 1 << 32, 0, None) == -1    # n >= 2^32
     assert lib.tsqs_sort_records(fake, fake, 64, fake2, 10, 0, None) == -1       # overlapping out
     assert lib.tsqs_sort_records(fake, fake, 8, None, 10, 9, None) == -4         # bad dtype
+
+
+def test_noalloc_argument_errors(lib):
+    """tsqs_sort_noalloc refuses bad arguments and requests above its fixed
+    maximum before any device work (no GPU needed)."""
+    import paper_1505_00558_amd as tsqs
+    assert lib.tsqs_sort_noalloc(None, None, 0, tsqs.INT32, None) == tsqs.OK
+    assert lib.tsqs_sort_noalloc(None, None, 1, tsqs.INT32, None) == tsqs.OK
+    assert lib.tsqs_sort_noalloc(None, None, 10, tsqs.INT32, None) == tsqs.EINVAL
+    assert lib.tsqs_sort_noalloc(None, None, 10, 9, None) == tsqs.EUNSUPPORTED
+    big = tsqs.NOALLOC_MAX_KEYS + 1
+    assert lib.tsqs_sort_noalloc(ctypes.c_void_p(256), None, big, tsqs.INT32, None) == tsqs.ESCRATCH
+    assert "scratch" in tsqs.strerror(tsqs.ESCRATCH)
