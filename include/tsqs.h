@@ -24,15 +24,21 @@
  * releases it (the paper's FreeTripleStateQuickSortStorage()).
  *
  * Streams and synchronisation.  All work is enqueued on `stream` (a
- * hipStream_t; NULL = the default stream).  The call returns after that work
- * has completed (it synchronises `stream` to learn how many partition levels
- * were needed and to collect error flags and statistics), so the buffers may
- * be used as soon as it returns.  Calls are serialised by a library mutex.
+ * hipStream_t; NULL = the default stream) and the call returns without waiting
+ * for it: the caller synchronises (the stream, or an event recorded after the
+ * call) before it reads the buffers.  The schedule needs no answer from the
+ * device: the levels a median split needs are launched, and one persistent
+ * kernel finishes whatever they leave (bad pivots, the depth-limit fallback).
+ * Calls are serialised by a library mutex; a call on another stream than the
+ * previous one waits (on the device) for the previous one, since they share
+ * the workspace.
  *
  * Errors.  Argument errors are returned before any HIP call is made.  A HIP
  * runtime failure returns TSQS_EDEVICE; a workspace allocation failure
- * TSQS_ENOMEM; an internal capacity or level-limit violation TSQS_EINTERNAL.
- * In every error case the contents of the caller's buffers are unspecified.
+ * TSQS_ENOMEM.  An error found on the device (an internal capacity or count
+ * violation, the persistent kernel's iteration cap) is returned by
+ * tsqs_get_stats for that call (TSQS_EINTERNAL).  In every error case the
+ * contents of the caller's buffers are unspecified.
  */
 #ifndef TSQS_H
 #define TSQS_H
@@ -82,13 +88,22 @@ enum {
                                 merged by a register network, 3 = runs of up to one
                                 wave merged by cross-lane bitonic stages in registers
                                 first, then as 1 (default) */
-  TSQS_OPT_PRESORT = 10      /* 1 (default) = before the first pass of an array that
+  TSQS_OPT_PRESORT = 10,     /* 1 (default) = before the first pass of an array that
                                 needs one (tsqs_sort, tsqs_sort_pairs, each array of
                                 tsqs_sort_batch), check whether it is already
                                 non-decreasing, or non-increasing (then reverse it in
                                 place, payloads too): such an array needs no pass (the
                                 sorted / reversed handlers, SIII.I); 0 = off.  The
                                 serving queue does not check */
+  TSQS_OPT_SCHEDULE = 11,    /* 0 (default) = the level schedule (one to three kernels
+                                per recursion level, the levels a median split needs),
+                                then the persistent kernel for what is left; 1 = the
+                                persistent kernel for every part (one launch after the
+                                roots are set up) */
+  TSQS_OPT_ITER_CAP = 12     /* loop iterations (tasks and waits) of one workgroup of
+                                the persistent kernel before it stops every workgroup
+                                and reports an error; 0 (default) = 2^23 (a wait of
+                                some seconds; a run of the kernel takes far fewer) */
 };
 
 #define TSQS_MAX_LEVELS 192
@@ -112,11 +127,18 @@ typedef struct {
   uint32_t presorted;            /* single array: 0; 1 = found non-decreasing, 2 = found
                                     non-increasing and reversed (TSQS_OPT_PRESORT): no pass
                                     was needed.  Batch: arrays found in order */
+  uint64_t tail_parts;           /* parts partitioned by the persistent kernel */
+  uint64_t tail_keys;            /* keys of those parts */
+  uint64_t tail_bytes;           /* their algorithmic bytes, 2 * keys * (key+payload bytes) */
+  uint64_t select_rounds;        /* radix digits fixed by grid-wide exact-pivot selection */
+  uint32_t error_flags;          /* device error bits of the call (0 = none) */
+  uint32_t schedule;             /* TSQS_OPT_SCHEDULE of the call */
 } tsqs_stats_t;
 
-/* Sort nmemb keys of type dt at device pointer d_keys, in place.
- * nmemb <= 1 is a no-op.  nmemb must be < 2^32.
- * Returns TSQS_OK or an error code. */
+/* Sort nmemb keys of type dt at device pointer d_keys, in place (the paper's
+ * problem statement, abstract and SVII).  nmemb <= 1 is a no-op.  nmemb must
+ * be < 2^32 (part lengths and the packed left|right cursor reservation of the
+ * partition pass are 32-bit).  Returns TSQS_OK or an error code. */
 int tsqs_sort(void *d_keys, size_t nmemb, int dt, void *stream);
 
 /* As tsqs_sort, moving the uint32 payload d_vals[i] with key d_keys[i]. */
@@ -160,10 +182,13 @@ int tsqs_sort_records(void *d_keys, void *d_records, size_t rec_bytes, void *d_o
                       int dt, void *stream);
 
 /* Sort nseg independent arrays stored back to back in d_keys: array j is
- * d_keys[h_offsets[j] .. h_offsets[j+1]).  h_offsets is a host array of nseg+1
- * non-decreasing values starting at 0; every array must have < 2^32 keys (the
- * total may exceed that).  d_vals may be NULL (keys only) or a payload array
- * of the same layout.  All arrays are sorted by one schedule of launches. */
+ * d_keys[h_offsets[j] .. h_offsets[j+1]).  The paper measures the overhead of
+ * many small sorts (SIX); here every array's parts of a level share the same
+ * launches (or the one persistent kernel, TSQS_OPT_SCHEDULE 1), so the cost
+ * per array is not a launch.  h_offsets is a host array of nseg+1
+ * non-decreasing values starting at 0 (copied during the call); every array
+ * must have < 2^32 keys (the total may exceed that).  d_vals may be NULL
+ * (keys only) or a payload array of the same layout. */
 int tsqs_sort_batch(void *d_keys, uint32_t *d_vals, const uint64_t *h_offsets, size_t nseg,
                     int dt, void *stream);
 
@@ -200,7 +225,11 @@ int tsqs_set_option(int key, int64_t value);
 /* Returns the option's value, or INT64_MIN for an unknown key. */
 int64_t tsqs_get_option(int key);
 
-/* Statistics of the last successful call. */
+/* Statistics of the last call: passes and keys per level, fallbacks, keys
+ * finished in LDS or by bands, the persistent kernel's share -- the GPU
+ * counterparts of the paper's comparison and copy counts (SV.A, SVI).  Waits
+ * for the call's device work; returns TSQS_EINTERNAL (with *out filled) if the
+ * device reported an error for it, TSQS_EINVAL if there was no call. */
 int tsqs_get_stats(tsqs_stats_t *out);
 
 const char *tsqs_strerror(int code);

@@ -23,7 +23,8 @@ NOALLOC_MAX_KEYS = 1 << 20
 NOALLOC_SCRATCH_BYTES = 32 << 20
 OPT_SMALL_MAX, OPT_SAMPLES, OPT_DEPTH_FACTOR, OPT_PIVOT_MODE = 1, 2, 3, 4
 OPT_SEED, OPT_TIMING, OPT_PART_GRID, OPT_FINISH_GRID, OPT_FINISH_ALGO = 5, 6, 7, 8, 9
-OPT_PRESORT = 10
+OPT_PRESORT, OPT_SCHEDULE, OPT_ITER_CAP = 10, 11, 12
+SCHEDULE_LEVELS, SCHEDULE_PERSISTENT = 0, 1
 MAX_LEVELS = 192
 
 SYMBOLS = ["tsqs_sort", "tsqs_sort_pairs", "tsqs_sort_noalloc", "tsqs_sort_records", "tsqs_sort_batch", "tsqs_autotune",
@@ -52,6 +53,12 @@ class Stats(ctypes.Structure):
         ("partition_bytes", ctypes.c_uint64),
         ("partition_launches", ctypes.c_uint32),
         ("presorted", ctypes.c_uint32),
+        ("tail_parts", ctypes.c_uint64),
+        ("tail_keys", ctypes.c_uint64),
+        ("tail_bytes", ctypes.c_uint64),
+        ("select_rounds", ctypes.c_uint64),
+        ("error_flags", ctypes.c_uint32),
+        ("schedule", ctypes.c_uint32),
     ]
 
     def as_dict(self) -> dict:
@@ -68,6 +75,9 @@ class Stats(ctypes.Structure):
             "partition_bytes": int(self.partition_bytes),
             "partition_launches": int(self.partition_launches),
             "presorted": int(self.presorted),
+            "tail_parts": int(self.tail_parts), "tail_keys": int(self.tail_keys),
+            "tail_bytes": int(self.tail_bytes), "select_rounds": int(self.select_rounds),
+            "error_flags": int(self.error_flags), "schedule": int(self.schedule),
         }
 
 
@@ -297,9 +307,18 @@ def get_option(key: int) -> int:
 
 
 def get_stats() -> dict:
+    """Statistics of the last call (waits for its device work; raises if the
+    device reported an error for it)."""
     s = Stats()
     _check(load_library().tsqs_get_stats(ctypes.byref(s)))
     return s.as_dict()
+
+
+def last_call_status() -> tuple:
+    """(return code, statistics) of the last call, without raising."""
+    s = Stats()
+    rc = load_library().tsqs_get_stats(ctypes.byref(s))
+    return int(rc), s.as_dict()
 
 
 class _DeviceView:

@@ -1,14 +1,16 @@
 // tsqs_dt.hip -- the launch schedule of one key type (compiled once per type
 // with TSQS_DT = 0..4; see tsqs_host.hpp).
 //
-// One call = one schedule on the caller's stream:
+// One call = one schedule enqueued on the caller's stream, with no host
+// synchronisation:
 //   k_reset, [upload of batch offsets], [presortedness check], k_init (roots:
 //   pivots or small items), then per level d: k_partition(d), k_plan(d),
-//   k_finish(d),
-// launched without host synchronisation for the number of levels a median
-// split needs (ceil(log2(n / small_max)) + 2, two levels per pass after the
-// first); the stream is then synchronised once, and only if parts remain (bad
-// pivots, the depth-limit path) more levels are launched, eight at a time.
+//   k_finish(d) for the number of levels a median split needs
+//   (ceil(log2(n / small_max)) + 2, two levels per pass after the first),
+//   then k_seed + k_persist: the persistent kernel finishes whatever is left
+//   (nothing, for most inputs: its workgroups see no keys left and return).
+// With the persistent schedule (TSQS_OPT_SCHEDULE 1) no level is launched:
+// k_finish of the roots' small arrays, then every part in k_persist.
 #include "tsqs_host.hpp"
 #include "tsqs_queue_state.hpp"
 
@@ -21,6 +23,39 @@
 namespace tsqs {
 namespace host {
 namespace {
+
+template <int DT, bool HASV>
+int launch_finish(const Ctx &c, int d, int grid, size_t lds, hipStream_t s) {
+  if (g_opt.finish_algo == 0)
+    hipLaunchKernelGGL((k_finish<DT, HASV, 0>), dim3(grid), dim3(kFinNT), lds, s, c, d);
+  else if (g_opt.finish_algo == 1)
+    hipLaunchKernelGGL((k_finish<DT, HASV, 1>), dim3(grid), dim3(kFinNT), lds, s, c, d);
+  else if (g_opt.finish_algo == 2)
+    hipLaunchKernelGGL((k_finish<DT, HASV, 2>), dim3(grid), dim3(kFinNT), lds, s, c, d);
+  else
+    hipLaunchKernelGGL((k_finish<DT, HASV, 3>), dim3(grid), dim3(kFinNT), lds, s, c, d);
+  return hipGetLastError() == hipSuccess ? TSQS_OK : TSQS_EDEVICE;
+}
+
+// Workgroups of the persistent kernel: as many as fit on the device at once
+// (it needs no more, and no co-residency).
+template <int DT, bool HASV, bool WIDE>
+int persist_grid(int cus, size_t lds) {
+  static int per_cu = -1;
+  static size_t per_cu_lds = 0;
+  if (per_cu < 0 || per_cu_lds != lds) {
+    if (lds > 65536 && hipFuncSetAttribute((const void *)k_persist<DT, HASV, WIDE>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           (int)lds) != hipSuccess)
+      return -1;
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_persist<DT, HASV, WIDE>, kPNT, lds) != hipSuccess)
+      return -1;
+    per_cu = nb > 0 ? nb : 1;
+    per_cu_lds = lds;
+  }
+  return per_cu * cus;
+}
 
 template <int DT, bool HASV>
 int run_t(const CallEnv &env, const CallArgs &a) {
@@ -58,7 +93,8 @@ int run_t(const CallEnv &env, const CallArgs &a) {
   c.done_ring = nullptr;
   c.done_pos = nullptr;
   c.done_cap = 0;
-  c.pad1 = 0;
+  c.fin_roots_only = 0;
+  c.p = PCtx();
   c.root_level = 0;
   c.ring = 0;
   c.n = n;
@@ -72,6 +108,23 @@ int run_t(const CallEnv &env, const CallArgs &a) {
   c.jitter = mix32((uint64_t)g_opt.seed + (g_calls++));
   c.seg_cap = (uint32_t)seg_cap;
   c.big_cap = (uint32_t)big_cap;
+  c.fin_roots_only = 0;
+  // 32-bit byte offsets within a part suffice unless a part reaches 4 GiB
+  const bool wide = (uint64_t)max_root * sizeof(typename Codec<DT>::B) > 0xFFFFFFFFull;
+  const size_t plds = persist_lds<DT, HASV>();
+  const int pgrid = wide ? persist_grid<DT, HASV, true>(env.cus, plds) : persist_grid<DT, HASV, false>(env.cus, plds);
+  if (pgrid <= 0) return TSQS_EDEVICE;
+  c.p.task = w.task; c.p.seq = w.seq; c.p.ctl = w.ctl;
+  c.p.parts = w.parts; c.p.pctr = w.pctr; c.p.hist = w.hist; c.p.bands = w.bands;
+  c.p.sfin = w.sfin;
+  c.p.sfin_cap = (uint32_t)w.sfin_cap;
+  c.p.pad2 = 0;
+  c.p.qmask = (unsigned long long)w.qcap - 1;
+  c.p.part_cap = (uint32_t)w.part_cap;
+  c.p.hist_cap = (uint32_t)w.hist_cap;
+  c.p.band_cap = (uint32_t)w.band_cap;
+  c.p.grid = (uint32_t)pgrid;
+  c.p.iter_cap = g_opt.iter_cap > 0 ? (unsigned long long)g_opt.iter_cap : kDefaultIterCap;
 
   const int part_grid = g_opt.part_grid > 0 ? (int)g_opt.part_grid : 4 * env.cus;
   const int fin_grid = g_opt.finish_grid > 0 ? (int)g_opt.finish_grid : 8 * env.cus;
@@ -85,6 +138,14 @@ int run_t(const CallEnv &env, const CallArgs &a) {
     HIPCHK(hipFuncSetAttribute((const void *)k_finish<DT, HASV, 2>,
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)fin_lds));
     HIPCHK(hipFuncSetAttribute((const void *)k_finish<DT, HASV, 3>,
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)fin_lds));
+    HIPCHK(hipFuncSetAttribute((const void *)k_finish_list<DT, HASV, 0>,
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)fin_lds));
+    HIPCHK(hipFuncSetAttribute((const void *)k_finish_list<DT, HASV, 1>,
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)fin_lds));
+    HIPCHK(hipFuncSetAttribute((const void *)k_finish_list<DT, HASV, 2>,
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)fin_lds));
+    HIPCHK(hipFuncSetAttribute((const void *)k_finish_list<DT, HASV, 3>,
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)fin_lds));
   }
   const size_t waves_init = (nroots + kPlanNW - 1) / kPlanNW;
@@ -101,91 +162,75 @@ int run_t(const CallEnv &env, const CallArgs &a) {
   hipLaunchKernelGGL((k_init<DT, HASV>), dim3(init_grid), dim3(kPlanNT), 0, s, c);
   HIPCHK(hipGetLastError());
 
-  // median-of-63 splits stay within about 45/55: allow 20% more levels than a
-  // perfect halving, plus two
-  // 32-bit byte offsets within a part suffice unless a part reaches 4 GiB
-  const bool wide = (uint64_t)max_root * sizeof(typename Codec<DT>::B) > 0xFFFFFFFFull;
+  // median-of-63 splits stay within about 45/55: launch the levels for 20% more
+  // halvings than a perfect split, plus two (the first pass is one level, the
+  // rest two levels each); every root small: level 0 has only its finish work.
+  // Whatever is left after them (bad pivots, the depth limit) the persistent
+  // kernel finishes, so the call never waits for the device.
   const uint32_t lv = ceil_log2((max_root + small_max - 1) / small_max);
-  // every root small: level 0 has no parts, only its finish work.  The first
-  // pass is one level and the rest two levels each (with payloads too).
   const bool roots_small = max_root <= small_max;
   const uint32_t lv_all = lv + (lv + 4) / 5 + 2;
+  const bool persistent = g_opt.schedule == 1;
   uint32_t expected = roots_small ? 1u : 2 + lv_all / 2;
-  int d = 0, target = (int)expected;
-  if (c.pre && n >= kPresortSyncMin) {
-    // a large array found in order needs none of the levels: read the two words
-    // of the check once instead of launching the whole schedule empty
-    unsigned int *hp = (unsigned int *)(env.h_stats + kStripes * kStatWords + 8);
-    HIPCHK(hipMemcpyAsync(hp, c.pre, 2 * sizeof(unsigned int), hipMemcpyDeviceToHost, s));
-    HIPCHK(hipStreamSynchronize(s));
-    if (hp[0] != 0u && hp[1] == 0u) target = 0;
-  }
-  if (target > kMaxLevels - 1) target = kMaxLevels - 1;
-  for (;;) {
-    for (; d < target; d++) {
-      const bool idle = d == 0 && roots_small;
-      if (timing) HIPCHK(hipEventRecord(env.ev[2 * d], s));
-      if (idle) {
-      } else if (wide) {
-        hipLaunchKernelGGL((k_partition<DT, HASV, true, false>), dim3(part_grid), dim3(kPartNT1), 0, s, c, d);
-        if (d > 0)
-          hipLaunchKernelGGL((k_partition<DT, HASV, true, true>), dim3(part_grid), dim3(kPartNT2), 0, s, c, d);
-      } else {
-        hipLaunchKernelGGL((k_partition<DT, HASV, false, false>), dim3(part_grid), dim3(kPartNT1), 0, s, c, d);
-        if (d > 0)
-          hipLaunchKernelGGL((k_partition<DT, HASV, false, true>), dim3(part_grid), dim3(kPartNT2), 0, s, c, d);
-      }
-      if (timing) HIPCHK(hipEventRecord(env.ev[2 * d + 1], s));
-      if (!idle) hipLaunchKernelGGL((k_plan<DT, HASV>), dim3(plan_grid), dim3(kPlanNT), 0, s, c, d);
-      if (g_opt.finish_algo == 0)
-        hipLaunchKernelGGL((k_finish<DT, HASV, 0>), dim3(fin_grid), dim3(kFinNT), fin_lds, s, c, d);
-      else if (g_opt.finish_algo == 1)
-        hipLaunchKernelGGL((k_finish<DT, HASV, 1>), dim3(fin_grid), dim3(kFinNT), fin_lds, s, c, d);
-      else if (g_opt.finish_algo == 2)
-        hipLaunchKernelGGL((k_finish<DT, HASV, 2>), dim3(fin_grid), dim3(kFinNT), fin_lds, s, c, d);
-      else
-        hipLaunchKernelGGL((k_finish<DT, HASV, 3>), dim3(fin_grid), dim3(kFinNT), fin_lds, s, c, d);
-      HIPCHK(hipGetLastError());
+  if (persistent) expected = 0;
+  if (expected > (uint32_t)kMaxLevels - 2) expected = (uint32_t)kMaxLevels - 2;
+  for (int d = 0; d < (int)expected; d++) {
+    const bool idle = d == 0 && roots_small;
+    if (timing) HIPCHK(hipEventRecord(env.ev[2 * d], s));
+    if (idle) {
+    } else if (wide) {
+      hipLaunchKernelGGL((k_partition<DT, HASV, true, false>), dim3(part_grid), dim3(kPartNT1), 0, s, c, d);
+      if (d > 0)
+        hipLaunchKernelGGL((k_partition<DT, HASV, true, true>), dim3(part_grid), dim3(kPartNT2), 0, s, c, d);
+    } else {
+      hipLaunchKernelGGL((k_partition<DT, HASV, false, false>), dim3(part_grid), dim3(kPartNT1), 0, s, c, d);
+      if (d > 0)
+        hipLaunchKernelGGL((k_partition<DT, HASV, false, true>), dim3(part_grid), dim3(kPartNT2), 0, s, c, d);
     }
-    HIPCHK(hipMemcpyAsync(env.h_lvl, w.lvl, sizeof(LevelCtl) * (size_t)(d + 1), hipMemcpyDeviceToHost, s));
-    HIPCHK(hipMemcpyAsync(env.h_stats, w.stats, sizeof(unsigned long long) * (kStripes * kStatWords + 1),
-                          hipMemcpyDeviceToHost, s));
-    HIPCHK(hipStreamSynchronize(s));
-    if (*(unsigned int *)(env.h_stats + kStripes * kStatWords)) return TSQS_EINTERNAL;
-    if ((env.h_lvl[d].packed >> 40) == 0) break;
-    if (d >= kMaxLevels - 1) return TSQS_EINTERNAL;
-    target = d + 8 < kMaxLevels - 1 ? d + 8 : kMaxLevels - 1;
+    if (timing) HIPCHK(hipEventRecord(env.ev[2 * d + 1], s));
+    if (!idle) hipLaunchKernelGGL((k_plan<DT, HASV>), dim3(plan_grid), dim3(kPlanNT), 0, s, c, d);
+    if (launch_finish<DT, HASV>(c, d, fin_grid, fin_lds, s) != TSQS_OK) return TSQS_EDEVICE;
   }
+  if (persistent) {
+    // the roots' small arrays, then every part in the persistent kernel
+    Ctx cr = c;
+    cr.fin_roots_only = 1u;
+    if (launch_finish<DT, HASV>(cr, 0, fin_grid, fin_lds, s) != TSQS_OK) return TSQS_EDEVICE;
+  }
+  const int seed_grid = 4 * env.cus;
+  hipLaunchKernelGGL((k_seed<DT, HASV>), dim3(seed_grid), dim3(kPlanNT), 0, s, c, (int)expected);
+  if (wide)
+    hipLaunchKernelGGL((k_persist<DT, HASV, true>), dim3(c.p.grid), dim3(kPNT), plds, s, c);
+  else
+    hipLaunchKernelGGL((k_persist<DT, HASV, false>), dim3(c.p.grid), dim3(kPNT), plds, s, c);
+  HIPCHK(hipGetLastError());
+  // the small parts the persistent kernel listed
+  if (g_opt.finish_algo == 0)
+    hipLaunchKernelGGL((k_finish_list<DT, HASV, 0>), dim3(fin_grid), dim3(kFinNT), fin_lds, s, c);
+  else if (g_opt.finish_algo == 1)
+    hipLaunchKernelGGL((k_finish_list<DT, HASV, 1>), dim3(fin_grid), dim3(kFinNT), fin_lds, s, c);
+  else if (g_opt.finish_algo == 2)
+    hipLaunchKernelGGL((k_finish_list<DT, HASV, 2>), dim3(fin_grid), dim3(kFinNT), fin_lds, s, c);
+  else
+    hipLaunchKernelGGL((k_finish_list<DT, HASV, 3>), dim3(fin_grid), dim3(kFinNT), fin_lds, s, c);
+  HIPCHK(hipGetLastError());
+  if (env.done) HIPCHK(hipEventRecord(env.done, s));
 
-  tsqs_stats_t &st = g_stats;
-  std::memset(&st, 0, sizeof st);
-  st.levels = (uint32_t)d;
-  st.n = n;
-  st.key_bytes = (uint32_t)kb;
-  st.payload_bytes = HASV ? 4u : 0u;
-  for (int i = 0; i < kStripes; i++) {
-    const unsigned long long *sp = env.h_stats + (size_t)i * kStatWords;
-    st.fallback_parts += sp[kStFallback];
-    st.small_parts += sp[kStSmallParts];
-    st.small_keys += sp[kStSmallKeys];
-    st.band_keys += sp[kStBandKeys];
-    st.presorted += (uint32_t)(sp[kStPresorted] + sp[kStPresortedRoots]);
-  }
-  for (int i = 0; i < d; i++)
-    if (env.h_lvl[i].packed >> 40) st.max_depth = (uint32_t)i;
-  for (int i = 0; i < d && i < TSQS_MAX_LEVELS; i++) {
-    st.level_keys[i] = env.h_lvl[i].keys;
-    st.level_parts[i] = (uint32_t)(env.h_lvl[i].packed >> 40);
-    st.partition_bytes += 2ull * env.h_lvl[i].keys * (kb + (HASV ? 4 : 0));
-    if (!(i == 0 && roots_small)) st.partition_launches++;
-    if (timing) {
-      float ms = 0.f;
-      HIPCHK(hipEventElapsedTime(&ms, env.ev[2 * i], env.ev[2 * i + 1]));
-      st.level_ms[i] = ms;
-      st.partition_ms += ms;
-    }
-  }
-  g_have_stats = true;
+  LastCall &lc = g_last;
+  lc.valid = true;
+  lc.done = env.done;
+  lc.s = s;
+  lc.d_lvl = w.lvl;
+  lc.d_stats = w.stats;
+  lc.h_lvl = env.h_lvl;
+  lc.h_stats = env.h_stats;
+  lc.ev = timing ? env.ev : nullptr;
+  lc.levels = expected;
+  lc.roots_small = roots_small;
+  lc.n = n;
+  lc.kb = (uint32_t)kb;
+  lc.vb = HASV ? 4u : 0u;
+  lc.schedule = persistent ? 1u : 0u;
   return TSQS_OK;
 }
 
@@ -231,7 +276,8 @@ int queue_tick(tsqs_queue *q, QGroup &G) {
   c.done_ring = q->d_ring;
   c.done_pos = q->d_pos;
   c.done_cap = kQMaxReq;
-  c.pad1 = 0;
+  c.fin_roots_only = 0;
+  c.p = PCtx();
   c.root_level = d;
   c.ring = 1;
   c.n = 0;

@@ -23,9 +23,8 @@ namespace tsqs {
 namespace host {
 Options g_opt;
 std::mutex g_mu;
-tsqs_stats_t g_stats;
-bool g_have_stats = false;
 uint64_t g_calls = 0;
+LastCall g_last;
 }  // namespace host
 }  // namespace tsqs
 
@@ -56,10 +55,14 @@ void free_ws(Workspace &w) {
   (void)hipFree(w.lvl); (void)hipFree(w.stats); (void)hipFree(w.offs);
   (void)hipHostFree(w.h_lvl); (void)hipHostFree(w.h_stats);
   if (w.ev_ok) for (int i = 0; i < 2 * kMaxLevels; i++) (void)hipEventDestroy(w.ev[i]);
+  (void)hipFree(w.task); (void)hipFree(w.seq); (void)hipFree(w.ctl);
+  (void)hipFree(w.parts); (void)hipFree(w.pctr); (void)hipFree(w.hist); (void)hipFree(w.bands);
+  (void)hipFree(w.sfin);
+  if (w.done) (void)hipEventDestroy(w.done);
   w = Workspace();
 }
 
-int ensure_static(Workspace &w, int dev) {
+int ensure_static(Workspace &w, int dev, hipStream_t s) {
   if (w.init) return TSQS_OK;
   hipDeviceProp_t prop;
   HIPCHK(hipGetDeviceProperties(&prop, dev));
@@ -70,13 +73,28 @@ int ensure_static(Workspace &w, int dev) {
   if (hipMalloc(&w.stats, stat_bytes) != hipSuccess) return TSQS_ENOMEM;
   if (hipHostMalloc(&w.h_lvl, sizeof(LevelCtl) * kMaxLevels, hipHostMallocDefault) != hipSuccess) return TSQS_ENOMEM;
   if (hipHostMalloc(&w.h_stats, stat_bytes, hipHostMallocDefault) != hipSuccess) return TSQS_ENOMEM;
+  if (hipMalloc(&w.ctl, sizeof(unsigned long long) * kQWords) != hipSuccess) return TSQS_ENOMEM;
+  HIPCHK(hipMemsetAsync(w.ctl, 0, sizeof(unsigned long long) * kQWords, s));
+  HIPCHK(hipEventCreateWithFlags(&w.done, hipEventDisableTiming));
   w.init = true;
   return TSQS_OK;
 }
 
+// The workspace's buffers may be freed (grown) only after the work that uses
+// them: the last call's completion.
+int ws_quiesce(Workspace &w) {
+  if (w.done_rec) HIPCHK(hipEventSynchronize(w.done));
+  return TSQS_OK;
+}
+
 // Workspace buffers of the allocating entry points, grown to what the call needs.
-int ws_grow(Workspace &w, const WsNeed &nd, bool hasv, WsView *v) {
+int ws_grow(Workspace &w, const WsNeed &nd, bool hasv, WsView *v, hipStream_t s) {
   int rc;
+  const bool grows = w.s_bytes < nd.s_bytes || (hasv && w.v_cap < nd.v_elems) || w.seg_cap < nd.seg_cap ||
+                     w.slot_cap < nd.slot_cap || w.band_cap < nd.band_cap || w.big_cap < nd.big_cap ||
+                     (nd.offs && w.off_cap < nd.offs) || w.qcap < nd.qcap || w.part_cap < nd.part_cap ||
+                     w.hist_cap < nd.hist_cap || w.lband_cap < nd.lband_cap || w.sfin_cap < nd.sfin_cap;
+  if (grows && (rc = ws_quiesce(w)) != TSQS_OK) return rc;
   {
     size_t cap_bytes = w.s_bytes;
     void *S = w.S;
@@ -106,6 +124,28 @@ int ws_grow(Workspace &w, const WsNeed &nd, bool hasv, WsView *v) {
   if ((rc = grow(&w.band, &w.band_cap, nd.band_cap)) != TSQS_OK) return rc;
   if ((rc = grow(&w.big, &w.big_cap, nd.big_cap)) != TSQS_OK) return rc;
   if (nd.offs && (rc = grow(&w.offs, &w.off_cap, nd.offs)) != TSQS_OK) return rc;
+  if (w.qcap < nd.qcap) {
+    // a new ring: its sequence words and indices start from zero
+    size_t a = w.qcap, b = w.qcap;
+    if ((rc = grow(&w.task, &a, nd.qcap)) != TSQS_OK) return rc;
+    if ((rc = grow(&w.seq, &b, nd.qcap)) != TSQS_OK) return rc;
+    HIPCHK(hipMemsetAsync(w.seq, 0, sizeof(unsigned long long) * nd.qcap, s));
+    HIPCHK(hipMemsetAsync(w.ctl, 0, sizeof(unsigned long long) * kQWords, s));
+    w.qcap = nd.qcap;
+  }
+  if (w.part_cap < nd.part_cap) {
+    size_t a = w.part_cap, b = w.part_cap * kCtrStride;
+    if ((rc = grow(&w.parts, &a, nd.part_cap)) != TSQS_OK) return rc;
+    if ((rc = grow(&w.pctr, &b, nd.part_cap * kCtrStride)) != TSQS_OK) return rc;
+    w.part_cap = nd.part_cap;
+  }
+  if (w.hist_cap < nd.hist_cap) {
+    size_t a = w.hist_cap * 256;
+    if ((rc = grow(&w.hist, &a, nd.hist_cap * 256)) != TSQS_OK) return rc;
+    w.hist_cap = nd.hist_cap;
+  }
+  if ((rc = grow(&w.bands, &w.lband_cap, nd.lband_cap)) != TSQS_OK) return rc;
+  if ((rc = grow(&w.sfin, &w.sfin_cap, nd.sfin_cap)) != TSQS_OK) return rc;
   if (g_opt.timing && !w.ev_ok) {
     for (int i = 0; i < 2 * kMaxLevels; i++) HIPCHK(hipEventCreate(&w.ev[i]));
     w.ev_ok = true;
@@ -115,6 +155,10 @@ int ws_grow(Workspace &w, const WsNeed &nd, bool hasv, WsView *v) {
   v->fin = w.fin; v->finw = w.finw; v->band = w.band; v->big = w.big;
   v->lvl = w.lvl; v->stats = w.stats; v->offs = w.offs;
   v->seg_cap = nd.seg_cap; v->slot_cap = nd.slot_cap; v->big_cap = nd.big_cap;
+  v->task = w.task; v->seq = w.seq; v->ctl = w.ctl; v->parts = w.parts; v->pctr = w.pctr;
+  v->hist = w.hist; v->bands = w.bands; v->sfin = w.sfin;
+  v->qcap = w.qcap; v->part_cap = w.part_cap; v->hist_cap = w.hist_cap; v->band_cap = w.lband_cap;
+  v->sfin_cap = w.sfin_cap;
   return TSQS_OK;
 }
 
@@ -148,24 +192,79 @@ int dispatch(void *keys, uint32_t *vals, const uint64_t *h_offs, size_t nroots, 
   if (dev < 0) return TSQS_EDEVICE;
   if ((size_t)dev >= g_ws.size()) g_ws.resize((size_t)dev + 1);
   Workspace &w = g_ws[(size_t)dev];
-  int rc = ensure_static(w, dev);
+  int rc = ensure_static(w, dev, s);
   if (rc != TSQS_OK) return rc;
-  g_have_stats = false;
+  g_last.valid = false;
   if (!dtype_ok(dt)) return TSQS_EUNSUPPORTED;
   const bool hv = vals != nullptr;
   const FinGeom geo = geom_any(dt, w.lds_budget, hv);
   const WsNeed nd = ws_need(n, nroots, dt_bytes(dt), hv, geo.small_max, h_offs != nullptr);
   CallEnv env;
-  if ((rc = ws_grow(w, nd, hv, &env.v)) != TSQS_OK) return rc;
+  // one workspace per device: a call on another stream starts after the last one
+  if (w.done_rec && w.last_stream != s) HIPCHK(hipStreamWaitEvent(s, w.done, 0));
+  if ((rc = ws_grow(w, nd, hv, &env.v, s)) != TSQS_OK) return rc;
   env.cus = w.cus;
   env.lds_budget = w.lds_budget;
   env.h_lvl = w.h_lvl;
   env.h_stats = w.h_stats;
   env.ev = w.ev_ok ? w.ev : nullptr;
+  env.done = w.done;
   CallArgs a;
   a.keys = keys; a.vals = vals; a.h_offs = h_offs; a.nroots = nroots; a.n = n;
   a.max_root = max_root; a.s = s;
-  return sort_any(dt, env, a);
+  rc = sort_any(dt, env, a);
+  if (rc == TSQS_OK) {
+    w.done_rec = true;
+    w.last_stream = s;
+  }
+  return rc;
+}
+
+// Statistics of the last call (waits for its completion).
+int stats_of_last(tsqs_stats_t *out) {
+  const LastCall &lc = g_last;
+  if (!lc.valid) return TSQS_EINVAL;
+  if (lc.done) HIPCHK(hipEventSynchronize(lc.done));
+  else HIPCHK(hipStreamSynchronize(lc.s));
+  const size_t nlv = (size_t)lc.levels + 1;
+  const size_t nst = kStripes * kStatWords + 16;
+  HIPCHK(hipMemcpy(lc.h_lvl, lc.d_lvl, sizeof(LevelCtl) * nlv, hipMemcpyDeviceToHost));
+  HIPCHK(hipMemcpy(lc.h_stats, lc.d_stats, sizeof(unsigned long long) * nst, hipMemcpyDeviceToHost));
+  tsqs_stats_t &st = *out;
+  std::memset(&st, 0, sizeof st);
+  st.levels = lc.levels;
+  st.n = lc.n;
+  st.key_bytes = lc.kb;
+  st.payload_bytes = lc.vb;
+  st.schedule = lc.schedule;
+  for (int i = 0; i < kStripes; i++) {
+    const unsigned long long *sp = lc.h_stats + (size_t)i * kStatWords;
+    st.fallback_parts += sp[kStFallback];
+    st.small_parts += sp[kStSmallParts];
+    st.small_keys += sp[kStSmallKeys];
+    st.band_keys += sp[kStBandKeys];
+    st.presorted += (uint32_t)(sp[kStPresorted] + sp[kStPresortedRoots]);
+    st.tail_parts += sp[kStTailParts];
+    st.tail_keys += sp[kStTailKeys];
+    st.select_rounds += sp[kStSelRounds];
+  }
+  for (uint32_t i = 0; i < lc.levels; i++)
+    if (lc.h_lvl[i].packed >> 40) st.max_depth = i;
+  for (uint32_t i = 0; i < lc.levels && i < TSQS_MAX_LEVELS; i++) {
+    st.level_keys[i] = lc.h_lvl[i].keys;
+    st.level_parts[i] = (uint32_t)(lc.h_lvl[i].packed >> 40);
+    st.partition_bytes += 2ull * lc.h_lvl[i].keys * (lc.kb + lc.vb);
+    if (!(i == 0 && lc.roots_small)) st.partition_launches++;
+    if (lc.ev) {
+      float ms = 0.f;
+      HIPCHK(hipEventElapsedTime(&ms, lc.ev[2 * i], lc.ev[2 * i + 1]));
+      st.level_ms[i] = ms;
+      st.partition_ms += ms;
+    }
+  }
+  st.tail_bytes = 2ull * st.tail_keys * (lc.kb + lc.vb);
+  st.error_flags = (uint32_t)lc.h_stats[kStripes * kStatWords];
+  return st.error_flags ? TSQS_EINTERNAL : TSQS_OK;
 }
 
 // ---- autotuner inputs: seeded uniform keys (SplitMix64) and payload = index ----
@@ -586,10 +685,21 @@ ScratchDev g_scr[kMaxDevices];
 LevelCtl g_scr_lvl[kMaxLevels];
 unsigned long long g_scr_stats[kStripes * kStatWords + 16];
 
+// The persistent schedule's ring and control words sit at the start of the
+// array, at the same place for every call: a ring slot's sequence word must
+// never have held anything but sequence words (cleared once at set-up).
+constexpr size_t kScrQcap = 1u << 14;
+constexpr size_t kScrRingBytes = kScrQcap * (sizeof(Task) + sizeof(unsigned long long)) +
+                                 kQWords * sizeof(unsigned long long);
+
 // Lays the buffers of a call out in [base, base + cap) (256-byte aligned
-// pieces); false if they do not fit.
+// pieces, after the ring); false if they do not fit.
 bool carve(unsigned char *base, size_t cap, const WsNeed &nd, bool hasv, WsView *v) {
-  size_t off = 0;
+  v->seq = (unsigned long long *)base;
+  v->ctl = v->seq + kScrQcap;
+  v->task = (Task *)(v->ctl + kQWords);
+  v->qcap = kScrQcap;
+  size_t off = (kScrRingBytes + 255) & ~(size_t)255;
   auto take = [&](size_t bytes) -> unsigned char * {
     unsigned char *p = base + off;
     off += (bytes + 255) & ~(size_t)255;
@@ -612,7 +722,16 @@ bool carve(unsigned char *base, size_t cap, const WsNeed &nd, bool hasv, WsView 
   v->seg_cap = nd.seg_cap;
   v->slot_cap = nd.slot_cap;
   v->big_cap = nd.big_cap;
-  return off <= cap;
+  v->parts = (TPart *)take(nd.part_cap * sizeof(TPart));
+  v->pctr = (unsigned long long *)take(nd.part_cap * kCtrStride * sizeof(unsigned long long));
+  v->hist = (uint32_t *)take(nd.hist_cap * 256 * sizeof(uint32_t));
+  v->bands = (FinItem *)take(nd.lband_cap * sizeof(FinItem));
+  v->sfin = (FinItem *)take(nd.sfin_cap * sizeof(FinItem));
+  v->sfin_cap = nd.sfin_cap;
+  v->part_cap = nd.part_cap;
+  v->hist_cap = nd.hist_cap;
+  v->band_cap = nd.lband_cap;
+  return off <= cap && nd.qcap <= kScrQcap;
 }
 
 }  // namespace
@@ -635,9 +754,14 @@ extern "C" int tsqs_sort_noalloc(void *d_keys, uint32_t *d_vals, size_t nmemb, i
     sd.ptr = (unsigned char *)ptr;
     sd.cus = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
     sd.lds_budget = prop.sharedMemPerBlock > 0 ? (size_t)prop.sharedMemPerBlock : 65536;
+    // the ring's sequence and control words start at zero (a kernel, on the
+    // caller's stream, before any use)
+    hipLaunchKernelGGL(k_zero, dim3(64), dim3(256), 0, (hipStream_t)stream, (unsigned long long *)sd.ptr,
+                       (uint64_t)(kScrQcap + kQWords));
+    HIPCHK(hipGetLastError());
     sd.ready = true;
   }
-  g_have_stats = false;
+  g_last.valid = false;
   const bool hv = d_vals != nullptr;
   const FinGeom geo = geom_any(dt, sd.lds_budget, hv);
   const WsNeed nd = ws_need((uint64_t)nmemb, 1, dt_bytes(dt), hv, geo.small_max, false);
@@ -689,7 +813,6 @@ int tsqs_sort_records(void *d_keys, void *d_records, size_t rec_bytes, void *d_o
   hipStream_t s = (hipStream_t)stream;
   if (nmemb == 1) {
     if (d_out) HIPCHK(hipMemcpyAsync(d_out, d_records, rec_bytes, hipMemcpyDeviceToDevice, s));
-    HIPCHK(hipStreamSynchronize(s));
     return TSQS_OK;
   }
   std::lock_guard<std::mutex> lk(g_rec_mu);
@@ -699,6 +822,12 @@ int tsqs_sort_records(void *d_keys, void *d_records, size_t rec_bytes, void *d_o
   if ((size_t)dev >= g_rec.size()) g_rec.resize((size_t)dev + 1);
   RecWs &r = g_rec[(size_t)dev];
   int rc;
+  if (r.idx_cap < nmemb || (!d_out && r.tmp_cap < total)) {
+    // the index and the staging buffer are regrown only after the last call
+    std::lock_guard<std::mutex> lk2(g_mu);
+    if ((size_t)dev < g_ws.size() && g_ws[(size_t)dev].init && (rc = ws_quiesce(g_ws[(size_t)dev])) != TSQS_OK)
+      return rc;
+  }
   if ((rc = grow(&r.idx, &r.idx_cap, nmemb)) != TSQS_OK) return rc;
   if ((rc = grow(&r.err, &r.err_cap, 1)) != TSQS_OK) return rc;
   int cus = 256;
@@ -719,28 +848,39 @@ int tsqs_sort_records(void *d_keys, void *d_records, size_t rec_bytes, void *d_o
     if ((rc = grow(&r.tmp, &r.tmp_cap, total)) != TSQS_OK) return rc;
     dst = r.tmp;
   }
+  unsigned int *err = nullptr;
+  {
+    std::lock_guard<std::mutex> lk2(g_mu);
+    err = (unsigned int *)(g_ws[(size_t)dev].stats + kStripes * kStatWords);
+  }
   const uintptr_t al = (uintptr_t)d_records | (uintptr_t)dst | (uintptr_t)rec_bytes;
   const size_t wsz = (al & 15u) == 0 ? 16 : (al & 7u) == 0 ? 8 : (al & 3u) == 0 ? 4 : 1;
   const uint64_t gtiles = (total / wsz + (uint64_t)kRecNT * kRecU - 1) / ((uint64_t)kRecNT * kRecU);
   const int ggrid = (int)(gtiles < (uint64_t)(16 * cus) ? gtiles : (uint64_t)(16 * cus));
   if ((al & 15u) == 0)
     hipLaunchKernelGGL(k_rec_gather<uint4>, dim3(ggrid), dim3(kRecNT), 0, s, (const uint4 *)d_records,
-                       (uint4 *)dst, r.idx, (uint64_t)nmemb, (uint32_t)(rec_bytes / 16), r.err);
+                       (uint4 *)dst, r.idx, (uint64_t)nmemb, (uint32_t)(rec_bytes / 16), err);
   else if ((al & 7u) == 0)
     hipLaunchKernelGGL(k_rec_gather<uint2>, dim3(ggrid), dim3(kRecNT), 0, s, (const uint2 *)d_records,
-                       (uint2 *)dst, r.idx, (uint64_t)nmemb, (uint32_t)(rec_bytes / 8), r.err);
+                       (uint2 *)dst, r.idx, (uint64_t)nmemb, (uint32_t)(rec_bytes / 8), err);
   else if ((al & 3u) == 0)
     hipLaunchKernelGGL(k_rec_gather<uint32_t>, dim3(ggrid), dim3(kRecNT), 0, s, (const uint32_t *)d_records,
-                       (uint32_t *)dst, r.idx, (uint64_t)nmemb, (uint32_t)(rec_bytes / 4), r.err);
+                       (uint32_t *)dst, r.idx, (uint64_t)nmemb, (uint32_t)(rec_bytes / 4), err);
   else
     hipLaunchKernelGGL(k_rec_gather<uint8_t>, dim3(ggrid), dim3(kRecNT), 0, s, (const uint8_t *)d_records,
-                       (uint8_t *)dst, r.idx, (uint64_t)nmemb, (uint32_t)rec_bytes, r.err);
+                       (uint8_t *)dst, r.idx, (uint64_t)nmemb, (uint32_t)rec_bytes, err);
   HIPCHK(hipGetLastError());
   if (!d_out) HIPCHK(hipMemcpyAsync(d_records, r.tmp, total, hipMemcpyDeviceToDevice, s));
-  unsigned int h_err = 0;
-  HIPCHK(hipMemcpyAsync(&h_err, r.err, sizeof h_err, hipMemcpyDeviceToHost, s));
-  HIPCHK(hipStreamSynchronize(s));
-  return h_err ? TSQS_EINTERNAL : TSQS_OK;
+  {
+    // the call ends after the gather: later calls wait for it, and its
+    // statistics (and an index that was not a permutation) are read after it
+    std::lock_guard<std::mutex> lk2(g_mu);
+    Workspace &w = g_ws[(size_t)dev];
+    HIPCHK(hipEventRecord(w.done, s));
+    w.done_rec = true;
+    w.last_stream = s;
+  }
+  return TSQS_OK;
 }
 
 int tsqs_sort_batch(void *d_keys, uint32_t *d_vals, const uint64_t *h_offsets, size_t nseg,
@@ -800,6 +940,8 @@ int tsqs_set_option(int key, int64_t v) {
     case TSQS_OPT_FINISH_GRID: if (v < 0 || v > 65536) return TSQS_EINVAL; g_opt.finish_grid = v; return TSQS_OK;
     case TSQS_OPT_FINISH_ALGO: if (v < 0 || v > 3) return TSQS_EINVAL; g_opt.finish_algo = v; return TSQS_OK;
     case TSQS_OPT_PRESORT: g_opt.presort = v ? 1 : 0; return TSQS_OK;
+    case TSQS_OPT_SCHEDULE: if (v < 0 || v > 1) return TSQS_EINVAL; g_opt.schedule = v; return TSQS_OK;
+    case TSQS_OPT_ITER_CAP: if (v < 0) return TSQS_EINVAL; g_opt.iter_cap = v; return TSQS_OK;
     default: return TSQS_EUNSUPPORTED;
   }
 }
@@ -817,6 +959,8 @@ int64_t tsqs_get_option(int key) {
     case TSQS_OPT_FINISH_GRID: return g_opt.finish_grid;
     case TSQS_OPT_FINISH_ALGO: return g_opt.finish_algo;
     case TSQS_OPT_PRESORT: return g_opt.presort;
+    case TSQS_OPT_SCHEDULE: return g_opt.schedule;
+    case TSQS_OPT_ITER_CAP: return g_opt.iter_cap;
     default: return INT64_MIN;
   }
 }
@@ -824,9 +968,7 @@ int64_t tsqs_get_option(int key) {
 int tsqs_get_stats(tsqs_stats_t *out) {
   std::lock_guard<std::mutex> lk(g_mu);
   if (!out) return TSQS_EINVAL;
-  if (!g_have_stats) return TSQS_EINVAL;
-  *out = g_stats;
-  return TSQS_OK;
+  return stats_of_last(out);
 }
 
 const char *tsqs_strerror(int code) {
@@ -843,7 +985,7 @@ const char *tsqs_strerror(int code) {
   }
 }
 
-int tsqs_version(void) { return 1; }
+int tsqs_version(void) { return 2; }
 
 }  // extern "C"
 
@@ -903,6 +1045,7 @@ int tsqs_autotune(int dt, int with_payload, size_t n, const uint64_t *h_offsets,
       else if (with_payload) r = tsqs_sort_pairs(keys, vals, n, dt, s);
       else r = tsqs_sort(keys, n, dt, s);
       if (r != TSQS_OK) return r;
+      HIPCHK(hipStreamSynchronize(s));
       const double t = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
       if (rep > 0 && t < best) best = t;
     }

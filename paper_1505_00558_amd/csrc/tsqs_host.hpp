@@ -11,6 +11,7 @@
 #include "tsqs.h"
 #include "tsqs_queue.h"
 #include "tsqs_kernels.hpp"
+#include "tsqs_persist.hpp"
 
 #include <hip/hip_runtime.h>
 
@@ -46,7 +47,11 @@ struct Options {
   int64_t finish_grid = 0;
   int64_t finish_algo = 3;
   int64_t presort = 1;
+  int64_t schedule = 0;        // TSQS_OPT_SCHEDULE
+  int64_t iter_cap = 0;        // TSQS_OPT_ITER_CAP (0: the default)
 };
+
+constexpr unsigned long long kDefaultIterCap = 1ull << 23;
 
 // Device buffers of one call: the scratch copy of the keys (and payloads), the
 // level tables and the small-part / band slots.  Capacities in elements.
@@ -60,11 +65,21 @@ struct WsView {
   unsigned long long *stats = nullptr;   // kStripes x kStatWords, then 16 words of flags
   uint64_t *offs = nullptr;
   size_t seg_cap = 0, slot_cap = 0, big_cap = 0;
+  // persistent schedule: task ring, its control words, the part pool
+  Task *task = nullptr;
+  unsigned long long *seq = nullptr, *ctl = nullptr;
+  TPart *parts = nullptr;
+  unsigned long long *pctr = nullptr;
+  uint32_t *hist = nullptr;
+  FinItem *bands = nullptr;
+  FinItem *sfin = nullptr;
+  size_t qcap = 0, part_cap = 0, hist_cap = 0, band_cap = 0, sfin_cap = 0;
 };
 
 // Element counts a call needs (see ws_need).
 struct WsNeed {
   size_t s_bytes = 0, v_elems = 0, seg_cap = 0, slot_cap = 0, band_cap = 0, big_cap = 0, offs = 0;
+  size_t qcap = 0, part_cap = 0, hist_cap = 0, lband_cap = 0, sfin_cap = 0;   // persistent schedule
 };
 
 // Per-device workspace of the allocating entry points: grows to the largest
@@ -90,6 +105,37 @@ struct Workspace {
   unsigned long long *h_stats = nullptr; // pinned
   hipEvent_t ev[2 * kMaxLevels];
   bool ev_ok = false;
+  // persistent schedule
+  size_t qcap = 0, part_cap = 0, hist_cap = 0, lband_cap = 0, sfin_cap = 0;
+  FinItem *sfin = nullptr;
+  Task *task = nullptr;
+  unsigned long long *seq = nullptr, *ctl = nullptr;
+  TPart *parts = nullptr;
+  unsigned long long *pctr = nullptr;
+  uint32_t *hist = nullptr;
+  FinItem *bands = nullptr;
+  // the last call's completion: later calls on another stream wait for it,
+  // buffers are freed or regrown only after it
+  hipEvent_t done = nullptr;
+  bool done_rec = false;
+  hipStream_t last_stream = nullptr;
+};
+
+// What the statistics of the last call need (read when they are asked for).
+struct LastCall {
+  bool valid = false;
+  hipEvent_t done = nullptr;             // or null: synchronise the stream
+  hipStream_t s = nullptr;
+  const LevelCtl *d_lvl = nullptr;
+  const unsigned long long *d_stats = nullptr;
+  LevelCtl *h_lvl = nullptr;
+  unsigned long long *h_stats = nullptr;
+  hipEvent_t *ev = nullptr;              // per-level timing events, or null
+  uint32_t levels = 0;
+  bool roots_small = false;
+  uint64_t n = 0;
+  uint32_t kb = 4, vb = 0;
+  uint32_t schedule = 0;
 };
 
 // Where a call's device buffers come from and where its level table is read back.
@@ -100,6 +146,7 @@ struct CallEnv {
   LevelCtl *h_lvl = nullptr;             // host copy of the level table (kMaxLevels)
   unsigned long long *h_stats = nullptr; // host copy of the statistics words
   hipEvent_t *ev = nullptr;              // 2 * kMaxLevels timing events, or null
+  hipEvent_t done = nullptr;             // recorded at the end of the call, or null
 };
 
 struct CallArgs {
@@ -114,9 +161,8 @@ struct CallArgs {
 
 extern Options g_opt;
 extern std::mutex g_mu;
-extern tsqs_stats_t g_stats;
-extern bool g_have_stats;
 extern uint64_t g_calls;
+extern LastCall g_last;
 
 template <typename T>
 int grow(T **p, size_t *cap, size_t need, size_t elem = sizeof(T)) {
@@ -176,6 +222,12 @@ FinGeom fin_geom(size_t lds_budget, int64_t small_opt) {
 
 // Buffer sizes of a call of n keys in nroots arrays with small parts of up to
 // small_max keys.
+inline size_t pow2_at_least(size_t x) {
+  size_t p = 1;
+  while (p < x) p <<= 1;
+  return p;
+}
+
 inline WsNeed ws_need(uint64_t n, size_t nroots, size_t kb, bool hasv, uint32_t small_max, bool batch) {
   WsNeed w;
   w.s_bytes = (size_t)n * kb;
@@ -185,6 +237,16 @@ inline WsNeed ws_need(uint64_t n, size_t nroots, size_t kb, bool hasv, uint32_t 
   w.band_cap = 3 * w.seg_cap;
   w.big_cap = 2 * (size_t)(n / kBandChunk) + 16;
   w.offs = batch ? nroots + 1 : 0;
+  // persistent schedule: every part of the recursion below the parts it is
+  // given (at most about 2 n / small_max), the roots, and the ring with room
+  // for every task that can be waiting at once
+  w.part_cap = 3 * (size_t)(n / (small_max + 1)) + nroots + 1024;
+  w.hist_cap = w.part_cap < 4096 ? w.part_cap : 4096;
+  w.lband_cap = (size_t)(n / kBandChunk) + 64;
+  w.sfin_cap = 4 * w.part_cap;   // at most four small children per planned part
+  const size_t tasks = 2 * (size_t)(n / (4096ull * kTaskChunks)) + 2 * (size_t)(n / (kSelChunk * kTaskChunks)) +
+                       (size_t)(n / kBandChunk) + w.part_cap + 4096;
+  w.qcap = pow2_at_least(2 * tasks);
   return w;
 }
 

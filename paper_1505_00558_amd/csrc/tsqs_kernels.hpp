@@ -58,6 +58,11 @@ constexpr int kPlanNT = 256;
 constexpr int kPlanNW = kPlanNT / kWave;
 constexpr int kFinNT = 256;
 constexpr int kFinNW = kFinNT / kWave;
+constexpr int kPNT = 256;                  // threads of a persistent-schedule workgroup
+constexpr int kPNW = kPNT / kWave;
+constexpr uint32_t kTaskChunks = 4;        // chunks per partition / select task
+constexpr uint32_t kSelChunk = 8192;       // keys per select chunk
+constexpr uint32_t kSelInline = 1u << 16;  // exact pivots of parts up to this size: one wave
 constexpr uint32_t kBandChunk = 1u << 16;
 constexpr int kMaxLevels = 192;
 constexpr unsigned long long kTileMask = (1ull << 40) - 1;
@@ -67,6 +72,8 @@ constexpr int kStatWords = 16;
 enum { kStFallback = 0, kStSmallParts = 1, kStSmallKeys = 2, kStBandKeys = 3, kStPresorted = 4,
        kStPresortedRoots = 5 };
 constexpr uint32_t kErrSegCap = 1, kErrFinCap = 2, kErrLevel = 4, kErrCount = 8;
+constexpr uint32_t kErrQueue = 16;   // persistent schedule: task ring or part pool full
+constexpr uint32_t kErrIter = 32;    // persistent schedule: a workgroup reached its iteration cap
 
 // ---- order-preserving codes (compares are done on these, never on floats) --
 
@@ -121,9 +128,9 @@ template <> struct Codec<4> {  // float32 bits, IEEE totalOrder: negatives rever
 };
 
 // Geometry of the partition pass per element type and pass type.
-template <int DT, bool HASV, bool TWO> struct PartCfg {
+template <int DT, bool HASV, bool TWO, int NT_ = (TWO ? kPartNT2 : kPartNT1)> struct PartCfg {
   using B = typename Codec<DT>::B;
-  static constexpr int NT = TWO ? kPartNT2 : kPartNT1;                  // threads
+  static constexpr int NT = NT_;                                        // threads
   static constexpr int NW = NT / kWave;
   static constexpr int KB = (int)sizeof(B);
   static constexpr int VEC = 16 / KB;                                   // keys per 16-byte load
@@ -179,6 +186,45 @@ struct FinItem {             // work of the finish kernel (len 0 = empty slot)
   uint32_t kind;             // bit 1: small part lives in S; bits 2..31: request
 };
 
+// ---- persistent schedule (tsqs_persist.hpp): tasks, parts and the queue ----
+//
+// Workgroups of one kernel take tasks from a ring in device memory: chunks of
+// a part to partition, chunks of a part whose exact pivot is being selected
+// (one radix digit per round), or a piece of a long equal band.  A part lives
+// in a pool (TPart); the workgroup that finishes the last chunk of a part
+// plans it (bands, small children sorted on the spot, new parts and their
+// tasks).  A count of keys not yet final ends the kernel when it reaches zero.
+constexpr uint32_t kSegSel = 4;            // flag: the part's exact pivot is being selected
+enum : uint32_t { kTaskPart = 0, kTaskSelect = 1, kTaskBand = 2 };
+struct Task { uint32_t kind, id, c0, c1; };   // chunks [c0, c1) of part id / band piece c0 of band id
+struct TPart {
+  Seg s;                     // s.chunk_begin = 0
+  uint32_t nchunks;          // chunks of the current phase (partition or one select round)
+  uint32_t done;             // chunks of the current phase finished
+  uint32_t round;            // select: digits fixed so far
+  uint32_t krem;             // select: rank sought among the keys that match prefix
+  uint64_t prefix, mask;     // select: the fixed digits (codes)
+  uint32_t hslot, pad;       // select: histogram slot
+};
+// control words of the queue, one 128-byte line each
+enum { kQHead = 0, kQTail = 16, kQLeft = 32, kQAbort = 48, kQParts = 64, kQBands = 80, kQHist = 96,
+       kQFin = 112, kQFinw = 128, kQWords = 144 };
+struct PCtx {
+  Task *task;                      // ring of tasks
+  unsigned long long *seq;         // per ring slot: index + 1 once the task at that index is written
+  unsigned long long *ctl;         // kQWords control words
+  TPart *parts;                    // part pool (null: no persistent schedule)
+  unsigned long long *pctr;        // counter lines of the pool's parts (kCtrStride words each)
+  uint32_t *hist;                  // select histograms, 256 words per slot
+  FinItem *bands;                  // long bands waiting for band tasks
+  FinItem *sfin;                   // small parts left for k_finish_list: workgroup-sized ones
+                                   // from the front, wave-sized ones from the back
+  unsigned long long qmask;        // ring slots - 1 (a power of two - 1)
+  uint32_t part_cap, hist_cap, band_cap, grid;   // grid: workgroups of the persistent kernel
+  uint32_t sfin_cap, pad2;
+  unsigned long long iter_cap;     // loop iterations of a workgroup before it gives up
+};
+
 struct RootRec {             // an array to sort, given by place instead of by offsets
   uint64_t off;
   uint32_t len;
@@ -212,7 +258,7 @@ struct Ctx {
   volatile unsigned int *done_ring;  // host-visible: request + 1 of each completion, in order
   unsigned int *done_pos;            // completions so far (next ring position)
   uint32_t done_cap;                 // ring entries
-  uint32_t pad1;
+  uint32_t fin_roots_only;           // k_finish: only the roots' slots (no level parts yet)
   int root_level;                    // level whose parts and finish work the roots join
   uint32_t ring;                     // 1: level indices wrap around kMaxLevels
   uint64_t n;
@@ -226,6 +272,7 @@ struct Ctx {
   uint32_t seg_cap;                  // part records per level; child slots are 4 * seg_cap
   uint32_t big_cap;
   uint32_t presort_roots;            // 1: k_init checks each root for order itself (batches)
+  PCtx p;                            // persistent schedule (p.parts null: none)
 };
 
 // ---- wave helpers ------------------------------------------------------------
@@ -511,6 +558,111 @@ __device__ inline void put_band(const Ctx &c, int level, uint32_t si, uint64_t o
   }
 }
 
+// ---- persistent schedule: ring, pool, grid-wide selection ----------------------
+
+__device__ inline void persist_abort(const Ctx &c, uint32_t why) {
+  atomicOr(c.err, why);
+  __hip_atomic_store(&c.p.ctl[kQAbort], 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Publishes n tasks, task i built by make(i) (whole wave; lane 0 reserves the
+// ring slots).  What the wave wrote before is visible to the workgroups that
+// take them.  False (and the run aborted) if the ring would overrun slots not
+// yet read.
+template <typename F>
+__device__ inline bool push_tasks(const Ctx &c, uint32_t n, F make) {
+  if (n == 0) return true;
+  const uint32_t lane = lane_id();
+  unsigned long long base = 0;
+  uint32_t ok = 1;
+  if (lane == 0) {
+    base = atomicAdd(&c.p.ctl[kQTail], (unsigned long long)n);
+    const unsigned long long head =
+        __hip_atomic_load(&c.p.ctl[kQHead], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    // slots are reused once read: keep one claim per workgroup of margin
+    if (base + n > head + (c.p.qmask + 1) - 2ull * c.p.grid) ok = 0;
+  }
+  ok = shfl_u32(ok, 0);
+  base = shfl_u64(base, 0);
+  if (!ok) {
+    if (lane == 0) persist_abort(c, kErrQueue);
+    return false;
+  }
+  __threadfence();
+  for (uint32_t i = lane; i < n; i += kWave) c.p.task[(base + i) & c.p.qmask] = make(i);
+  __threadfence();
+  for (uint32_t i = lane; i < n; i += kWave)
+    __hip_atomic_store(&c.p.seq[(base + i) & c.p.qmask], base + i + 1, __ATOMIC_RELEASE,
+                       __HIP_MEMORY_SCOPE_AGENT);
+  return true;
+}
+
+// Chunks of a pool part's partition pass (persistent workgroups of kPNT
+// threads): windows of CH keys from the 128-byte line of its first key.
+template <int DT, bool HASV>
+__device__ inline uint32_t pool_chunks(const Ctx &c, uint64_t off, uint32_t len, uint32_t flags) {
+  using C1 = PartCfg<DT, HASV, false, kPNT>;
+  using C2 = PartCfg<DT, HASV, true, kPNT>;
+  const void *buf = (flags & kSegInS) ? c.S : c.K;
+  const uint64_t a0 = (uint64_t)(uintptr_t)buf / C1::KB + off;
+  const uint64_t ch = (flags & kSegTwo) ? C2::CH : C1::CH;
+  return (uint32_t)((a0 % C1::LINE + len + ch - 1) / ch);
+}
+
+// Writes pool part id (lane 0 writes the record; lanes clear its counter line).
+__device__ inline void pool_put(const Ctx &c, uint32_t id, const TPart &tp) {
+  const uint32_t lane = lane_id();
+  if (lane == 0) c.p.parts[id] = tp;
+  if (lane < (uint32_t)kCtrStride) c.p.pctr[(size_t)id * kCtrStride + lane] = 0ull;
+}
+
+// Tasks of a pool part's current phase (partition or one select round).
+__device__ inline bool pool_tasks(const Ctx &c, uint32_t id, uint32_t kind, uint32_t nchunks) {
+  return push_tasks(c, (nchunks + kTaskChunks - 1) / kTaskChunks, [&](uint32_t i) {
+    Task t;
+    t.kind = kind; t.id = id; t.c0 = i * kTaskChunks;
+    t.c1 = (i + 1) * kTaskChunks < nchunks ? (i + 1) * kTaskChunks : nchunks;
+    return t;
+  });
+}
+
+// The grid-wide selection of the k-th smallest key of a part, its exact pivot
+// (the depth limit, or the exact-minimum test mode): a pool part in select
+// phase and its first round of tasks.  Whole wave.  False if no histogram
+// slot or pool part is free (the caller then selects with one wave).  With
+// count, the part's keys are added to the count of keys not yet final (a part
+// that no pool part held before).
+__device__ inline bool start_select(const Ctx &c, uint64_t off, uint32_t len, uint32_t depth,
+                                    uint32_t dmax, uint32_t req, bool in_s, uint32_t k, bool count) {
+  const uint32_t lane = lane_id();
+  uint32_t id = ~0u, slot = ~0u;
+  if (lane == 0) {
+    const unsigned long long hs = atomicAdd(&c.p.ctl[kQHist], 1ull);
+    if (hs < c.p.hist_cap) {
+      const unsigned long long pid = atomicAdd(&c.p.ctl[kQParts], 1ull);
+      if (pid < c.p.part_cap) { id = (uint32_t)pid; slot = (uint32_t)hs; }
+    }
+  }
+  id = shfl_u32(id, 0);
+  slot = shfl_u32(slot, 0);
+  if (id == ~0u) return false;
+  TPart tp;
+  tp.s.off = off;
+#pragma unroll
+  for (int q = 0; q < 7; q++) tp.s.piv[q] = 0;
+  tp.s.len = len; tp.s.chunk_begin = 0; tp.s.depth = depth; tp.s.dmax = dmax; tp.s.req = req;
+  tp.s.flags = (in_s ? kSegInS : 0u) | kSegSel;
+  tp.s.nlt = 0; tp.s.neq = 0;
+  tp.nchunks = (len + kSelChunk - 1) / kSelChunk;
+  tp.done = 0; tp.round = 0; tp.krem = k; tp.prefix = 0; tp.mask = 0;
+  tp.hslot = slot; tp.pad = 0;
+  pool_put(c, id, tp);
+  for (uint32_t q = lane; q < 256; q += kWave) c.p.hist[(size_t)slot * 256 + q] = 0u;
+  if (count && lane == 0) atomicAdd(&c.p.ctl[kQLeft], (unsigned long long)len);
+  pool_tasks(c, id, kTaskSelect, tp.nchunks);
+  return true;
+}
+
 // Parts a workgroup emits in one iteration (up to 4 per wave), staged in LDS
 // and reserved in the next level with a single atomic (records keep the wave
 // order, so chunk_begin stays increasing with the record index).
@@ -554,6 +706,13 @@ __device__ inline void child(const Ctx &c, uint32_t slot, uint64_t off, uint32_t
   if (exact) {
     const uint32_t k = (c.pivot_mode == 1 && depth < dmax) ? 0u : len / 2;
     if (lane == 0 && depth >= dmax) stat_add(c, kStFallback, 1ull);
+    // a large part: its exact pivot is selected by the whole grid of the
+    // persistent schedule (the part waits there); else by this wave
+    if (len > kSelInline && c.p.parts &&
+        start_select(c, off, len, depth, dmax, req, in_s, k, true)) {
+      if (lane == 0) put_small(c, slot, 0, 0, false, req);
+      return;
+    }
     p0 = wave_select<DT>(Y, off, len, k, hist);
   }
   uint64_t piv[7];
@@ -636,6 +795,21 @@ static __global__ void k_reset(Ctx c) {
   for (int i = threadIdx.x; i < kStripes * kStatWords; i += blockDim.x) c.stats[i] = 0ull;
   if (threadIdx.x == 0) *c.err = 0u;
   if (c.pre && threadIdx.x < 2) c.pre[threadIdx.x] = 0u;
+  if (c.p.ctl && threadIdx.x == 0) {
+    // ring indices only grow (a slot's sequence word then never matches an
+    // index of an earlier call); the other control words start at zero
+    unsigned long long *q = c.p.ctl;
+    const unsigned long long m = q[kQHead] > q[kQTail] ? q[kQHead] : q[kQTail];
+    q[kQHead] = m; q[kQTail] = m;
+    q[kQLeft] = 0; q[kQAbort] = 0; q[kQParts] = 0; q[kQBands] = 0; q[kQHist] = 0;
+    q[kQFin] = 0; q[kQFinw] = 0;
+  }
+}
+
+// Clears n words (setup of a fixed ring; no memset nodes in captured work).
+static __global__ void k_zero(unsigned long long *p, uint64_t n) {
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
+    p[i] = 0ull;
 }
 
 // Clears the counters of level `lvl` (a serving tick reuses level indices
@@ -907,6 +1081,10 @@ __device__ inline Seg load_seg(const CSeg *p) {
   return r;
 }
 
+// a part record written during the same kernel (the persistent schedule):
+// ordinary global loads
+__device__ inline Seg load_seg(const Seg *p) { return *p; }
+
 // s_waitcnt immediate (gfx9 encoding): lgkmcnt(0), the other counters free
 constexpr int kWaitLgkm0 = 0xC07F;
 
@@ -916,47 +1094,42 @@ __device__ inline T *at(T *base, uint32_t i) {
   else return (T *)((char *)base + (uint32_t)(i * (uint32_t)sizeof(T)));
 }
 
-// One partition level: every chunk of every part of level d whose pass type is
-// TWO (two-level parts); the parts of the other type are skipped (a
-// kernel per type, so each has the registers, and the occupancy, its own work
-// needs).  WIDE: some part may span 4 GiB or more of keys or payloads.
-template <int DT, bool HASV, bool WIDE, bool TWO>
-__global__ __launch_bounds__(TWO ? kPartNT2 : kPartNT1) void k_partition(Ctx c, int d) {
-  using Cfg = PartCfg<DT, HASV, TWO>;
+// LDS of a partition workgroup: per-wave class counts (one-level [<, >,
+// look-ahead <<, <=, ><, >=, = (payloads)], two-level [<<, <>, ><, >>, = of
+// each pivot (payloads), then the look-ahead sums as packed 16-bit fields]),
+// the part of the first chunk, and the stage: the keys of the next chunk,
+// loaded from HBM straight into LDS while the current chunk is processed; each
+// wave loads, and later reads, only its own blocks (element j * NT + tid is
+// window block j * NT + tid), so no barrier guards the stage.
+template <int DT, bool HASV, bool TWO, int NT>
+struct PartLds {
+  using Cfg = PartCfg<DT, HASV, TWO, NT>;
+  static constexpr bool STAGE = TWO ? kStageTwo : kStageOne;
+  uint32_t cnt[2][8][Cfg::NW];
+  uint32_t sh_part;
+  uint4 stage[STAGE ? Cfg::NLOAD * NT : 1];
+};
+
+// Partition of chunks [t0, t1) of the chunk space of the parts segs[0..nseg)
+// (each part's chunks start at its chunk_begin; parts whose pass type is not
+// TWO are skipped), workgroup of NT threads.  ctr: the parts' counter lines.
+// WIDE: some part may span 4 GiB or more of keys or payloads.  SP: pointer to
+// the records (constant address space when they are read-only for the kernel).
+template <int DT, bool HASV, bool WIDE, bool TWO, int NT, typename SP>
+__device__ __attribute__((always_inline)) inline void partition_chunks(
+    const Ctx &c, SP segs, unsigned long long *ctr, uint32_t nseg, uint32_t t0, uint32_t t1,
+    PartLds<DT, HASV, TWO, NT> &L) {
+  using Cfg = PartCfg<DT, HASV, TWO, NT>;
   using B = typename Cfg::B;
   using C = typename Codec<DT>::C;
   // keys staged through LDS (the next chunk's loads in flight during this one)
-  constexpr bool STAGE = TWO ? kStageTwo : kStageOne;
-  constexpr int NT = Cfg::NT, NW = Cfg::NW, VEC = Cfg::VEC, KPT = Cfg::KPT;
+  constexpr bool STAGE = PartLds<DT, HASV, TWO, NT>::STAGE;
+  constexpr int NW = Cfg::NW, VEC = Cfg::VEC, KPT = Cfg::KPT;
   constexpr int NLOAD = Cfg::NLOAD, KB = Cfg::KB;
   constexpr uint64_t CH = Cfg::CH;
-  // per-wave class counts: one-level [<, >, look-ahead <<, <=, ><, >=, = (payloads)],
-  // two-level [<<, <>, ><, >>, = of each pivot (payloads), then the look-ahead
-  // sums as packed 16-bit fields]
-  constexpr int NCLS = 8;
-  __shared__ uint32_t cnt[2][NCLS][NW];
-  __shared__ uint32_t sh_part;
-  // the keys of the next chunk, loaded from HBM straight into LDS while the
-  // current chunk is processed; each wave loads, and later reads, only its own
-  // blocks (element j * NT + tid is window block j * NT + tid), so no barrier
-  // guards the stage
-  __shared__ uint4 stage[STAGE ? NLOAD * NT : 1];
-
-  const unsigned long long packed = c.lvl[d].packed;
-  const uint32_t nseg = (uint32_t)(packed >> 40);
-  const uint32_t nch = (uint32_t)(packed & kTileMask);
-  // a failed capacity check leaves the count above the records written: stop
-  if (nch == 0 || nseg == 0 || nseg > c.seg_cap) return;
-  const uint32_t per = (nch + gridDim.x - 1) / gridDim.x;
-  const uint32_t t0 = blockIdx.x * per;
-  if (t0 >= nch) return;
-  const uint32_t t1 = (nch - t0 < per) ? nch : t0 + per;
-
-  // the records of level d are read-only here (written by the previous level's
-  // planning): read through the constant address space, so that uniform reads
-  // become scalar loads even after this kernel's own stores
-  const CSeg *segs = (const CSeg *)((d & 1) ? c.seg1 : c.seg0);
-  unsigned long long *ctr = (d & 1) ? c.ctr1 : c.ctr0;
+  auto &cnt = L.cnt;
+  auto &sh_part = L.sh_part;
+  auto &stage = L.stage;
   const uint32_t tid = threadIdx.x, lane = tid & 63u, w = tid >> 6;
 
   // part containing chunk t0: 64-ary search by wave 0
@@ -1413,6 +1586,30 @@ __global__ __launch_bounds__(TWO ? kPartNT2 : kPartNT1) void k_partition(Ctx c, 
     t = tn;
     pi = pn;
   }
+}
+
+// One partition level: every chunk of every part of level d whose pass type is
+// TWO (two-level parts); the parts of the other type are skipped (a kernel per
+// type, so each has the registers, and the occupancy, its own work needs).
+template <int DT, bool HASV, bool WIDE, bool TWO>
+__global__ __launch_bounds__(TWO ? kPartNT2 : kPartNT1) void k_partition(Ctx c, int d) {
+  constexpr int NT = TWO ? kPartNT2 : kPartNT1;
+  __shared__ PartLds<DT, HASV, TWO, NT> L;
+  const unsigned long long packed = c.lvl[d].packed;
+  const uint32_t nseg = (uint32_t)(packed >> 40);
+  const uint32_t nch = (uint32_t)(packed & kTileMask);
+  // a failed capacity check leaves the count above the records written: stop
+  if (nch == 0 || nseg == 0 || nseg > c.seg_cap) return;
+  const uint32_t per = (nch + gridDim.x - 1) / gridDim.x;
+  const uint32_t t0 = blockIdx.x * per;
+  if (t0 >= nch) return;
+  const uint32_t t1 = (nch - t0 < per) ? nch : t0 + per;
+  // the records of level d are read-only here (written by the previous level's
+  // planning): read through the constant address space, so that uniform reads
+  // become scalar loads even after this kernel's own stores
+  const CSeg *segs = (const CSeg *)((d & 1) ? c.seg1 : c.seg0);
+  unsigned long long *ctr = (d & 1) ? c.ctr1 : c.ctr0;
+  partition_chunks<DT, HASV, WIDE, TWO, NT>(c, segs, ctr, nseg, t0, t1, L);
 }
 
 // After level d: bands, small children, next-level parts with pivots (a wave per
@@ -2049,9 +2246,63 @@ __device__ inline void fill_band(const Ctx &c, const FinItem &it, uint32_t t, ui
 // ALGO: 0 bitonic network, 1 merging with ordered outputs, 2 merging with
 // register merge networks, 3 as 1 after cross-lane bitonic merging of runs of
 // up to 16 threads (merge_group).
+// One small part sorted by a workgroup of NTW threads (the algorithm's
+// records per thread chosen by the part's padded size).
+template <int DT, bool HASV, int ALGO, int NTW>
+__device__ __attribute__((always_inline)) inline void finish_group(
+    const Ctx &c, const FinItem &it, typename Rec<typename Codec<DT>::B, HASV>::T *lds, uint32_t tid) {
+  constexpr bool BITONIC = ALGO == 0, REG = ALGO == 2, HYB = ALGO == 3;
+  using T = typename Rec<typename Codec<DT>::B, HASV>::T;
+  const uint32_t P = next_pow2(it.len);
+  constexpr int ME = max_e<T>();
+  if constexpr (BITONIC) {
+    if (P <= 4 * NTW) sort_group<DT, HASV, NTW, 4>(c, it, lds, tid);
+    else if (P <= 8 * NTW || ME < 16) sort_group<DT, HASV, NTW, 8>(c, it, lds, tid);
+    else if constexpr (ME >= 16) {
+      if (P <= 16 * NTW || ME < 32) sort_group<DT, HASV, NTW, 16>(c, it, lds, tid);
+      else if constexpr (ME >= 32) sort_group<DT, HASV, NTW, 32>(c, it, lds, tid);
+    }
+  } else {
+    if (P <= 4 * NTW) merge_group<DT, HASV, NTW, 4, REG, HYB>(c, it, lds, tid);
+    else if (P <= 8 * NTW || ME < 16) merge_group<DT, HASV, NTW, 8, REG, HYB>(c, it, lds, tid);
+    else if constexpr (ME >= 16) {
+      if (P <= 16 * NTW || ME < 32) merge_group<DT, HASV, NTW, 16, REG, HYB>(c, it, lds, tid);
+      else if constexpr (ME >= 32) merge_group<DT, HASV, NTW, 32, REG, HYB>(c, it, lds, tid);
+    }
+  }
+}
+
+// One small part of at most wave_max keys sorted by a wave.
+template <int DT, bool HASV, int ALGO>
+__device__ __attribute__((always_inline)) inline void finish_wave(
+    const Ctx &c, const FinItem &it, typename Rec<typename Codec<DT>::B, HASV>::T *wl, uint32_t lane) {
+  constexpr bool BITONIC = ALGO == 0, REG = ALGO == 2, HYB = ALGO == 3;
+  using T = typename Rec<typename Codec<DT>::B, HASV>::T;
+  const uint32_t P = next_pow2(it.len);
+  constexpr int ME = max_e<T>();
+  if constexpr (BITONIC) {
+    if (P <= 64) sort_group<DT, HASV, kWave, 1>(c, it, wl, lane);
+    else if (P <= 128) sort_group<DT, HASV, kWave, 2>(c, it, wl, lane);
+    else if (P <= 256) sort_group<DT, HASV, kWave, 4>(c, it, wl, lane);
+    else if (P <= 512 || ME < 16) sort_group<DT, HASV, kWave, 8>(c, it, wl, lane);
+    else if constexpr (ME >= 16) {
+      if (P <= 1024 || ME < 32) sort_group<DT, HASV, kWave, 16>(c, it, wl, lane);
+      else if constexpr (ME >= 32) sort_group<DT, HASV, kWave, 32>(c, it, wl, lane);
+    }
+  } else {
+    if (P <= 64) merge_group<DT, HASV, kWave, 1, REG, HYB>(c, it, wl, lane);
+    else if (P <= 128) merge_group<DT, HASV, kWave, 2, REG, HYB>(c, it, wl, lane);
+    else if (P <= 256) merge_group<DT, HASV, kWave, 4, REG, HYB>(c, it, wl, lane);
+    else if (P <= 512 || ME < 16) merge_group<DT, HASV, kWave, 8, REG, HYB>(c, it, wl, lane);
+    else if constexpr (ME >= 16) {
+      if (P <= 1024 || ME < 32) merge_group<DT, HASV, kWave, 16, REG, HYB>(c, it, wl, lane);
+      else if constexpr (ME >= 32) merge_group<DT, HASV, kWave, 32, REG, HYB>(c, it, wl, lane);
+    }
+  }
+}
+
 template <int DT, bool HASV, int ALGO>
 __global__ __launch_bounds__(kFinNT) void k_finish(Ctx c, int d) {
-  constexpr bool BITONIC = ALGO == 0, REG = ALGO == 2, HYB = ALGO == 3;
   using B = typename Codec<DT>::B;
   using R = Rec<B, HASV>;
   using T = typename R::T;
@@ -2060,7 +2311,8 @@ __global__ __launch_bounds__(kFinNT) void k_finish(Ctx c, int d) {
   const uint32_t nseg = (uint32_t)(c.lvl[d].packed >> 40);
   const uint32_t nbig = c.lvl[d].nbig;
   if (nseg > c.seg_cap || nbig > c.big_cap) return;
-  const uint32_t nchild = 4 * nseg;
+  const uint32_t nchild = c.fin_roots_only ? 0u : 4 * nseg;
+  const uint32_t nbands = c.fin_roots_only ? 0u : 3 * nseg;
   const uint32_t nslots = nchild + (d == c.root_level ? c.nroots : 0u);
   const uint32_t tid = threadIdx.x;
   for (uint32_t ii = blockIdx.x; ii < nbig + nslots; ii += gridDim.x) {
@@ -2078,28 +2330,12 @@ __global__ __launch_bounds__(kFinNT) void k_finish(Ctx c, int d) {
     const uint32_t slot = q < nchild ? q : 4 * c.seg_cap + (q - nchild);
     const FinItem it = c.fin[slot];
     if (it.len == 0) continue;
-    const uint32_t P = next_pow2(it.len);
-    constexpr int ME = max_e<T>();
-    if constexpr (BITONIC) {
-      if (P <= 1024) sort_group<DT, HASV, kFinNT, 4>(c, it, lds, tid);
-      else if (P <= 2048 || ME < 16) sort_group<DT, HASV, kFinNT, 8>(c, it, lds, tid);
-      else if constexpr (ME >= 16) {
-        if (P <= 4096 || ME < 32) sort_group<DT, HASV, kFinNT, 16>(c, it, lds, tid);
-        else if constexpr (ME >= 32) sort_group<DT, HASV, kFinNT, 32>(c, it, lds, tid);
-      }
-    } else {
-      if (P <= 1024) merge_group<DT, HASV, kFinNT, 4, REG, HYB>(c, it, lds, tid);
-      else if (P <= 2048 || ME < 16) merge_group<DT, HASV, kFinNT, 8, REG, HYB>(c, it, lds, tid);
-      else if constexpr (ME >= 16) {
-        if (P <= 4096 || ME < 32) merge_group<DT, HASV, kFinNT, 16, REG, HYB>(c, it, lds, tid);
-        else if constexpr (ME >= 32) merge_group<DT, HASV, kFinNT, 32, REG, HYB>(c, it, lds, tid);
-      }
-    }
+    finish_group<DT, HASV, ALGO, kFinNT>(c, it, lds, tid);
   }
   const uint32_t wv = tid / kWave, lane = tid & 63u;
   T *wl = lds + (size_t)wv * lds_pad(c.wave_max);
   const uint32_t gw = blockIdx.x * kFinNW + wv, nw = gridDim.x * kFinNW;
-  for (uint32_t q = gw; q < nslots + 3 * nseg; q += nw) {
+  for (uint32_t q = gw; q < nslots + nbands; q += nw) {
     if (q >= nslots) {
       const FinItem bd = c.band[q - nslots];
       if (bd.len) {
@@ -2115,28 +2351,26 @@ __global__ __launch_bounds__(kFinNT) void k_finish(Ctx c, int d) {
     const uint32_t slot = q < nchild ? q : 4 * c.seg_cap + (q - nchild);
     const FinItem it = c.finw[slot];
     if (it.len == 0) continue;
-    const uint32_t P = next_pow2(it.len);
-    constexpr int ME = max_e<T>();
-    if constexpr (BITONIC) {
-      if (P <= 64) sort_group<DT, HASV, kWave, 1>(c, it, wl, lane);
-      else if (P <= 128) sort_group<DT, HASV, kWave, 2>(c, it, wl, lane);
-      else if (P <= 256) sort_group<DT, HASV, kWave, 4>(c, it, wl, lane);
-      else if (P <= 512 || ME < 16) sort_group<DT, HASV, kWave, 8>(c, it, wl, lane);
-      else if constexpr (ME >= 16) {
-        if (P <= 1024 || ME < 32) sort_group<DT, HASV, kWave, 16>(c, it, wl, lane);
-        else if constexpr (ME >= 32) sort_group<DT, HASV, kWave, 32>(c, it, wl, lane);
-      }
-    } else {
-      if (P <= 64) merge_group<DT, HASV, kWave, 1, REG, HYB>(c, it, wl, lane);
-      else if (P <= 128) merge_group<DT, HASV, kWave, 2, REG, HYB>(c, it, wl, lane);
-      else if (P <= 256) merge_group<DT, HASV, kWave, 4, REG, HYB>(c, it, wl, lane);
-      else if (P <= 512 || ME < 16) merge_group<DT, HASV, kWave, 8, REG, HYB>(c, it, wl, lane);
-      else if constexpr (ME >= 16) {
-        if (P <= 1024 || ME < 32) merge_group<DT, HASV, kWave, 16, REG, HYB>(c, it, wl, lane);
-        else if constexpr (ME >= 32) merge_group<DT, HASV, kWave, 32, REG, HYB>(c, it, wl, lane);
-      }
-    }
+    finish_wave<DT, HASV, ALGO>(c, it, wl, lane);
   }
+}
+
+// The small parts the persistent kernel listed (after it has ended).
+template <int DT, bool HASV, int ALGO>
+__global__ __launch_bounds__(kFinNT) void k_finish_list(Ctx c) {
+  using T = typename Rec<typename Codec<DT>::B, HASV>::T;
+  extern __shared__ unsigned char smem[];
+  T *lds = reinterpret_cast<T *>(smem);
+  const unsigned long long nf = c.p.ctl[kQFin], nw = c.p.ctl[kQFinw];
+  if (nf + nw > c.p.sfin_cap) return;   // overflow (reported by the persistent kernel)
+  const uint32_t tid = threadIdx.x;
+  for (unsigned long long i = blockIdx.x; i < nf; i += gridDim.x)
+    finish_group<DT, HASV, ALGO, kFinNT>(c, c.p.sfin[i], lds, tid);
+  const uint32_t wv = tid / kWave, lane = tid & 63u;
+  T *wl = lds + (size_t)wv * lds_pad(c.wave_max);
+  for (unsigned long long i = (unsigned long long)blockIdx.x * kFinNW + wv; i < nw;
+       i += (unsigned long long)gridDim.x * kFinNW)
+    finish_wave<DT, HASV, ALGO>(c, c.p.sfin[c.p.sfin_cap - 1 - i], wl, lane);
 }
 
 }  // namespace tsqs

@@ -17,12 +17,22 @@ def from_dev(t, dtype):
     return t.cpu().numpy().view(np.dtype(dtype))
 
 
+def device_ok():
+    """The last call reported no device error (its statistics wait for it)."""
+    import paper_1505_00558_amd as tsqs
+    rc, st = tsqs.last_call_status()
+    assert rc == tsqs.OK and st["error_flags"] == 0, (rc, st["error_flags"])
+    return st
+
+
 def gpu_sort(a):
     import paper_1505_00558_amd as tsqs
     import torch
     t = to_dev(a)
     tsqs.sort(t, CODES[np.dtype(a.dtype)])
     torch.cuda.synchronize()
+    if a.size > 1:
+        device_ok()
     return from_dev(t, a.dtype)
 
 
@@ -33,6 +43,8 @@ def gpu_sort_pairs(a, v):
     tv = to_dev(np.asarray(v, dtype=np.uint32))
     tsqs.sort_pairs(t, tv, CODES[np.dtype(a.dtype)])
     torch.cuda.synchronize()
+    if a.size > 1:
+        device_ok()
     return from_dev(t, a.dtype), from_dev(tv, np.uint32)
 
 

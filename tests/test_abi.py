@@ -42,7 +42,7 @@ def test_exports_every_declared_symbol(lib):
 
 
 def test_version_and_strerror(lib):
-    assert lib.tsqs_version() == 1
+    assert lib.tsqs_version() == 2
     import paper_1505_00558_amd as tsqs
     for code in (0, -1, -2, -3, -4, -5, -6):
         assert tsqs.strerror(code) and tsqs.strerror(code) != "unknown error code"
@@ -102,6 +102,14 @@ def test_options(lib):
         assert lib.tsqs_set_option(tsqs.OPT_PRESORT, 0) == 0
         assert tsqs.get_option(tsqs.OPT_PRESORT) == 0
         assert lib.tsqs_set_option(tsqs.OPT_PRESORT, 1) == 0
+        assert tsqs.get_option(tsqs.OPT_SCHEDULE) == 0
+        assert lib.tsqs_set_option(tsqs.OPT_SCHEDULE, 2) == -1
+        assert lib.tsqs_set_option(tsqs.OPT_SCHEDULE, 1) == 0
+        assert tsqs.get_option(tsqs.OPT_SCHEDULE) == 1
+        assert lib.tsqs_set_option(tsqs.OPT_SCHEDULE, 0) == 0
+        assert tsqs.get_option(tsqs.OPT_ITER_CAP) == 0
+        assert lib.tsqs_set_option(tsqs.OPT_ITER_CAP, -1) == -1
+        assert lib.tsqs_set_option(tsqs.OPT_ITER_CAP, 0) == 0
         assert lib.tsqs_set_option(999, 1) == -4
         assert tsqs.get_option(999) == -(1 << 63)
     finally:

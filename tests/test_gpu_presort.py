@@ -189,9 +189,10 @@ def test_batch_arrays(oracle_mod):
         assert np.array_equal(np.sort(gv), np.arange(keys.size)) and np.array_equal(keys[gv], got)
 
 
-def test_large_arrays_skip_the_schedule(oracle_mod):
-    """From 2^24 keys the host reads the check's answer and launches no level for an
-    array found in order; one pair out of order still takes every pass."""
+def test_large_arrays_skip_the_passes(oracle_mod):
+    """A large array found in order partitions nothing (its levels are launched
+    without waiting for the check's answer, and find no part); one pair out of
+    order still takes every pass."""
     import paper_1505_00558_amd as tsqs
     n = (1 << 24) + 5
     print("case: presort large", n, flush=True)
@@ -200,10 +201,11 @@ def test_large_arrays_skip_the_schedule(oracle_mod):
         got = gpu_sort(k)
         st = tsqs.get_stats()
         assert np.array_equal(got, asc)
-        assert st["presorted"] == want and st["levels"] == 0
+        assert st["presorted"] == want
+        assert sum(st["level_parts"]) == 0 and st["tail_parts"] == 0
     k = asc.copy()
     k[n - 3], k[n - 2] = k[n - 2], k[n - 3]
     got = gpu_sort(k)
     st = tsqs.get_stats()
     assert same_bits(got, oracle_mod.sort(k))
-    assert st["presorted"] == 0 and st["levels"] > 0
+    assert st["presorted"] == 0 and sum(st["level_parts"]) > 0
