@@ -69,6 +69,24 @@ def measured_traffic(workload: str):
     return t.get("bytes_per_launch")
 
 
+def host_cpu() -> str:
+    """The host's CPU model and the logical CPUs this process may use."""
+    model = "unknown CPU"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        ncpu = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        ncpu = os.cpu_count() or 0
+    return "%s, %d logical CPUs available to the process (the oracle uses one)" % (model, ncpu)
+
+
 def cpu_baseline(families, n_sample: int, dtype="int32"):
     """The oracle (single-threaded) on n_sample keys of each family."""
     import oracle
@@ -83,7 +101,8 @@ def cpu_baseline(families, n_sample: int, dtype="int32"):
         tot_keys += n_sample
     return {"value": tot_keys / tot_s, "unit": "keys/s", "cores": 1, "kind": "oracle",
             "sample": "%d families x %d %s keys, one single-threaded oracle sort each "
-                      "(%.1f s of CPU work)" % (len(families), n_sample, dtype, tot_s)}
+                      "(%.1f s of CPU work)" % (len(families), n_sample, dtype, tot_s),
+            "host": host_cpu()}
 
 
 def cpu_baseline_samples(samples, note):
@@ -101,7 +120,8 @@ def cpu_baseline_samples(samples, note):
         tot_s += time.perf_counter() - t0
         tot_keys += k.size
     return {"value": tot_keys / tot_s, "unit": "keys/s", "cores": 1, "kind": "oracle",
-            "sample": "%s, one single-threaded oracle sort each (%.1f s of CPU work)" % (note, tot_s)}
+            "sample": "%s, one single-threaded oracle sort each (%.1f s of CPU work)" % (note, tot_s),
+            "host": host_cpu()}
 
 
 def to_dev(a):
@@ -318,7 +338,7 @@ def workload_paper(args):
             "value": len(arrays) * n / tot_s, "unit": "keys/s", "cores": 1, "kind": "oracle",
             "sample": "the same %d inputs of %d keys, one single-threaded oracle sort each with "
                       "its counters (%.1f s of CPU work)" % (len(arrays), n, tot_s),
-            "counts": counts}
+            "counts": counts, "host": host_cpu()}
     return out
 
 

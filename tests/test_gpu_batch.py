@@ -11,7 +11,7 @@ import numpy as np
 import pytest
 
 import tsqs_inputs as ti
-from gpu_util import CODES, from_dev, same_bits
+from gpu_util import device_ok, CODES, from_dev, same_bits
 
 pytestmark = pytest.mark.gpu
 
@@ -58,46 +58,6 @@ def test_device_batch_matches_host():
     assert same_bits(from_dev(t, np.int32), keys)
 
 
-def _array_sums(t, offs):
-    """Per-array (sum of x, sum of x*x + 0x9E3779B97F4A7C15*x) modulo 2^64, on the
-    device, in slices (int64 arithmetic wraps)."""
-    import torch
-    n = int(offs[-1])
-    o = torch.from_numpy(offs.astype(np.int64)).to(t.device)
-    c1 = torch.zeros(offs.size, dtype=torch.int64, device=t.device)
-    c2 = torch.zeros_like(c1)
-    step = 1 << 27
-    carry1 = torch.zeros((), dtype=torch.int64, device=t.device)
-    carry2 = torch.zeros_like(carry1)
-    golden = -7046029254386353131  # 0x9E3779B97F4A7C15 as int64
-    for a in range(0, n, step):
-        b = min(n, a + step)
-        x = t[a:b].to(torch.int64)
-        s1 = torch.cumsum(x, 0) + carry1
-        s2 = torch.cumsum(x * x + x * golden, 0) + carry2
-        # prefix sums at the offsets that fall in (a, b]
-        sel = (o > a) & (o <= b)
-        idx = o[sel] - a - 1
-        c1[sel] = s1[idx]
-        c2[sel] = s2[idx]
-        carry1, carry2 = s1[-1], s2[-1]
-        del x, s1, s2
-    return (c1[1:] - c1[:-1]).cpu().numpy(), (c2[1:] - c2[:-1]).cpu().numpy()
-
-
-def _sorted_each(t, offs):
-    import torch
-    n = int(offs[-1])
-    starts = torch.from_numpy(offs[1:-1].astype(np.int64)).to(t.device)
-    step = 1 << 28
-    for a in range(0, n - 1, step):
-        b = min(n - 1, a + step)
-        desc = torch.nonzero(t[a:b] > t[a + 1:b + 1]).flatten() + (a + 1)
-        if desc.numel() and not bool(torch.isin(desc, starts).all()):
-            return False
-    return True
-
-
 def test_batch_100000_arrays_full_size(oracle_mod):
     """The batched workload at full size in the benchmark's launch configuration:
     100,000 int32 arrays, log-uniform sizes in [16, 2^20], one tsqs_sort_batch."""
@@ -106,12 +66,27 @@ def test_batch_100000_arrays_full_size(oracle_mod):
     sizes, offs, fams, seeds = ti.batch_plan(BATCH_SEED, 100000, 4, 20)
     print("case: batch 100000 arrays, %d keys" % int(offs[-1]), flush=True)
     t, doffs, _ = ti.device_batch(BATCH_SEED, 100000, 4, 20)
-    before = _array_sums(t, offs)
+    t0 = t.clone()
     tsqs.sort_batch(t, offs)
     torch.cuda.synchronize()
-    assert _sorted_each(t, offs)
-    after = _array_sums(t, offs)
-    assert np.array_equal(before[0], after[0]) and np.array_equal(before[1], after[1])
+    device_ok()
+    # every array element by element against an independent sort: torch.sort of
+    # (array index << 32 | key code) over groups of arrays of up to 2^28 keys
+    nseg = offs.size - 1
+    j0 = 0
+    while j0 < nseg:
+        j1 = j0 + 1
+        while j1 < nseg and int(offs[j1 + 1] - offs[j0]) <= (1 << 28):
+            j1 += 1
+        a, b = int(offs[j0]), int(offs[j1])
+        lens = torch.from_numpy((offs[j0 + 1:j1 + 1] - offs[j0:j1]).astype(np.int64)).to(t.device)
+        ids = torch.repeat_interleave(torch.arange(j1 - j0, dtype=torch.int64, device=t.device), lens)
+        comp = (ids << 32) | (t0[a:b].to(torch.int64) + (1 << 31))
+        exp = (torch.sort(comp).values & 0xFFFFFFFF) - (1 << 31)
+        assert bool(torch.equal(t[a:b].to(torch.int64), exp)), (j0, j1)
+        del lens, ids, comp, exp
+        j0 = j1
+    del t0
     # sampled arrays against the oracle: the largest, the smallest, and a spread
     pick = set(np.linspace(0, len(sizes) - 1, 24).astype(int).tolist())
     pick |= {int(np.argmax(sizes)), int(np.argmin(sizes))}
