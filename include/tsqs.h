@@ -84,10 +84,10 @@ enum {
   TSQS_OPT_FINISH_GRID = 8,  /* workgroups of the finish kernel (0 = auto: 8 per CU) */
   TSQS_OPT_FINISH_ALGO = 9,  /* small parts: 0 = bitonic sorting network, 1 = per-thread
                                 sorting network + merge-path merging in LDS, one output
-                                at a time, 2 = the same with each thread's outputs
-                                merged by a register network, 3 = runs of up to one
-                                wave merged by cross-lane bitonic stages in registers
-                                first, then as 1 (default) */
+                                at a time, 3 = runs of up to one wave merged by
+                                cross-lane bitonic stages in registers first, then as 1
+                                (default), 2 = as 3 with each thread's outputs of a
+                                merge in LDS merged by a register network */
   TSQS_OPT_PRESORT = 10,     /* 1 (default) = before the first pass of an array that
                                 needs one (tsqs_sort, tsqs_sort_pairs, each array of
                                 tsqs_sort_batch), check whether it is already

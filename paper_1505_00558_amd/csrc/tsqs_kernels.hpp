@@ -1947,6 +1947,43 @@ __device__ inline void cross_stage(typename R::T (&v)[E], bool take_min, int add
   }
 }
 
+// Write a sorted small part from LDS to K (and V).  The LDS reads are
+// unconditional, eight at a time ahead of their stores, so they are in flight
+// together rather than one read and wait per store: slots [len, NT*E) lie in
+// the part's LDS area (NT*E is the part's padded power-of-two size) and are
+// read but never stored; a payload is gathered only for a slot below len.
+template <int DT, bool HASV, int NT, int E>
+__device__ __attribute__((always_inline)) inline void write_part(
+    const Ctx &c, const typename Rec<typename Codec<DT>::B, HASV>::T *lds, const uint32_t *srcV,
+    typename Codec<DT>::B *K, uint64_t off, uint32_t len, uint32_t t) {
+  using R = Rec<typename Codec<DT>::B, HASV>;
+  constexpr int WB = E < 8 ? E : 8;
+  uint32_t pv[HASV ? E : 1];
+  if constexpr (HASV) {
+#pragma unroll
+    for (int i = 0; i < E; i++) {
+      const uint32_t x = (uint32_t)i * NT + t;
+      const uint32_t li = x < len ? R::idx(lds[lds_pad(x)]) : 0u;
+      pv[i] = srcV[off + li];
+    }
+    group_sync<NT>();   // every payload is read before any is overwritten (in-place parts)
+  }
+#pragma unroll
+  for (int i0 = 0; i0 < E; i0 += WB) {
+    typename R::T o[WB];
+#pragma unroll
+    for (int g = 0; g < WB; g++) o[g] = lds[lds_pad((uint32_t)(i0 + g) * NT + t)];
+#pragma unroll
+    for (int g = 0; g < WB; g++) {
+      const uint32_t x = (uint32_t)(i0 + g) * NT + t;
+      if (x < len) {
+        K[off + x] = Codec<DT>::dec(R::code(o[g]));
+        if constexpr (HASV) c.V[off + x] = pv[i0 + g];
+      }
+    }
+  }
+}
+
 // Sort one small part of len <= NT*E keys with NT threads (one wave or the whole
 // workgroup), E consecutive elements per thread, and write it to K (and V).
 template <int DT, bool HASV, int NT, int E>
@@ -2024,33 +2061,19 @@ __device__ void sort_group(const Ctx &c, const FinItem &it,
 #pragma unroll
   for (int i = 0; i < E; i++) lds[lds_pad(t * E + i)] = v[i];
   group_sync<NT>();
-  if constexpr (HASV) {
-    uint32_t pv[E];
-#pragma unroll
-    for (int i = 0; i < E; i++) {
-      const uint32_t x = (uint32_t)i * NT + t;
-      const uint32_t li = x < len ? R::idx(lds[lds_pad(x)]) : 0u;
-      pv[i] = srcV[off + li];
-    }
-    group_sync<NT>();   // every payload is read before any is overwritten (in-place parts)
-#pragma unroll
-    for (int i = 0; i < E; i++) {
-      const uint32_t x = (uint32_t)i * NT + t;
-      if (x < len) {
-        K[off + x] = Codec<DT>::dec(R::code(lds[lds_pad(x)]));
-        c.V[off + x] = pv[i];
-      }
-    }
-  } else {
-#pragma unroll
-    for (int i = 0; i < E; i++) {
-      const uint32_t x = (uint32_t)i * NT + t;
-      if (x < len) K[off + x] = Codec<DT>::dec(R::code(lds[lds_pad(x)]));
-    }
-  }
+  write_part<DT, HASV, NT, E>(c, lds, srcV, K, off, len, t);
   if (c.req_left) __threadfence();
   group_sync<NT>();
   if (c.req_left && t == 0) req_final(c, it.kind >> 2, len);
+}
+
+// Length of the sorted runs the register phase of the merging sort leaves
+// (cross-lane merging stops at a wave's records or at the padded part).
+template <int NT, int E>
+__device__ inline uint32_t hyb_run(uint32_t Lp) {
+  uint32_t k = E;
+  while (k < Lp && k < (uint32_t)kWave * E && k < (uint32_t)NT * E) k <<= 1;
+  return k;
 }
 
 // Sort one small part of len <= NT*E keys with NT threads by merging: every
@@ -2104,38 +2127,40 @@ __device__ __attribute__((always_inline)) void merge_group(const Ctx &c, const F
   if constexpr (HYB) {
     // runs of up to a wave's records are merged in registers by bitonic
     // cross-lane stages (lane exchanges, no LDS), the last round ascending
-    // everywhere; records past Lp are padding
-#pragma unroll
-    for (int i = 0; i < E; i++) v[i] = act ? lds[lds_pad(t * E + i)] : R::pad();
-    sort_regs_asc<R, E>(v);
-    uint32_t kmax = E;
-    while (kmax < Lp && kmax < (uint32_t)kWave * E && kmax < (uint32_t)NT * E) kmax <<= 1;
-    if (kmax > (uint32_t)E) reverse_if<R, E>(v, (t & 1u) != 0);
-    // round m merges runs of E << (m - 1) into runs of E << m: partners at
-    // 2^(m-1), ..., 2, 1 lanes
-    static_for<1, 7>([&](auto M) __attribute__((always_inline)) {
-      constexpr int m = decltype(M)::value;
-      const uint32_t k = (uint32_t)E << m;
-      if (k <= kmax) {
-        const bool asc = k == kmax || ((t * E) & k) == 0;
-        // stage by stage: scheduling across stages only raises register pressure
-        if constexpr (m >= 6) cross_stage<R, E, 32>(v, ((t & 32u) == 0) == asc, 0);
-        __builtin_amdgcn_sched_barrier(0);
-        if constexpr (m >= 5) cross_stage<R, E, 16>(v, ((t & 16u) == 0) == asc, 0);
-        __builtin_amdgcn_sched_barrier(0);
-        if constexpr (m >= 4) cross_stage<R, E, 8>(v, ((t & 8u) == 0) == asc, 0);
-        __builtin_amdgcn_sched_barrier(0);
-        if constexpr (m >= 3) cross_stage<R, E, 4>(v, ((t & 4u) == 0) == asc, 0);
-        __builtin_amdgcn_sched_barrier(0);
-        if constexpr (m >= 2) cross_stage<R, E, 2>(v, ((t & 2u) == 0) == asc, 0);
-        __builtin_amdgcn_sched_barrier(0);
-        cross_stage<R, E, 1>(v, ((t & 1u) == 0) == asc, 0);
-        __builtin_amdgcn_sched_barrier(0);
-        merge_regs_dir<R, E>(v, asc);
-        __builtin_amdgcn_sched_barrier(0);
-      }
-    });
+    // everywhere; records past Lp are padding.  A wave whose records all lie
+    // past Lp has nothing to sort (the merges below read only [0, Lp)).
+    const uint32_t kmax = hyb_run<NT, E>(Lp);
     r0 = kmax;
+    if (NT == kWave || (t & ~(uint32_t)(kWave - 1)) * (uint32_t)E < Lp) {
+#pragma unroll
+      for (int i = 0; i < E; i++) v[i] = act ? lds[lds_pad(t * E + i)] : R::pad();
+      sort_regs_asc<R, E>(v);
+      if (kmax > (uint32_t)E) reverse_if<R, E>(v, (t & 1u) != 0);
+      // round m merges runs of E << (m - 1) into runs of E << m: partners at
+      // 2^(m-1), ..., 2, 1 lanes
+      static_for<1, 7>([&](auto M) __attribute__((always_inline)) {
+        constexpr int m = decltype(M)::value;
+        const uint32_t k = (uint32_t)E << m;
+        if (k <= kmax) {
+          const bool asc = k == kmax || ((t * E) & k) == 0;
+          // stage by stage: scheduling across stages only raises register pressure
+          if constexpr (m >= 6) cross_stage<R, E, 32>(v, ((t & 32u) == 0) == asc, 0);
+          __builtin_amdgcn_sched_barrier(0);
+          if constexpr (m >= 5) cross_stage<R, E, 16>(v, ((t & 16u) == 0) == asc, 0);
+          __builtin_amdgcn_sched_barrier(0);
+          if constexpr (m >= 4) cross_stage<R, E, 8>(v, ((t & 8u) == 0) == asc, 0);
+          __builtin_amdgcn_sched_barrier(0);
+          if constexpr (m >= 3) cross_stage<R, E, 4>(v, ((t & 4u) == 0) == asc, 0);
+          __builtin_amdgcn_sched_barrier(0);
+          if constexpr (m >= 2) cross_stage<R, E, 2>(v, ((t & 2u) == 0) == asc, 0);
+          __builtin_amdgcn_sched_barrier(0);
+          cross_stage<R, E, 1>(v, ((t & 1u) == 0) == asc, 0);
+          __builtin_amdgcn_sched_barrier(0);
+          merge_regs_dir<R, E>(v, asc);
+          __builtin_amdgcn_sched_barrier(0);
+        }
+      });
+    }
   } else if (act) {
 #pragma unroll
     for (int i = 0; i < E; i++) v[i] = lds[lds_pad(t * E + i)];
@@ -2199,30 +2224,7 @@ __device__ __attribute__((always_inline)) void merge_group(const Ctx &c, const F
     }
   }
   group_sync<NT>();
-  if constexpr (HASV) {
-    uint32_t pv[E];
-#pragma unroll
-    for (int i = 0; i < E; i++) {
-      const uint32_t x = (uint32_t)i * NT + t;
-      const uint32_t li = x < len ? R::idx(lds[lds_pad(x)]) : 0u;
-      pv[i] = srcV[off + li];
-    }
-    group_sync<NT>();   // every payload is read before any is overwritten (in-place parts)
-#pragma unroll
-    for (int i = 0; i < E; i++) {
-      const uint32_t x = (uint32_t)i * NT + t;
-      if (x < len) {
-        K[off + x] = Codec<DT>::dec(R::code(lds[lds_pad(x)]));
-        c.V[off + x] = pv[i];
-      }
-    }
-  } else {
-#pragma unroll
-    for (int i = 0; i < E; i++) {
-      const uint32_t x = (uint32_t)i * NT + t;
-      if (x < len) K[off + x] = Codec<DT>::dec(R::code(lds[lds_pad(x)]));
-    }
-  }
+  write_part<DT, HASV, NT, E>(c, lds, srcV, K, off, len, t);
   if (c.req_left) __threadfence();
   group_sync<NT>();
   if (c.req_left && t == 0) req_final(c, it.kind >> 2, len);
@@ -2243,15 +2245,15 @@ __device__ inline void fill_band(const Ctx &c, const FinItem &it, uint32_t t, ui
 // (workgroup each), then wave-sized small parts and short bands (wave each).
 // Child slots are [0, 4 * parts of level d), band slots [0, 3 * parts); at the
 // roots' level also the root slots.
-// ALGO: 0 bitonic network, 1 merging with ordered outputs, 2 merging with
-// register merge networks, 3 as 1 after cross-lane bitonic merging of runs of
-// up to 16 threads (merge_group).
+// ALGO: 0 bitonic network, 1 merging with ordered outputs, 2 as 3 with
+// register merge networks for the merges in LDS, 3 merging with ordered outputs
+// after cross-lane bitonic merging of runs of up to a wave (merge_group).
 // One small part sorted by a workgroup of NTW threads (the algorithm's
 // records per thread chosen by the part's padded size).
 template <int DT, bool HASV, int ALGO, int NTW>
 __device__ __attribute__((always_inline)) inline void finish_group(
     const Ctx &c, const FinItem &it, typename Rec<typename Codec<DT>::B, HASV>::T *lds, uint32_t tid) {
-  constexpr bool BITONIC = ALGO == 0, REG = ALGO == 2, HYB = ALGO == 3;
+  constexpr bool BITONIC = ALGO == 0, REG = ALGO == 2, HYB = ALGO >= 2;
   using T = typename Rec<typename Codec<DT>::B, HASV>::T;
   const uint32_t P = next_pow2(it.len);
   constexpr int ME = max_e<T>();
@@ -2276,7 +2278,7 @@ __device__ __attribute__((always_inline)) inline void finish_group(
 template <int DT, bool HASV, int ALGO>
 __device__ __attribute__((always_inline)) inline void finish_wave(
     const Ctx &c, const FinItem &it, typename Rec<typename Codec<DT>::B, HASV>::T *wl, uint32_t lane) {
-  constexpr bool BITONIC = ALGO == 0, REG = ALGO == 2, HYB = ALGO == 3;
+  constexpr bool BITONIC = ALGO == 0, REG = ALGO == 2, HYB = ALGO >= 2;
   using T = typename Rec<typename Codec<DT>::B, HASV>::T;
   const uint32_t P = next_pow2(it.len);
   constexpr int ME = max_e<T>();

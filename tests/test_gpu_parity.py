@@ -251,9 +251,10 @@ def test_full_size_int32_properties():
 @pytest.mark.parametrize("dtype", list(ti.DTYPES))
 def test_finish_variants(oracle_mod, dtype, algo):
     """The alternative small-part sorts (TSQS_OPT_FINISH_ALGO 0: the bitonic
-    network; 1: merge-path merging one output at a time; 2: merge-path merging
-    with register merge networks): keys and payloads as for the default
-    (cross-lane bitonic merging within a wave, then merge-path merging)."""
+    network; 1: merge-path merging one output at a time; 2: cross-lane bitonic
+    merging within a wave, then merge-path merging with register merge
+    networks): keys and payloads as for the default (cross-lane bitonic merging
+    within a wave, then merge-path merging one output at a time)."""
     import paper_1505_00558_amd as tsqs
     before = tsqs.get_option(tsqs.OPT_FINISH_ALGO)
     tsqs.set_option(tsqs.OPT_FINISH_ALGO, algo)
@@ -321,3 +322,24 @@ def test_batch_empty_and_one_key_arrays(oracle_mod, dtype):
                 assert np.all((gv[lo:hi] >= lo) & (gv[lo:hi] < hi)), j
         if with_vals:
             assert payload_valid(keys, got, gv)
+
+
+@pytest.mark.parametrize("algo", [2, 3])
+@pytest.mark.parametrize("dtype", list(ti.DTYPES))
+def test_small_part_sizes(oracle_mod, dtype, algo):
+    """Arrays the small-part sort takes whole, sized so that the last waves of
+    the workgroup hold only padding (they skip the register phase) or a few
+    keys and padding, for every key type, keys alone and with payloads."""
+    import paper_1505_00558_amd as tsqs
+    before = tsqs.get_option(tsqs.OPT_FINISH_ALGO)
+    tsqs.set_option(tsqs.OPT_FINISH_ALGO, algo)
+    try:
+        for n in (1025, 2049, 2100, 3000, 4095, 4097, 5000, 6145, 8191, 8192):
+            print("case: small part", dtype, algo, n, flush=True)
+            k = ti.family("uniform", n, dtype, seed=n)
+            assert same_bits(gpu_sort(k), oracle_mod.sort(k)), n
+            v = np.arange(n, dtype=np.uint32)
+            gk, gv = gpu_sort_pairs(k, v)
+            assert same_bits(gk, oracle_mod.sort(k)) and payload_valid(k, gk, gv), n
+    finally:
+        tsqs.set_option(tsqs.OPT_FINISH_ALGO, before)
