@@ -461,20 +461,36 @@ def run_batch_case(args, keys0, offs, label):
     work = torch.empty_like(keys0)
     stream = torch.cuda.current_stream()
 
-    # batched: restore (untimed), then one tsqs_sort_batch
-    batch_ms = []
-    for step in range(args.warmup + args.steps):
-        work.copy_(keys0)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        tsqs.sort_batch(work, offs)
-        torch.cuda.synchronize()
-        if step >= args.warmup:
-            batch_ms.append((time.perf_counter() - t0) * 1e3)
-    levels = tsqs.get_stats()["levels"]
-    ok_batch = device_sorted_check(work, offs)
+    def batched(schedule):
+        # restore (untimed), then one tsqs_sort_batch under the given schedule
+        tsqs.set_option(tsqs.OPT_SCHEDULE, schedule)
+        try:
+            ms = []
+            for step in range(args.warmup + args.steps):
+                work.copy_(keys0)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                tsqs.sort_batch(work, offs)
+                torch.cuda.synchronize()
+                if step >= args.warmup:
+                    ms.append((time.perf_counter() - t0) * 1e3)
+            st = tsqs.get_stats()
+        finally:
+            tsqs.set_option(tsqs.OPT_SCHEDULE, tsqs.SCHEDULE_LEVELS)
+        bm = float(np.median(ms))
+        return {"ms_median": bm, "ms_all": [round(x, 3) for x in ms],
+                "keys_per_s": total / (bm / 1e3), "levels": st["levels"],
+                "schedule": "levels" if schedule == tsqs.SCHEDULE_LEVELS else "persistent",
+                # every array of a batched call completes when the call returns
+                "latency_ms_p50": bm, "latency_ms_p99": bm, "sorted": device_sorted_check(work, offs)}
 
-    # plain: one tsqs_sort per array, serially on one stream, from one host thread
+    batch = batched(tsqs.SCHEDULE_LEVELS)
+    batch_p = batched(tsqs.SCHEDULE_PERSISTENT)
+
+    # plain: one tsqs_sort per array on one stream from one host thread; each call
+    # only enqueues, so the device runs the arrays back to back while the host
+    # enqueues the next ones.  Completion times from timing events recorded after
+    # every 16th array (an array's latency is that of its group of 16).
     work.copy_(keys0)
     torch.cuda.synchronize()
     base = work.data_ptr()
@@ -482,30 +498,35 @@ def run_batch_case(args, keys0, offs, label):
     dt = tsqs._dtype_code(work)
     sh = ctypes.c_void_p(stream.cuda_stream)
     o = offs.astype(np.int64)
-    done_ms = np.empty(nseg)
+    group = 16
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range((nseg + group - 1) // group + 1)]
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
+    evs[0].record(stream)
     for j in range(nseg):
         rc = lib.tsqs_sort(ctypes.c_void_p(base + int(o[j]) * esz), int(o[j + 1] - o[j]), dt, sh)
         if rc != 0:
             raise RuntimeError("tsqs_sort failed: %d" % rc)
-        done_ms[j] = (time.perf_counter() - t0) * 1e3
+        if (j + 1) % group == 0 or j + 1 == nseg:
+            evs[(j + group) // group].record(stream)
     torch.cuda.synchronize()
     plain_ms = (time.perf_counter() - t0) * 1e3
+    grp_ms = np.array([evs[0].elapsed_time(e) for e in evs[1:]])
+    done_ms = np.repeat(grp_ms, group)[:nseg]
     ok_plain = device_sorted_check(work, offs)
 
-    bm = float(np.median(batch_ms))
     return {
         "case": label,
         "arrays": nseg,
         "total_keys": total,
-        "batch": {"ms_median": bm, "ms_all": [round(x, 3) for x in batch_ms],
-                  "keys_per_s": total / (bm / 1e3), "levels": levels,
-                  # every array of a batched call completes when the call returns
-                  "latency_ms_p50": bm, "latency_ms_p99": bm, "sorted": ok_batch},
+        "batch": batch,
+        "batch_persistent": batch_p,
         "plain": {"ms": plain_ms, "keys_per_s": total / (plain_ms / 1e3),
+                  "device_ms": float(grp_ms[-1]),
                   "latency_ms_p50": pct(done_ms, 50), "latency_ms_p99": pct(done_ms, 99),
-                  "sorted": ok_plain},
-        "speedup": plain_ms / bm,
+                  "sorted": ok_plain, "calls": "non-blocking (enqueue only)"},
+        "speedup": plain_ms / batch["ms_median"],
+        "speedup_persistent": plain_ms / batch_p["ms_median"],
     }
 
 
@@ -593,9 +614,15 @@ def poisson_arrivals(seed: int, count: int, rate: float) -> np.ndarray:
     return np.cumsum(-np.log(u) / rate)
 
 
-def plain_server(items, order, arrivals, work):
-    """One request at a time, in arrival order: copy the keys in, tsqs_sort.
-    Returns per-request latency (s) and the busy time."""
+def plain_server(items, order, arrivals, dst):
+    """The plain path at its best schedule: each request is enqueued when it
+    arrives (copy of its keys into a destination area of its own, then
+    tsqs_sort, which only enqueues, then an event), with no host wait between
+    requests, so the device runs them back to back; a request's latency ends
+    when the host sees its event complete.  ``dst[j]`` is template j's
+    destination pointer.  Returns per-request latency (s) and the time from the
+    first arrival to the last completion."""
+    import collections
     import ctypes
     import torch
     import paper_1505_00558_amd as tsqs
@@ -603,26 +630,53 @@ def plain_server(items, order, arrivals, work):
     hip = ctypes.CDLL("libamdhip64.so")
     hip.hipMemcpyAsync.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t,
                                    ctypes.c_int, ctypes.c_void_p]
+    hip.hipEventRecord.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
+    hip.hipEventQuery.argtypes = [ctypes.c_void_p]
+    hip.hipEventCreateWithFlags.argtypes = [ctypes.POINTER(ctypes.c_void_p), ctypes.c_uint]
+    hip.hipEventDestroy.argtypes = [ctypes.c_void_p]
     sh = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
-    dst = work.data_ptr()
-    lat = np.empty(len(order))
-    busy = 0.0
+    n_req = len(order)
+    ring = min(n_req, 8192)
+    evs = []
+    for _ in range(ring):
+        e = ctypes.c_void_p()
+        if hip.hipEventCreateWithFlags(ctypes.byref(e), 2) != 0:     # hipEventDisableTiming
+            raise RuntimeError("hipEventCreateWithFlags failed")
+        evs.append(e)
+    lat = np.empty(n_req)
+    pending = collections.deque()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for i, j in enumerate(order):
-        ptr, n, dt, esz = items[j]
-        while time.perf_counter() - t0 < arrivals[i]:
-            pass
-        s0 = time.perf_counter()
-        if hip.hipMemcpyAsync(ctypes.c_void_p(dst), ctypes.c_void_p(ptr), n * esz, 3, sh) != 0:
-            raise RuntimeError("hipMemcpyAsync failed")
-        rc = lib.tsqs_sort(ctypes.c_void_p(dst), n, dt, sh)
-        if rc != 0:
-            raise RuntimeError("tsqs_sort failed: %d" % rc)
-        s1 = time.perf_counter()
-        busy += s1 - s0
-        lat[i] = (s1 - t0) - arrivals[i]
-    return lat, busy
+    i = done = 0
+    while done < n_req:
+        now = time.perf_counter() - t0
+        while i < n_req and arrivals[i] <= now and len(pending) < ring:
+            j = order[i]
+            ptr, n, dt, esz = items[j]
+            if hip.hipMemcpyAsync(ctypes.c_void_p(dst[j]), ctypes.c_void_p(ptr), n * esz, 3, sh) != 0:
+                raise RuntimeError("hipMemcpyAsync failed")
+            rc = lib.tsqs_sort(ctypes.c_void_p(dst[j]), n, dt, sh)
+            if rc != 0:
+                raise RuntimeError("tsqs_sort failed: %d" % rc)
+            if hip.hipEventRecord(evs[i % ring], sh) != 0:
+                raise RuntimeError("hipEventRecord failed")
+            pending.append(i)
+            i += 1
+        while pending:
+            k = pending[0]
+            rc = hip.hipEventQuery(evs[k % ring])
+            if rc == 600:            # hipErrorNotReady
+                break
+            if rc != 0:
+                raise RuntimeError("hipEventQuery failed: %d" % rc)
+            lat[k] = (time.perf_counter() - t0) - arrivals[k]
+            pending.popleft()
+            done += 1
+    span = (time.perf_counter() - t0) - arrivals[0]
+    torch.cuda.synchronize()
+    for e in evs:
+        hip.hipEventDestroy(e)
+    return lat, span
 
 
 def queue_server(q, items, order, arrivals):
@@ -637,10 +691,13 @@ def queue_server(q, items, order, arrivals):
     reap_buf = (ctypes.c_uint64 * 8192)()
     cnt = ctypes.c_size_t()
     tk = ctypes.c_uint64()
-    t0 = time.perf_counter()
+    host = {"submit_s": 0.0, "step_s": 0.0, "reap_s": 0.0, "loops": 0}
+    pc = time.perf_counter
+    t0 = pc()
     i = done = 0
     while done < n_req:
-        now = time.perf_counter() - t0
+        a = pc()
+        now = a - t0
         while i < n_req and arrivals[i] <= now:
             ptr, n, dt, _ = items[order[i]]
             rc = lib.tsqs_queue_submit(qh, ctypes.c_void_p(ptr), n, dt, ctypes.byref(tk))
@@ -648,27 +705,36 @@ def queue_server(q, items, order, arrivals):
                 raise RuntimeError("tsqs_queue_submit failed: %d" % rc)
             t_of[tk.value] = i
             i += 1
+        b = pc()
         rc = lib.tsqs_queue_step(qh)
         if rc != 0:
             raise RuntimeError("tsqs_queue_step failed: %d" % rc)
+        c = pc()
         rc = lib.tsqs_queue_reap(qh, reap_buf, 8192, ctypes.byref(cnt))
         if rc != 0:
             raise RuntimeError("tsqs_queue_reap failed: %d" % rc)
         if cnt.value:
-            now = time.perf_counter() - t0
+            now = pc() - t0
             for k in range(cnt.value):
                 t = reap_buf[k]
                 r = t_of.pop(t)
                 lat[r] = now - arrivals[r]
                 lib.tsqs_queue_release(qh, ctypes.c_uint64(t))
             done += cnt.value
-    return lat
+        d = pc()
+        host["submit_s"] += b - a
+        host["step_s"] += c - b
+        host["reap_s"] += d - c
+        host["loops"] += 1
+    host["wall_s"] = pc() - t0
+    return lat, host
 
 
 def workload_serve(args):
     """Poisson arrivals of sort requests served by the continuous-batching queue,
-    against the plain serial path (one tsqs_sort per request) on the same
-    arrivals; the latency target is the plain path's p99 at 70% of its capacity."""
+    against the plain path (one tsqs_sort per request, enqueued at its arrival;
+    the device runs them back to back) on the same kind of arrivals; the latency
+    target is the plain path's p99 at 70% of its capacity."""
     import torch
     import paper_1505_00558_amd as tsqs
     import tsqs_inputs as ti
@@ -678,18 +744,22 @@ def workload_serve(args):
     n_req = n_meas + n_warm
     order = (ti.splitmix64(seed + 11, n_req) % np.uint64(len(items))).astype(np.int64)
     keys_of = np.array([items[j][1] for j in order], dtype=np.float64)
-    max_n = max(it[1] for it in items)
-    work = torch.empty(max_n * 8 // 4, dtype=torch.int32, device="cuda:0")
+    # a destination area per template (a request's result stays there until the
+    # next request of the same template overwrites it, in stream order)
+    dst_bytes = [((it[1] * it[3] + 255) // 256) * 256 for it in items]
+    work = torch.empty(sum(dst_bytes), dtype=torch.uint8, device="cuda:0")
+    dst = np.concatenate([[0], np.cumsum(dst_bytes)[:-1]]).astype(np.int64) + work.data_ptr()
+    dst = [int(x) for x in dst]
 
-    # plain capacity: back-to-back service of the request stream
+    # plain capacity: every request enqueued at once, the device runs them back to back
     log("serve: plain capacity")
-    _, busy = plain_server(items, order[:n_warm], np.zeros(n_warm), work)
-    _, busy = plain_server(items, order[:n_req], np.zeros(n_req), work)
+    plain_server(items, order[:n_warm], np.zeros(n_warm), dst)
+    _, busy = plain_server(items, order[:n_req], np.zeros(n_req), dst)
     mu_p = n_req / busy
     lam_slo = 0.7 * mu_p
     log("serve: plain at %.0f req/s" % lam_slo)
     arr = poisson_arrivals(seed + 21, n_req, lam_slo)
-    lat_p, _ = plain_server(items, order, arr, work)
+    lat_p, _ = plain_server(items, order, arr, dst)
     m = slice(n_warm, n_req)
     slo = pct(lat_p[m], 99)
     span_p = (arr[n_req - 1] + lat_p[n_req - 1]) - arr[n_warm]
@@ -702,12 +772,13 @@ def workload_serve(args):
         lam = f * mu_p
         log("serve: queue at %.0f req/s (%.1fx plain capacity)" % (lam, f))
         arr = poisson_arrivals(seed + 31, n_req, lam)
-        lat = queue_server(q, items, order, arr)
+        lat, host = queue_server(q, items, order, arr)
         end = np.nanmax(arr[m] + lat[m])
         span = end - arr[n_warm]
         sweep.append({"rate_x_plain_capacity": f, "rate_req_s": lam,
                       "p50_ms": pct(lat[m], 50) * 1e3, "p99_ms": pct(lat[m], 99) * 1e3,
-                      "keys_per_s": keys_of[m].sum() / span, "meets_slo": pct(lat[m], 99) <= slo})
+                      "keys_per_s": keys_of[m].sum() / span, "meets_slo": pct(lat[m], 99) <= slo,
+                      "host": {k: (round(v, 4) if isinstance(v, float) else v) for k, v in host.items()}})
     q.close()
     ok = [r for r in sweep if r["meets_slo"]]
     best = max(ok, key=lambda r: r["keys_per_s"]) if ok else None
