@@ -766,6 +766,9 @@ def workload_serve(args):
     plain = {"rate_req_s": lam_slo, "p50_ms": pct(lat_p[m], 50) * 1e3, "p99_ms": slo * 1e3,
              "keys_per_s": keys_of[m].sum() / span_p, "capacity_req_s": mu_p}
 
+    if args.serve_direct is not None:
+        tsqs.set_option(tsqs.OPT_QUEUE_DIRECT, args.serve_direct)
+    direct_min = tsqs.get_option(tsqs.OPT_QUEUE_DIRECT)
     q = tsqs.Queue(args.serve_budget_gb << 30)
     sweep = []
     for f in args.serve_rates:
@@ -799,7 +802,8 @@ def workload_serve(args):
                                "key type uniform over int32/float32/int64, family uniform over "
                                "the seven; %d measured requests after %d warm-up; queue budget "
                                "%d GB" % (n_meas, n_warm, args.serve_budget_gb),
-                   "templates": len(items)},
+                   "templates": len(items),
+                   "queue_direct_min_keys": direct_min},
         "slo_p99_ms": slo * 1e3,
         "plain": plain,
         "served": sweep,
@@ -831,7 +835,9 @@ def main():
     ap.add_argument("--serve-templates", type=int, default=256)
     ap.add_argument("--serve-budget-gb", type=int, default=64)
     ap.add_argument("--serve-rates", type=lambda v: [float(x) for x in v.split(",")],
-                    default=[0.7, 1.0, 1.25, 1.5, 2.0, 3.0, 6.0])
+                    default=[0.7, 1.0, 1.1, 1.2, 1.3, 1.4, 1.5, 2.0, 3.0])
+    ap.add_argument("--serve-direct", type=int, default=None,
+                    help="TSQS_OPT_QUEUE_DIRECT for the queue (default: the library's)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-presort", dest="presort", action="store_false",
                     help="switch the presortedness check off (every array takes the passes)")

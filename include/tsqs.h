@@ -100,10 +100,15 @@ enum {
                                 then the persistent kernel for what is left; 1 = the
                                 persistent kernel for every part (one launch after the
                                 roots are set up) */
-  TSQS_OPT_ITER_CAP = 12     /* loop iterations (tasks and waits) of one workgroup of
+  TSQS_OPT_ITER_CAP = 12,    /* loop iterations (tasks and waits) of one workgroup of
                                 the persistent kernel before it stops every workgroup
                                 and reports an error; 0 (default) = 2^23 (a wait of
                                 some seconds; a run of the kernel takes far fewer) */
+  TSQS_OPT_QUEUE_DIRECT = 13 /* serving queues opened after this: requests of at
+                                least this many keys are sorted by the single-array
+                                schedule on a stream of the queue's own instead of
+                                the queue's ticks (tsqs_queue.h); 0 = never;
+                                default 2^22 */
 };
 
 #define TSQS_MAX_LEVELS 192

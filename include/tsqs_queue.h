@@ -12,6 +12,15 @@
  * first levels run in the same kernels as older requests' deeper levels.
  * Results stay in the arena (sorted in place there) until released.
  *
+ * Large requests.  A request of at least TSQS_OPT_QUEUE_DIRECT keys (the value
+ * when the queue was opened; default 2^22, 0 = none) does not join the ticks:
+ * its keys are copied into the arena and sorted there by the single-array
+ * schedule of tsqs_sort, on a stream of the queue's own, one such request after
+ * another.  Such a sort already runs at the single-array rate, and it does not
+ * wait a tick per recursion level.  These sorts use the library's per-device
+ * workspace, which tsqs_sort also uses: calls on other streams are ordered
+ * after them, and tsqs_get_stats keeps reporting the caller's own last call.
+ *
  * Ownership.  The queue owns its arena (keys and the scratch copy, each half of
  * the budget less the level tables), its tables and a page of host-mapped
  * completion flags.  The caller owns each request's source buffer, which must
@@ -21,9 +30,11 @@
  * type (created at the default priority), so ticks of different key types
  * overlap.  Work enqueued on the stream given to tsqs_queue_open before a
  * request is admitted completes before the queue reads that request's source.
- * tsqs_queue_step never waits for the device (a key type whose ticks in flight
- * are at their limit is skipped until one finishes); tsqs_queue_poll and
- * tsqs_queue_reap read host-mapped memory and never wait.  A queue is used from
+ * tsqs_queue_step does not wait for the device (a key type whose ticks in
+ * flight are at their limit is skipped until one finishes), except when a large
+ * request needs a larger workspace than any call before it: the workspace is
+ * regrown after the work that uses it.  tsqs_queue_poll and tsqs_queue_reap
+ * read host-mapped memory and event states and never wait.  A queue is used from
  * one host thread at a time (calls are serialised by a per-queue mutex).
  *
  * Errors are the TSQS_* codes of tsqs.h; TSQS_EAGAIN (below) means "not yet".

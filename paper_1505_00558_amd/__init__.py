@@ -23,7 +23,7 @@ NOALLOC_MAX_KEYS = 1 << 20
 NOALLOC_SCRATCH_BYTES = 32 << 20
 OPT_SMALL_MAX, OPT_SAMPLES, OPT_DEPTH_FACTOR, OPT_PIVOT_MODE = 1, 2, 3, 4
 OPT_SEED, OPT_TIMING, OPT_PART_GRID, OPT_FINISH_GRID, OPT_FINISH_ALGO = 5, 6, 7, 8, 9
-OPT_PRESORT, OPT_SCHEDULE, OPT_ITER_CAP = 10, 11, 12
+OPT_PRESORT, OPT_SCHEDULE, OPT_ITER_CAP, OPT_QUEUE_DIRECT = 10, 11, 12, 13
 SCHEDULE_LEVELS, SCHEDULE_PERSISTENT = 0, 1
 MAX_LEVELS = 192
 

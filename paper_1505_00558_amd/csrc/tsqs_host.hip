@@ -184,8 +184,10 @@ FinGeom geom_any(int dt, size_t lds, bool hasv) {
   }
 }
 
+// record = false: the call leaves the statistics of the caller's last call in
+// place (sorts the serving queue runs for its requests).
 int dispatch(void *keys, uint32_t *vals, const uint64_t *h_offs, size_t nroots, uint64_t n,
-             uint64_t max_root, int dt, hipStream_t s) {
+             uint64_t max_root, int dt, hipStream_t s, bool record = true) {
   std::lock_guard<std::mutex> lk(g_mu);
   int dev = 0;
   HIPCHK(hipGetDevice(&dev));
@@ -194,6 +196,7 @@ int dispatch(void *keys, uint32_t *vals, const uint64_t *h_offs, size_t nroots, 
   Workspace &w = g_ws[(size_t)dev];
   int rc = ensure_static(w, dev, s);
   if (rc != TSQS_OK) return rc;
+  const LastCall saved = g_last;
   g_last.valid = false;
   if (!dtype_ok(dt)) return TSQS_EUNSUPPORTED;
   const bool hv = vals != nullptr;
@@ -217,6 +220,7 @@ int dispatch(void *keys, uint32_t *vals, const uint64_t *h_offs, size_t nroots, 
     w.done_rec = true;
     w.last_stream = s;
   }
+  if (!record) g_last = saved;
   return rc;
 }
 
@@ -392,6 +396,18 @@ void arena_give(tsqs_queue *q, uint64_t off, uint64_t bytes) {
 // Requests the device has appended to the completion ring become done (the
 // ring is read in order up to the first entry not yet written).
 void collect_done(tsqs_queue *q) {
+  while (!q->direct.empty()) {
+    const hipError_t e = hipEventQuery(q->direct.front().second);
+    if (e == hipErrorNotReady) break;
+    if (e != hipSuccess) { q->broken = true; break; }
+    const uint64_t tk = q->direct.front().first;
+    q->ev_free.push_back(q->direct.front().second);
+    q->direct.pop_front();
+    QReq &r = q->reqs[tk];
+    r.state = 2;
+    q->n_done++;
+    q->reap.push_back(tk);
+  }
   for (;;) {
     unsigned int *e = &q->h_ring[q->ring_cur % kQMaxReq];
     const unsigned int v = __atomic_load_n(e, __ATOMIC_ACQUIRE);
@@ -416,6 +432,32 @@ int admit(tsqs_queue *q) {
     if (!G.ready) {
       const int rc = group_init(q, r.dt);
       if (rc != TSQS_OK) return rc;
+    }
+    const bool direct = q->direct_min > 0 && r.n >= q->direct_min;
+    if (direct) {
+      // a large request: the single-array schedule on the queue's direct
+      // stream, in place in the arena (its own launches are already efficient;
+      // it does not wait for ticks), done when its event has completed
+      uint64_t off = 0;
+      if (!arena_take(q, r.bytes, &off)) break;
+      r.boff = off;
+      if (!q->ds_waits_src) {
+        HIPCHK(hipEventRecord(q->ev_src, q->s));
+        HIPCHK(hipStreamWaitEvent(q->ds, q->ev_src, 0));
+        q->ds_waits_src = true;
+      }
+      HIPCHK(hipMemcpyAsync(q->KA + off, r.src, r.n * G.kb, hipMemcpyDeviceToDevice, q->ds));
+      const int rc = dispatch(q->KA + off, nullptr, nullptr, 1, r.n, r.n, r.dt, q->ds, false);
+      if (rc != TSQS_OK) { q->broken = true; return rc; }
+      hipEvent_t ev = nullptr;
+      if (!q->ev_free.empty()) { ev = q->ev_free.back(); q->ev_free.pop_back(); }
+      else HIPCHK(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+      HIPCHK(hipEventRecord(ev, q->ds));
+      q->direct.emplace_back(tk, ev);
+      r.direct = true;
+      r.state = 1;
+      q->pending.pop_front();
+      continue;
     }
     if (G.next_roots.size() >= kQRootsPerTick || q->free_ids.empty()) break;
     uint64_t off = 0;
@@ -465,6 +507,11 @@ void queue_free(tsqs_queue *q) {
   (void)hipHostFree(q->h_flag);
   (void)hipHostFree(q->h_ring);
   if (q->ev_src) (void)hipEventDestroy(q->ev_src);
+  for (auto &d : q->direct) (void)hipEventDestroy(d.second);
+  for (hipEvent_t e : q->ev_free) (void)hipEventDestroy(e);
+  q->direct.clear();
+  q->ev_free.clear();
+  if (q->ds) (void)hipStreamDestroy(q->ds);
 }
 
 }  // namespace
@@ -518,6 +565,11 @@ int tsqs_queue_open(size_t budget_bytes, void *stream, tsqs_queue_t **out) {
   if (grow(&q->d_pos, &c0, (size_t)1) != TSQS_OK) return fail(TSQS_ENOMEM);
   if (hipMemset(q->d_pos, 0, sizeof(unsigned int)) != hipSuccess) return fail(TSQS_EDEVICE);
   if (hipEventCreateWithFlags(&q->ev_src, hipEventDisableTiming) != hipSuccess) return fail(TSQS_EDEVICE);
+  if (hipStreamCreateWithFlags(&q->ds, hipStreamNonBlocking) != hipSuccess) return fail(TSQS_EDEVICE);
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    q->direct_min = (uint64_t)g_opt.queue_direct;
+  }
   q->id_ticket.assign(kQMaxReq, 0);
   q->free_ranges[0] = arena;
   q->free_ids.reserve(kQMaxReq);
@@ -564,6 +616,7 @@ int tsqs_queue_step(tsqs_queue_t *q) {
   if (hipSetDevice(q->dev) != hipSuccess) return TSQS_EDEVICE;
   collect_done(q);
   for (int dt = 0; dt < 5; dt++) q->g[dt].waits_src = false;
+  q->ds_waits_src = false;
   int rc = admit(q);
   if (rc != TSQS_OK) return rc;
   for (int dt = 0; dt < 5; dt++) {
@@ -582,7 +635,7 @@ int tsqs_queue_poll(tsqs_queue_t *q, uint64_t ticket) {
   auto it = q->reqs.find(ticket);
   if (it == q->reqs.end()) return TSQS_EINVAL;
   QReq &r = it->second;
-  if (r.state == 1 && __atomic_load_n(&q->h_flag[r.id], __ATOMIC_ACQUIRE)) collect_done(q);
+  if (r.state == 1 && (r.direct || __atomic_load_n(&q->h_flag[r.id], __ATOMIC_ACQUIRE))) collect_done(q);
   return r.state;
 }
 
@@ -592,7 +645,7 @@ int tsqs_queue_result(tsqs_queue_t *q, uint64_t ticket, void **d_keys, size_t *n
   auto it = q->reqs.find(ticket);
   if (it == q->reqs.end()) return TSQS_EINVAL;
   QReq &r = it->second;
-  if (r.state == 1 && __atomic_load_n(&q->h_flag[r.id], __ATOMIC_ACQUIRE)) collect_done(q);
+  if (r.state == 1 && (r.direct || __atomic_load_n(&q->h_flag[r.id], __ATOMIC_ACQUIRE))) collect_done(q);
   if (r.state != 2) return TSQS_EAGAIN;
   *d_keys = r.n == 1 ? (void *)r.src : (void *)(q->KA + r.boff);
   if (nmemb) *nmemb = (size_t)r.n;
@@ -618,11 +671,11 @@ int tsqs_queue_release(tsqs_queue_t *q, uint64_t ticket) {
   auto it = q->reqs.find(ticket);
   if (it == q->reqs.end()) return TSQS_EINVAL;
   QReq &r = it->second;
-  if (r.state == 1 && __atomic_load_n(&q->h_flag[r.id], __ATOMIC_ACQUIRE)) collect_done(q);
+  if (r.state == 1 && (r.direct || __atomic_load_n(&q->h_flag[r.id], __ATOMIC_ACQUIRE))) collect_done(q);
   if (r.state != 2) return TSQS_EAGAIN;
   if (r.n > 1) {
     arena_give(q, r.boff, r.bytes);
-    q->free_ids.push_back(r.id);
+    if (!r.direct) q->free_ids.push_back(r.id);
   }
   q->n_done--;
   q->reqs.erase(it);
@@ -634,7 +687,7 @@ int tsqs_queue_info(tsqs_queue_t *q, uint64_t *queued, uint64_t *running, uint64
   if (!q) return TSQS_EINVAL;
   std::lock_guard<std::mutex> lk(q->mu);
   collect_done(q);
-  uint64_t run = 0;
+  uint64_t run = q->direct.size();
   for (int i = 0; i < 5; i++) run += q->g[i].live;
   if (queued) *queued = q->pending.size();
   if (running) *running = run;
@@ -651,6 +704,7 @@ int tsqs_queue_close(tsqs_queue_t *q) {
     std::lock_guard<std::mutex> lk(q->mu);
     for (int i = 0; i < 5; i++)
       if (q->g[i].s && hipStreamSynchronize(q->g[i].s) != hipSuccess) rc = TSQS_EDEVICE;
+    if (q->ds && hipStreamSynchronize(q->ds) != hipSuccess) rc = TSQS_EDEVICE;
     if (hipStreamSynchronize(q->s) != hipSuccess) rc = TSQS_EDEVICE;
     queue_free(q);
   }
@@ -942,6 +996,7 @@ int tsqs_set_option(int key, int64_t v) {
     case TSQS_OPT_PRESORT: g_opt.presort = v ? 1 : 0; return TSQS_OK;
     case TSQS_OPT_SCHEDULE: if (v < 0 || v > 1) return TSQS_EINVAL; g_opt.schedule = v; return TSQS_OK;
     case TSQS_OPT_ITER_CAP: if (v < 0) return TSQS_EINVAL; g_opt.iter_cap = v; return TSQS_OK;
+    case TSQS_OPT_QUEUE_DIRECT: if (v < 0 || v > 0xFFFFFFFFll) return TSQS_EINVAL; g_opt.queue_direct = v; return TSQS_OK;
     default: return TSQS_EUNSUPPORTED;
   }
 }
@@ -961,6 +1016,7 @@ int64_t tsqs_get_option(int key) {
     case TSQS_OPT_PRESORT: return g_opt.presort;
     case TSQS_OPT_SCHEDULE: return g_opt.schedule;
     case TSQS_OPT_ITER_CAP: return g_opt.iter_cap;
+    case TSQS_OPT_QUEUE_DIRECT: return g_opt.queue_direct;
     default: return INT64_MIN;
   }
 }

@@ -32,10 +32,6 @@ namespace host {
     if (e_ != hipSuccess) return TSQS_EDEVICE;         \
   } while (0)
 
-// Arrays of at least this many keys synchronise once after the presortedness
-// check (about 10-20 us) so that an array found in order skips the level schedule.
-constexpr uint64_t kPresortSyncMin = 1ull << 24;
-
 struct Options {
   int64_t small_max = 8192;
   int64_t samples = 63;
@@ -49,6 +45,7 @@ struct Options {
   int64_t presort = 1;
   int64_t schedule = 0;        // TSQS_OPT_SCHEDULE
   int64_t iter_cap = 0;        // TSQS_OPT_ITER_CAP (0: the default)
+  int64_t queue_direct = 1 << 22;   // TSQS_OPT_QUEUE_DIRECT
 };
 
 constexpr unsigned long long kDefaultIterCap = 1ull << 23;

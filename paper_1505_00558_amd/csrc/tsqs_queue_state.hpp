@@ -7,6 +7,11 @@
 // counter; tick t uses level index t mod kMaxLevels (the tables' parity and the
 // kernels' buffer choice only need t's parity, and kMaxLevels is even).
 //
+// Requests of at least TSQS_OPT_QUEUE_DIRECT keys (read when the queue opens)
+// skip the ticks: the single-array schedule sorts each in place in the arena on
+// the queue's direct stream, one after another, and an event per request marks
+// it done.  They hold arena space but no device request id.
+//
 // A tick of a group: clear the counters of the next level index, add the roots
 // admitted since the last tick (k_init, which also sets each request's count of
 // keys not yet final), then k_partition / k_plan / k_finish on every part of
@@ -37,8 +42,9 @@ struct QReq {
   uint64_t n = 0;
   uint64_t boff = 0;       // byte offset in both arenas
   uint64_t bytes = 0;      // reserved bytes (rounded)
-  uint32_t id = 0;         // device request id
+  uint32_t id = 0;         // device request id (requests sorted by the ticks)
   int state = 0;           // 0 queued, 1 running, 2 done
+  bool direct = false;     // sorted by the single-array schedule on the direct stream
 };
 
 struct QGroup {
@@ -94,6 +100,13 @@ struct tsqs_queue {
   uint64_t n_done = 0;
   std::deque<uint64_t> reap;                  // done, not yet reported by tsqs_queue_reap
   tsqs::host::QGroup g[5];
+  // requests of at least direct_min keys (0: none) are sorted by the
+  // single-array schedule on stream ds; in flight: (ticket, completion event)
+  uint64_t direct_min = 0;
+  hipStream_t ds = nullptr;
+  bool ds_waits_src = false;
+  std::deque<std::pair<uint64_t, hipEvent_t>> direct;
+  std::vector<hipEvent_t> ev_free;
   bool broken = false;
 };
 

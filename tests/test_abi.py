@@ -110,6 +110,12 @@ def test_options(lib):
         assert tsqs.get_option(tsqs.OPT_ITER_CAP) == 0
         assert lib.tsqs_set_option(tsqs.OPT_ITER_CAP, -1) == -1
         assert lib.tsqs_set_option(tsqs.OPT_ITER_CAP, 0) == 0
+        assert tsqs.get_option(tsqs.OPT_QUEUE_DIRECT) == 1 << 22
+        assert lib.tsqs_set_option(tsqs.OPT_QUEUE_DIRECT, -1) == -1
+        assert lib.tsqs_set_option(tsqs.OPT_QUEUE_DIRECT, 1 << 32) == -1
+        assert lib.tsqs_set_option(tsqs.OPT_QUEUE_DIRECT, 0) == 0
+        assert tsqs.get_option(tsqs.OPT_QUEUE_DIRECT) == 0
+        assert lib.tsqs_set_option(tsqs.OPT_QUEUE_DIRECT, 1 << 22) == 0
         assert lib.tsqs_set_option(999, 1) == -4
         assert tsqs.get_option(999) == -(1 << 63)
     finally:

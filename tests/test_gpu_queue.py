@@ -48,13 +48,26 @@ def _drain(q, tickets, limit_s=120.0):
         assert time.time() - t0 < limit_s, "queue did not finish in %.0f s" % limit_s
 
 
-def test_queue_mix_equals_alone_and_oracle(oracle_mod):
+@pytest.fixture
+def direct_min(request):
+    """TSQS_OPT_QUEUE_DIRECT for the queues a test opens (restored after)."""
+    import paper_1505_00558_amd as tsqs
+    before = tsqs.get_option(tsqs.OPT_QUEUE_DIRECT)
+    tsqs.set_option(tsqs.OPT_QUEUE_DIRECT, request.param)
+    yield request.param
+    tsqs.set_option(tsqs.OPT_QUEUE_DIRECT, before)
+
+
+# 0: every request through the ticks; 1 << 19: the largest of these requests by
+# the single-array schedule; 20000: most of them
+@pytest.mark.parametrize("direct_min", [0, 1 << 19, 20000], indirect=True)
+def test_queue_mix_equals_alone_and_oracle(oracle_mod, direct_min):
     import paper_1505_00558_amd as tsqs
     import torch
     reqs = _requests(0x5E12, 48, 10, 20)
     srcs = [to_dev(a) for _, _, a in reqs]
-    print("case: queue mix of %d requests, %d keys" % (len(reqs), sum(a.size for *_, a in reqs)),
-          flush=True)
+    print("case: queue mix of %d requests, %d keys, direct from %d" % (
+        len(reqs), sum(a.size for *_, a in reqs), direct_min), flush=True)
     q = tsqs.Queue(4 << 30)
     # alone: one request in the queue at a time
     alone = []
@@ -126,10 +139,12 @@ def test_queue_admission_waits_for_space(oracle_mod):
     q.close()
 
 
-def test_queue_largest_requests():
+@pytest.mark.parametrize("direct_min", [0, 1 << 22], indirect=True)
+def test_queue_largest_requests(direct_min):
     """The largest request size of the serving workload (2^24 keys) for each key
-    type, together in one queue; checked against an independent library sort
-    (torch.sort; for float32 on the totalOrder integer codes)."""
+    type, together in one queue, through the ticks and by the single-array
+    schedule; checked against an independent library sort (torch.sort; for
+    float32 on the totalOrder integer codes)."""
     import paper_1505_00558_amd as tsqs
     import torch
     n = 1 << 24
@@ -155,4 +170,32 @@ def test_queue_largest_requests():
         else:
             assert bool(torch.equal(got, torch.sort(t).values))
         q.release(tk)
+    q.close()
+
+
+@pytest.mark.parametrize("direct_min", [4096], indirect=True)
+def test_queue_direct_keeps_caller_stats(direct_min):
+    """Requests sorted by the single-array schedule inside the queue leave the
+    statistics of the caller's own last tsqs_sort in place, and a tsqs_sort on
+    the caller's stream after them sees its keys sorted."""
+    import paper_1505_00558_amd as tsqs
+    import torch
+    mine = ti.device_family("uniform", 100003, "int32", seed=77)
+    ref = torch.sort(mine).values
+    tsqs.sort(mine)
+    st = tsqs.get_stats()
+    assert st["n"] == 100003
+    q = tsqs.Queue(1 << 30)
+    srcs = [ti.device_family(f, 50000 + 17 * j, "int64", seed=j) for j, f in enumerate(ti.FAMILIES)]
+    tks = [q.submit(t) for t in srcs]
+    _drain(q, tks)
+    assert tsqs.get_stats()["n"] == 100003
+    for t, tk in zip(srcs, tks):
+        assert bool(torch.equal(q.result(tk), torch.sort(t).values))
+        q.release(tk)
+    again = ti.device_family("organ_pipe", 70001, "int32", seed=78)
+    tsqs.sort(again)
+    torch.cuda.synchronize()
+    assert bool(torch.equal(again, torch.sort(ti.device_family("organ_pipe", 70001, "int32", seed=78)).values))
+    assert bool(torch.equal(mine, ref))
     q.close()
