@@ -127,7 +127,7 @@ int run_t(const CallEnv &env, const CallArgs &a) {
   c.p.iter_cap = g_opt.iter_cap > 0 ? (unsigned long long)g_opt.iter_cap : kDefaultIterCap;
 
   const int part_grid = g_opt.part_grid > 0 ? (int)g_opt.part_grid : 4 * env.cus;
-  const int fin_grid = g_opt.finish_grid > 0 ? (int)g_opt.finish_grid : 8 * env.cus;
+  const int fin_grid = g_opt.finish_grid > 0 ? (int)g_opt.finish_grid : kFinGridPerCu * env.cus;
   const int plan_grid = 4 * env.cus;
   const size_t fin_lds = geo.fin_lds;
   if (fin_lds > 65536) {
@@ -311,7 +311,7 @@ int queue_tick(tsqs_queue *q, QGroup &G) {
     hipLaunchKernelGGL((k_partition<DT, false, false, true>), dim3(grid), dim3(kPartNT2), 0, G.s, c, d);
   }
   hipLaunchKernelGGL((k_plan<DT, false>), dim3(grid), dim3(kPlanNT), 0, G.s, c, d);
-  const int fgrid = g_opt.finish_grid > 0 ? (int)g_opt.finish_grid : 8 * q->cus;
+  const int fgrid = g_opt.finish_grid > 0 ? (int)g_opt.finish_grid : kFinGridPerCu * q->cus;
   if (g_opt.finish_algo == 0)
     hipLaunchKernelGGL((k_finish<DT, false, 0>), dim3(fgrid), dim3(kFinNT), G.geo.fin_lds, G.s, c, d);
   else if (g_opt.finish_algo == 1)

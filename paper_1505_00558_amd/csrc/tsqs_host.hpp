@@ -32,6 +32,10 @@ namespace host {
     if (e_ != hipSuccess) return TSQS_EDEVICE;         \
   } while (0)
 
+// Workgroups of the small-part finish per compute unit (default grid): many
+// more than fit at once, so that parts of unequal size balance over the CUs.
+constexpr int kFinGridPerCu = 32;
+
 struct Options {
   int64_t small_max = 8192;
   int64_t samples = 63;

@@ -2304,7 +2304,7 @@ __device__ __attribute__((always_inline)) inline void finish_wave(
 }
 
 template <int DT, bool HASV, int ALGO>
-__global__ __launch_bounds__(kFinNT) void k_finish(Ctx c, int d) {
+__global__ __launch_bounds__(kFinNT) __attribute__((amdgpu_waves_per_eu(4))) void k_finish(Ctx c, int d) {
   using B = typename Codec<DT>::B;
   using R = Rec<B, HASV>;
   using T = typename R::T;
@@ -2359,7 +2359,7 @@ __global__ __launch_bounds__(kFinNT) void k_finish(Ctx c, int d) {
 
 // The small parts the persistent kernel listed (after it has ended).
 template <int DT, bool HASV, int ALGO>
-__global__ __launch_bounds__(kFinNT) void k_finish_list(Ctx c) {
+__global__ __launch_bounds__(kFinNT) __attribute__((amdgpu_waves_per_eu(4))) void k_finish_list(Ctx c) {
   using T = typename Rec<typename Codec<DT>::B, HASV>::T;
   extern __shared__ unsigned char smem[];
   T *lds = reinterpret_cast<T *>(smem);
