@@ -681,6 +681,19 @@ struct PendLds {
 // depth limit, the exact-minimum test mode, or a root) it gets a one-level pass
 // around the sample median, or around the exact median / minimum found by radix
 // select.  Whole wave.
+// Depth a child part enters with: its parent's depth plus the recursion levels
+// between them, or the depth limit itself when the child kept more than 15/16
+// of the parent's keys.  A split that unbalanced sends the child and its whole
+// subtree to exact-median pivots at once, rather than after the up to
+// 2 ceil(log2 n) nearly full passes the depth limit alone allows.  A median of
+// up to 63 jittered samples practically never splits that badly unless the
+// input is built against the sampling.
+__device__ inline uint32_t child_depth(uint32_t pdepth, uint32_t levels, uint32_t plen, uint32_t clen,
+                                       uint32_t dmax) {
+  const uint32_t d = pdepth + levels;
+  return (d < dmax && (uint64_t)clen * 16 > (uint64_t)plen * 15) ? dmax : d;
+}
+
 template <int DT, bool HASV>
 __device__ inline void child(const Ctx &c, uint32_t slot, uint64_t off, uint32_t len, uint32_t depth,
                              uint32_t dmax, uint32_t req, bool in_s, bool own_known, uint64_t own,
@@ -1666,7 +1679,8 @@ __global__ __launch_bounds__(kPlanNT) void k_plan(Ctx c, int d) {
 #pragma unroll
         for (int k = 0; k < 4; k++) {
           const unsigned long long la = cp[kCtrLook + k];
-          child<DT, HASV>(c, 4 * si + k, coff[k], clen[k], s.depth + 2, s.dmax, s.req, out_s, true,
+          child<DT, HASV>(c, 4 * si + k, coff[k], clen[k], child_depth(s.depth, 2, s.len, clen[k], s.dmax),
+                          s.dmax, s.req, out_s, true,
                           s.piv[3 + k], (uint32_t)la, (uint32_t)(la >> 32), hist[wv], pend, wv,
                           small_parts, small_keys);
         }
@@ -1686,10 +1700,12 @@ __global__ __launch_bounds__(kPlanNT) void k_plan(Ctx c, int d) {
           put_small(c, 4 * si + 2, 0, 0, false, s.req);
         }
         const unsigned long long la = cp[kCtrLook + 0], ga = cp[kCtrLook + 1];
-        child<DT, HASV>(c, 4 * si, s.off, L, s.depth + 1, s.dmax, s.req, out_s, true, s.piv[1],
+        child<DT, HASV>(c, 4 * si, s.off, L, child_depth(s.depth, 1, s.len, L, s.dmax), s.dmax, s.req,
+                        out_s, true, s.piv[1],
                         (uint32_t)la, (uint32_t)(la >> 32), hist[wv], pend, wv, small_parts,
                         small_keys);
-        child<DT, HASV>(c, 4 * si + 3, s.off + s.len - G, G, s.depth + 1, s.dmax, s.req, out_s, true,
+        child<DT, HASV>(c, 4 * si + 3, s.off + s.len - G, G, child_depth(s.depth, 1, s.len, G, s.dmax),
+                        s.dmax, s.req, out_s, true,
                         s.piv[2], (uint32_t)ga, (uint32_t)(ga >> 32), hist[wv], pend, wv,
                         small_parts, small_keys);
       }

@@ -179,7 +179,7 @@ __device__ void persist_plan(const Ctx &c, PersistCtl &P, unsigned char *area, u
     coff[0] = s.off; coff[1] = s.off + nlt - nlg; coff[2] = s.off + g0; coff[3] = s.off + s.len - ngg;
     clen[0] = nll; clen[1] = nlg; clen[2] = ngl; clen[3] = ngg;
     nch = 4;
-    cdepth = s.depth + 2;
+    cdepth = 2;   // recursion levels from the part to its children
     for (int k = 0; k < 4; k++) {
       cown[k] = s.piv[3 + k];
       clook[k] = __hip_atomic_load(cp + kCtrLook + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -197,7 +197,7 @@ __device__ void persist_plan(const Ctx &c, PersistCtl &P, unsigned char *area, u
     clook[0] = __hip_atomic_load(cp + kCtrLook + 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     clook[1] = __hip_atomic_load(cp + kCtrLook + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     nch = 2;
-    cdepth = s.depth + 1;
+    cdepth = 1;
   }
   if (tid == 0) {
     P.final_keys = 0;
@@ -233,7 +233,8 @@ __device__ void persist_plan(const Ctx &c, PersistCtl &P, unsigned char *area, u
   uint32_t *hist = reinterpret_cast<uint32_t *>(area) + wv * 256;
   if ((int)wv < nch) {
     const int k = (int)wv;
-    persist_child<DT, HASV>(c, P, coff[k], clen[k], cdepth, s.dmax, s.req, out_s, cown[k], clook[k], hist);
+    persist_child<DT, HASV>(c, P, coff[k], clen[k], child_depth(s.depth, cdepth, s.len, clen[k], s.dmax),
+                            s.dmax, s.req, out_s, cown[k], clook[k], hist);
   }
   __syncthreads();
   if (tid == 0) {

@@ -150,7 +150,8 @@ def test_three_samples(oracle_mod):
 
 @pytest.mark.parametrize("fam", ["uniform", "many_equals", "sorted"])
 def test_min_pivot_forces_depth_fallback(oracle_mod, fam):
-    """Exact-minimum pivots peel one value per level until the depth limit; the
+    """Exact-minimum pivots peel one value off a part; a child that keeps more
+    than 15/16 of its part's keys takes the depth limit at once, and the
     exact-median fallback must then finish within log2(n) more levels."""
     import paper_1505_00558_amd as tsqs
     n = 60001
