@@ -104,11 +104,17 @@ enum {
                                 the persistent kernel before it stops every workgroup
                                 and reports an error; 0 (default) = 2^23 (a wait of
                                 some seconds; a run of the kernel takes far fewer) */
-  TSQS_OPT_QUEUE_DIRECT = 13 /* serving queues opened after this: requests of at
+  TSQS_OPT_QUEUE_DIRECT = 13, /* serving queues opened after this: requests of at
                                 least this many keys are sorted by the single-array
                                 schedule on a stream of the queue's own instead of
                                 the queue's ticks (tsqs_queue.h); 0 = never;
                                 default 2^22 */
+  TSQS_OPT_PART_THREADS1 = 14, /* workgroup size of the one-level partition kernel: 512
+                                (default; 32 4-byte keys per thread) or 1024 (16 per
+                                thread); a chunk is the same 16384 keys either way */
+  TSQS_OPT_PART_THREADS2 = 15  /* workgroup size of the two-level partition kernel: 256
+                                (default; 32 4-byte keys per thread) or 512 (16 per
+                                thread); a chunk is the same 8192 keys either way */
 };
 
 #define TSQS_MAX_LEVELS 192
@@ -206,8 +212,10 @@ typedef struct {
   int64_t finish_algo;   /* TSQS_OPT_FINISH_ALGO */
   double ms_default;     /* sort time with the options in force at the call */
   double ms_best;        /* sort time with the chosen options */
-  uint32_t trials;       /* configurations timed */
+  uint32_t trials;       /* configurations timed (0: taken from the tuning cache) */
   uint32_t reserved;
+  int64_t part_threads1; /* TSQS_OPT_PART_THREADS1 */
+  int64_t part_threads2; /* TSQS_OPT_PART_THREADS2 */
 } tsqs_tune_t;
 
 /* Autotuner: times sorts of seeded uniform keys of type dt (with a uint32
@@ -215,11 +223,20 @@ typedef struct {
  * when h_offsets is NULL, else the nseg arrays of h_offsets (as for
  * tsqs_sort_batch; n must equal h_offsets[nseg]) -- over candidate values of
  * the small-part threshold, the pivot sample count, the partition and finish
- * grids and the small-part algorithm (one parameter at a time, keeping the best
+ * grids, the small-part algorithm and the partition kernels' workgroup sizes
+ * (threads against keys per thread; one parameter at a time, keeping the best
  * so far), then sets the fastest as the current options and reports it in *out
  * (may be NULL).  Uses 2 n keys (+ 2 n payloads) of temporary device memory,
  * freed before it returns.  Returns TSQS_OK or an error code; on error the
- * options in force at the call are restored. */
+ * options in force at the call are restored.
+ *
+ * Tuning cache: when the environment variable TSQS_TUNE_CACHE names a file, a
+ * line there for the same device architecture (gcnArchName up to its first
+ * ':'), key type, payload, batch or single array, and ceil(log2 n) is applied
+ * without timing anything (out->trials = 0); otherwise the tuner runs and
+ * appends its result as one text line.  The file is read and appended under
+ * the library's lock, so the threads of one process share it; separate
+ * processes must not tune into the same file at the same time. */
 int tsqs_autotune(int dt, int with_payload, size_t n, const uint64_t *h_offsets, size_t nseg,
                   void *stream, tsqs_tune_t *out);
 

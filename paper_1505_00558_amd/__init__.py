@@ -24,6 +24,7 @@ NOALLOC_SCRATCH_BYTES = 32 << 20
 OPT_SMALL_MAX, OPT_SAMPLES, OPT_DEPTH_FACTOR, OPT_PIVOT_MODE = 1, 2, 3, 4
 OPT_SEED, OPT_TIMING, OPT_PART_GRID, OPT_FINISH_GRID, OPT_FINISH_ALGO = 5, 6, 7, 8, 9
 OPT_PRESORT, OPT_SCHEDULE, OPT_ITER_CAP, OPT_QUEUE_DIRECT = 10, 11, 12, 13
+OPT_PART_THREADS1, OPT_PART_THREADS2 = 14, 15
 SCHEDULE_LEVELS, SCHEDULE_PERSISTENT = 0, 1
 MAX_LEVELS = 192
 
@@ -92,6 +93,8 @@ class Tune(ctypes.Structure):
         ("ms_best", ctypes.c_double),
         ("trials", ctypes.c_uint32),
         ("reserved", ctypes.c_uint32),
+        ("part_threads1", ctypes.c_int64),
+        ("part_threads2", ctypes.c_int64),
     ]
 
     def as_dict(self) -> dict:

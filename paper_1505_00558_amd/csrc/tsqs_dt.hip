@@ -24,6 +24,23 @@ namespace tsqs {
 namespace host {
 namespace {
 
+// The partition kernels of level d: the one-level kernel, then (d > 0 or
+// `two`) the two-level kernel, each at the workgroup size the options choose
+// (TSQS_OPT_PART_THREADS1 / 2: the default, or twice the threads with half the
+// keys each).
+template <int DT, bool HASV, bool WIDE>
+void launch_pass(const Ctx &c, int d, bool two, int grid, hipStream_t s) {
+  if (g_opt.part_threads1 == 2 * kPartNT1)
+    hipLaunchKernelGGL((k_partition<DT, HASV, WIDE, false, 2>), dim3(grid), dim3(2 * kPartNT1), 0, s, c, d);
+  else
+    hipLaunchKernelGGL((k_partition<DT, HASV, WIDE, false, 1>), dim3(grid), dim3(kPartNT1), 0, s, c, d);
+  if (!two) return;
+  if (g_opt.part_threads2 == 2 * kPartNT2)
+    hipLaunchKernelGGL((k_partition<DT, HASV, WIDE, true, 2>), dim3(grid), dim3(2 * kPartNT2), 0, s, c, d);
+  else
+    hipLaunchKernelGGL((k_partition<DT, HASV, WIDE, true, 1>), dim3(grid), dim3(kPartNT2), 0, s, c, d);
+}
+
 template <int DT, bool HASV>
 int launch_finish(const Ctx &c, int d, int grid, size_t lds, hipStream_t s) {
   if (g_opt.finish_algo == 0)
@@ -179,13 +196,9 @@ int run_t(const CallEnv &env, const CallArgs &a) {
     if (timing) HIPCHK(hipEventRecord(env.ev[2 * d], s));
     if (idle) {
     } else if (wide) {
-      hipLaunchKernelGGL((k_partition<DT, HASV, true, false>), dim3(part_grid), dim3(kPartNT1), 0, s, c, d);
-      if (d > 0)
-        hipLaunchKernelGGL((k_partition<DT, HASV, true, true>), dim3(part_grid), dim3(kPartNT2), 0, s, c, d);
+      launch_pass<DT, HASV, true>(c, d, d > 0, part_grid, s);
     } else {
-      hipLaunchKernelGGL((k_partition<DT, HASV, false, false>), dim3(part_grid), dim3(kPartNT1), 0, s, c, d);
-      if (d > 0)
-        hipLaunchKernelGGL((k_partition<DT, HASV, false, true>), dim3(part_grid), dim3(kPartNT2), 0, s, c, d);
+      launch_pass<DT, HASV, false>(c, d, d > 0, part_grid, s);
     }
     if (timing) HIPCHK(hipEventRecord(env.ev[2 * d + 1], s));
     if (!idle) hipLaunchKernelGGL((k_plan<DT, HASV>), dim3(plan_grid), dim3(kPlanNT), 0, s, c, d);
@@ -303,13 +316,8 @@ int queue_tick(tsqs_queue *q, QGroup &G) {
     hipLaunchKernelGGL((k_init<DT, false>), dim3(wgs < (uint32_t)grid ? wgs : (uint32_t)grid),
                        dim3(kPlanNT), 0, G.s, c);
   }
-  if ((uint64_t)G.max_n * G.kb > 0xFFFFFFFFull) {
-    hipLaunchKernelGGL((k_partition<DT, false, true, false>), dim3(grid), dim3(kPartNT1), 0, G.s, c, d);
-    hipLaunchKernelGGL((k_partition<DT, false, true, true>), dim3(grid), dim3(kPartNT2), 0, G.s, c, d);
-  } else {
-    hipLaunchKernelGGL((k_partition<DT, false, false, false>), dim3(grid), dim3(kPartNT1), 0, G.s, c, d);
-    hipLaunchKernelGGL((k_partition<DT, false, false, true>), dim3(grid), dim3(kPartNT2), 0, G.s, c, d);
-  }
+  if ((uint64_t)G.max_n * G.kb > 0xFFFFFFFFull) launch_pass<DT, false, true>(c, d, true, grid, G.s);
+  else launch_pass<DT, false, false>(c, d, true, grid, G.s);
   hipLaunchKernelGGL((k_plan<DT, false>), dim3(grid), dim3(kPlanNT), 0, G.s, c, d);
   const int fgrid = g_opt.finish_grid > 0 ? (int)g_opt.finish_grid : kFinGridPerCu * q->cus;
   if (g_opt.finish_algo == 0)

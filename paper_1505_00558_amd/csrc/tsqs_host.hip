@@ -9,6 +9,9 @@
 #include <hip/hip_runtime.h>
 
 #include <chrono>
+#include <cstdio>
+#include <cstdlib>
+#include <string>
 #include <climits>
 #include <cstring>
 #include <deque>
@@ -269,6 +272,60 @@ int stats_of_last(tsqs_stats_t *out) {
   st.tail_bytes = 2ull * st.tail_keys * (lc.kb + lc.vb);
   st.error_flags = (uint32_t)lc.h_stats[kStripes * kStatWords];
   return st.error_flags ? TSQS_EINTERNAL : TSQS_OK;
+}
+
+// ---- tuning cache (TSQS_TUNE_CACHE): one text line per tuned shape ----------
+//   <arch> dt=<t> v=<0|1> b=<0|1> lg=<ceil log2 n> | small_max=.. samples=..
+//   part_grid=.. finish_grid=.. finish_algo=.. part_threads1=.. part_threads2=..
+//   ms_default=.. ms_best=..
+// The last valid line for a key wins.
+
+std::mutex g_tune_mu;
+
+bool tune_values_ok(const Options &o) {
+  return o.small_max >= 16 && o.small_max <= 8192 && o.samples >= 3 && o.samples <= 63 &&
+         (o.samples & 1) && o.part_grid >= 0 && o.part_grid <= 65536 && o.finish_grid >= 0 &&
+         o.finish_grid <= 65536 && o.finish_algo >= 0 && o.finish_algo <= 3 &&
+         (o.part_threads1 == kPartNT1 || o.part_threads1 == 2 * kPartNT1) &&
+         (o.part_threads2 == kPartNT2 || o.part_threads2 == 2 * kPartNT2);
+}
+
+bool tune_cache_find(const char *path, const std::string &key, Options *o, double *md, double *mb) {
+  FILE *f = std::fopen(path, "r");
+  if (!f) return false;
+  bool found = false;
+  char line[512];
+  while (std::fgets(line, sizeof line, f)) {
+    const char *bar = std::strstr(line, " | ");
+    if (!bar || (size_t)(bar - line) != key.size() || std::strncmp(line, key.c_str(), key.size()) != 0) continue;
+    Options t = *o;
+    long long sm, sa, pg, fg, fa, p1, p2;
+    double d0, d1;
+    if (std::sscanf(bar + 3,
+                    "small_max=%lld samples=%lld part_grid=%lld finish_grid=%lld finish_algo=%lld "
+                    "part_threads1=%lld part_threads2=%lld ms_default=%lf ms_best=%lf",
+                    &sm, &sa, &pg, &fg, &fa, &p1, &p2, &d0, &d1) != 9)
+      continue;
+    t.small_max = sm; t.samples = sa; t.part_grid = pg; t.finish_grid = fg; t.finish_algo = fa;
+    t.part_threads1 = p1; t.part_threads2 = p2;
+    if (!tune_values_ok(t)) continue;
+    *o = t; *md = d0; *mb = d1;
+    found = true;
+  }
+  std::fclose(f);
+  return found;
+}
+
+void tune_cache_append(const char *path, const std::string &key, const Options &o, double md, double mb) {
+  FILE *f = std::fopen(path, "a");
+  if (!f) return;
+  std::fprintf(f,
+               "%s | small_max=%lld samples=%lld part_grid=%lld finish_grid=%lld finish_algo=%lld "
+               "part_threads1=%lld part_threads2=%lld ms_default=%.4f ms_best=%.4f\n",
+               key.c_str(), (long long)o.small_max, (long long)o.samples, (long long)o.part_grid,
+               (long long)o.finish_grid, (long long)o.finish_algo, (long long)o.part_threads1,
+               (long long)o.part_threads2, md, mb);
+  std::fclose(f);
 }
 
 // ---- autotuner inputs: seeded uniform keys (SplitMix64) and payload = index ----
@@ -997,6 +1054,8 @@ int tsqs_set_option(int key, int64_t v) {
     case TSQS_OPT_SCHEDULE: if (v < 0 || v > 1) return TSQS_EINVAL; g_opt.schedule = v; return TSQS_OK;
     case TSQS_OPT_ITER_CAP: if (v < 0) return TSQS_EINVAL; g_opt.iter_cap = v; return TSQS_OK;
     case TSQS_OPT_QUEUE_DIRECT: if (v < 0 || v > 0xFFFFFFFFll) return TSQS_EINVAL; g_opt.queue_direct = v; return TSQS_OK;
+    case TSQS_OPT_PART_THREADS1: if (v != kPartNT1 && v != 2 * kPartNT1) return TSQS_EINVAL; g_opt.part_threads1 = v; return TSQS_OK;
+    case TSQS_OPT_PART_THREADS2: if (v != kPartNT2 && v != 2 * kPartNT2) return TSQS_EINVAL; g_opt.part_threads2 = v; return TSQS_OK;
     default: return TSQS_EUNSUPPORTED;
   }
 }
@@ -1017,6 +1076,8 @@ int64_t tsqs_get_option(int key) {
     case TSQS_OPT_SCHEDULE: return g_opt.schedule;
     case TSQS_OPT_ITER_CAP: return g_opt.iter_cap;
     case TSQS_OPT_QUEUE_DIRECT: return g_opt.queue_direct;
+    case TSQS_OPT_PART_THREADS1: return g_opt.part_threads1;
+    case TSQS_OPT_PART_THREADS2: return g_opt.part_threads2;
     default: return INT64_MIN;
   }
 }
@@ -1041,7 +1102,7 @@ const char *tsqs_strerror(int code) {
   }
 }
 
-int tsqs_version(void) { return 2; }
+int tsqs_version(void) { return 3; }
 
 }  // extern "C"
 
@@ -1070,6 +1131,39 @@ int tsqs_autotune(int dt, int with_payload, size_t n, const uint64_t *h_offsets,
   {
     std::lock_guard<std::mutex> lk(g_mu);
     saved = g_opt;
+  }
+  // tuning cache: the same architecture and shape tuned before
+  const char *cache = std::getenv("TSQS_TUNE_CACHE");
+  if (cache && !*cache) cache = nullptr;
+  std::string ckey;
+  if (cache) {
+    std::string arch(prop.gcnArchName);
+    arch = arch.substr(0, arch.find(':'));
+    char kb_[160];
+    std::snprintf(kb_, sizeof kb_, "%s dt=%d v=%d b=%d lg=%u", arch.c_str(), dt, with_payload ? 1 : 0,
+                  h_offsets ? 1 : 0, ceil_log2(n));
+    ckey = kb_;
+    Options o = saved;
+    double md = 0.0, mb = 0.0;
+    bool hit;
+    {
+      std::lock_guard<std::mutex> lk(g_tune_mu);
+      hit = tune_cache_find(cache, ckey, &o, &md, &mb);
+    }
+    if (hit) {
+      {
+        std::lock_guard<std::mutex> lk(g_mu);
+        g_opt = o;
+      }
+      if (out) {
+        std::memset(out, 0, sizeof *out);
+        out->small_max = o.small_max; out->samples = o.samples; out->part_grid = o.part_grid;
+        out->finish_grid = o.finish_grid; out->finish_algo = o.finish_algo;
+        out->part_threads1 = o.part_threads1; out->part_threads2 = o.part_threads2;
+        out->ms_default = md; out->ms_best = mb; out->trials = 0;
+      }
+      return TSQS_OK;
+    }
   }
   unsigned char *keys0 = nullptr, *keys = nullptr;
   uint32_t *vals = nullptr;
@@ -1129,6 +1223,9 @@ int tsqs_autotune(int dt, int with_payload, size_t n, const uint64_t *h_offsets,
   for (int64_t m : {2, 4, 8}) try_value(&Options::part_grid, m * cus);
   for (int64_t m : {8, 16, 32}) try_value(&Options::finish_grid, m * cus);
   for (int64_t a : {0, 1, 2, 3}) try_value(&Options::finish_algo, a);
+  // workgroup size against keys per thread (the same chunk of keys)
+  for (int64_t t : {(int64_t)kPartNT1, (int64_t)2 * kPartNT1}) try_value(&Options::part_threads1, t);
+  for (int64_t t : {(int64_t)kPartNT2, (int64_t)2 * kPartNT2}) try_value(&Options::part_threads2, t);
   {
     std::lock_guard<std::mutex> lk(g_mu);
     g_opt = rc == TSQS_OK ? best : saved;
@@ -1142,10 +1239,16 @@ int tsqs_autotune(int dt, int with_payload, size_t n, const uint64_t *h_offsets,
     out->part_grid = best.part_grid;
     out->finish_grid = best.finish_grid;
     out->finish_algo = best.finish_algo;
+    out->part_threads1 = best.part_threads1;
+    out->part_threads2 = best.part_threads2;
     out->ms_default = ms_default;
     out->ms_best = ms_best;
     out->trials = trials;
     out->reserved = 0;
+  }
+  if (rc == TSQS_OK && cache) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    tune_cache_append(cache, ckey, best, ms_default, ms_best);
   }
   return rc;
 }

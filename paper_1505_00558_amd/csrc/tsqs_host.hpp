@@ -50,6 +50,8 @@ struct Options {
   int64_t schedule = 0;        // TSQS_OPT_SCHEDULE
   int64_t iter_cap = 0;        // TSQS_OPT_ITER_CAP (0: the default)
   int64_t queue_direct = 1 << 22;   // TSQS_OPT_QUEUE_DIRECT
+  int64_t part_threads1 = kPartNT1;  // TSQS_OPT_PART_THREADS1
+  int64_t part_threads2 = kPartNT2;  // TSQS_OPT_PART_THREADS2
 };
 
 constexpr unsigned long long kDefaultIterCap = 1ull << 23;

@@ -128,13 +128,15 @@ template <> struct Codec<4> {  // float32 bits, IEEE totalOrder: negatives rever
 };
 
 // Geometry of the partition pass per element type and pass type.
-template <int DT, bool HASV, bool TWO, int NT_ = (TWO ? kPartNT2 : kPartNT1)> struct PartCfg {
+// KPT_ = 0: the default keys per thread of the key type; a workgroup of twice
+// the threads with half the keys each (KPT_ = default / 2) has the same chunk.
+template <int DT, bool HASV, bool TWO, int NT_ = (TWO ? kPartNT2 : kPartNT1), int KPT_ = 0> struct PartCfg {
   using B = typename Codec<DT>::B;
   static constexpr int NT = NT_;                                        // threads
   static constexpr int NW = NT / kWave;
   static constexpr int KB = (int)sizeof(B);
   static constexpr int VEC = 16 / KB;                                   // keys per 16-byte load
-  static constexpr int KPT = KB == 4 ? (HASV ? 16 : 32) : (HASV ? 8 : 16);  // keys per thread
+  static constexpr int KPT = KPT_ ? KPT_ : (KB == 4 ? (HASV ? 16 : 32) : (HASV ? 8 : 16));  // keys per thread
   static constexpr int NLOAD = KPT / VEC;
   static constexpr uint64_t CH = (uint64_t)NT * KPT;                    // keys per chunk
   static constexpr uint64_t LINE = 128 / KB;                            // keys per 128-byte line
@@ -1114,9 +1116,9 @@ __device__ inline T *at(T *base, uint32_t i) {
 // loaded from HBM straight into LDS while the current chunk is processed; each
 // wave loads, and later reads, only its own blocks (element j * NT + tid is
 // window block j * NT + tid), so no barrier guards the stage.
-template <int DT, bool HASV, bool TWO, int NT>
+template <int DT, bool HASV, bool TWO, int NT, int KPT_ = 0>
 struct PartLds {
-  using Cfg = PartCfg<DT, HASV, TWO, NT>;
+  using Cfg = PartCfg<DT, HASV, TWO, NT, KPT_>;
   static constexpr bool STAGE = TWO ? kStageTwo : kStageOne;
   uint32_t cnt[2][8][Cfg::NW];
   uint32_t sh_part;
@@ -1128,15 +1130,15 @@ struct PartLds {
 // TWO are skipped), workgroup of NT threads.  ctr: the parts' counter lines.
 // WIDE: some part may span 4 GiB or more of keys or payloads.  SP: pointer to
 // the records (constant address space when they are read-only for the kernel).
-template <int DT, bool HASV, bool WIDE, bool TWO, int NT, typename SP>
+template <int DT, bool HASV, bool WIDE, bool TWO, int NT, int KPT_ = 0, typename SP>
 __device__ __attribute__((always_inline)) inline void partition_chunks(
     const Ctx &c, SP segs, unsigned long long *ctr, uint32_t nseg, uint32_t t0, uint32_t t1,
-    PartLds<DT, HASV, TWO, NT> &L) {
-  using Cfg = PartCfg<DT, HASV, TWO, NT>;
+    PartLds<DT, HASV, TWO, NT, KPT_> &L) {
+  using Cfg = PartCfg<DT, HASV, TWO, NT, KPT_>;
   using B = typename Cfg::B;
   using C = typename Codec<DT>::C;
   // keys staged through LDS (the next chunk's loads in flight during this one)
-  constexpr bool STAGE = PartLds<DT, HASV, TWO, NT>::STAGE;
+  constexpr bool STAGE = PartLds<DT, HASV, TWO, NT, KPT_>::STAGE;
   constexpr int NW = Cfg::NW, VEC = Cfg::VEC, KPT = Cfg::KPT;
   constexpr int NLOAD = Cfg::NLOAD, KB = Cfg::KB;
   constexpr uint64_t CH = Cfg::CH;
@@ -1604,10 +1606,14 @@ __device__ __attribute__((always_inline)) inline void partition_chunks(
 // One partition level: every chunk of every part of level d whose pass type is
 // TWO (two-level parts); the parts of the other type are skipped (a kernel per
 // type, so each has the registers, and the occupancy, its own work needs).
-template <int DT, bool HASV, bool WIDE, bool TWO>
-__global__ __launch_bounds__(TWO ? kPartNT2 : kPartNT1) void k_partition(Ctx c, int d) {
-  constexpr int NT = TWO ? kPartNT2 : kPartNT1;
-  __shared__ PartLds<DT, HASV, TWO, NT> L;
+// WGX = 2: twice the threads per workgroup, half the keys per thread (the same
+// chunks: the planning's chunk counts hold for either).
+template <int DT, bool HASV, bool WIDE, bool TWO, int WGX = 1>
+__global__ __launch_bounds__((TWO ? kPartNT2 : kPartNT1) * WGX) void k_partition(Ctx c, int d) {
+  constexpr int NT = (TWO ? kPartNT2 : kPartNT1) * WGX;
+  constexpr int KPT_ = WGX == 1 ? 0 : PartCfg<DT, HASV, TWO>::KPT / WGX;
+  static_assert(PartCfg<DT, HASV, TWO, NT, KPT_>::CH == PartCfg<DT, HASV, TWO>::CH, "chunk");
+  __shared__ PartLds<DT, HASV, TWO, NT, KPT_> L;
   const unsigned long long packed = c.lvl[d].packed;
   const uint32_t nseg = (uint32_t)(packed >> 40);
   const uint32_t nch = (uint32_t)(packed & kTileMask);
@@ -1622,7 +1628,7 @@ __global__ __launch_bounds__(TWO ? kPartNT2 : kPartNT1) void k_partition(Ctx c, 
   // become scalar loads even after this kernel's own stores
   const CSeg *segs = (const CSeg *)((d & 1) ? c.seg1 : c.seg0);
   unsigned long long *ctr = (d & 1) ? c.ctr1 : c.ctr0;
-  partition_chunks<DT, HASV, WIDE, TWO, NT>(c, segs, ctr, nseg, t0, t1, L);
+  partition_chunks<DT, HASV, WIDE, TWO, NT, KPT_>(c, segs, ctr, nseg, t0, t1, L);
 }
 
 // After level d: bands, small children, next-level parts with pivots (a wave per

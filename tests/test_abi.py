@@ -42,7 +42,7 @@ def test_exports_every_declared_symbol(lib):
 
 
 def test_version_and_strerror(lib):
-    assert lib.tsqs_version() == 2
+    assert lib.tsqs_version() == 3
     import paper_1505_00558_amd as tsqs
     for code in (0, -1, -2, -3, -4, -5, -6):
         assert tsqs.strerror(code) and tsqs.strerror(code) != "unknown error code"
@@ -116,6 +116,14 @@ def test_options(lib):
         assert lib.tsqs_set_option(tsqs.OPT_QUEUE_DIRECT, 0) == 0
         assert tsqs.get_option(tsqs.OPT_QUEUE_DIRECT) == 0
         assert lib.tsqs_set_option(tsqs.OPT_QUEUE_DIRECT, 1 << 22) == 0
+        for key, ok, bad in ((tsqs.OPT_PART_THREADS1, (512, 1024), (256, 768, 2048)),
+                             (tsqs.OPT_PART_THREADS2, (256, 512), (128, 384, 1024))):
+            assert tsqs.get_option(key) == ok[0]
+            for v in bad:
+                assert lib.tsqs_set_option(key, v) == -1
+            for v in ok[::-1]:
+                assert lib.tsqs_set_option(key, v) == 0
+                assert tsqs.get_option(key) == v
         assert lib.tsqs_set_option(999, 1) == -4
         assert tsqs.get_option(999) == -(1 << 63)
     finally:

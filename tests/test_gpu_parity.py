@@ -29,6 +29,8 @@ def gpu():
     tsqs.set_option(tsqs.OPT_SAMPLES, 63)
     tsqs.set_option(tsqs.OPT_PIVOT_MODE, 0)
     tsqs.set_option(tsqs.OPT_PRESORT, 1)
+    tsqs.set_option(tsqs.OPT_PART_THREADS1, 512)
+    tsqs.set_option(tsqs.OPT_PART_THREADS2, 256)
 
 
 def test_config1_one_million_int32(oracle_mod):
@@ -277,7 +279,8 @@ def test_autotune_chooses_valid_options_and_sorts(oracle_mod):
     import paper_1505_00558_amd as tsqs
     before = {k: tsqs.get_option(k) for k in (tsqs.OPT_SMALL_MAX, tsqs.OPT_SAMPLES,
                                                tsqs.OPT_PART_GRID, tsqs.OPT_FINISH_GRID,
-                                               tsqs.OPT_FINISH_ALGO)}
+                                               tsqs.OPT_FINISH_ALGO, tsqs.OPT_PART_THREADS1,
+                                               tsqs.OPT_PART_THREADS2)}
     try:
         r = tsqs.autotune(tsqs.INT32, 1 << 22)
         print("case: autotune", r, flush=True)
@@ -285,6 +288,8 @@ def test_autotune_chooses_valid_options_and_sorts(oracle_mod):
         assert tsqs.get_option(tsqs.OPT_SMALL_MAX) == r["small_max"]
         assert tsqs.get_option(tsqs.OPT_SAMPLES) == r["samples"]
         assert tsqs.get_option(tsqs.OPT_FINISH_ALGO) == r["finish_algo"]
+        assert tsqs.get_option(tsqs.OPT_PART_THREADS1) == r["part_threads1"] in (512, 1024)
+        assert tsqs.get_option(tsqs.OPT_PART_THREADS2) == r["part_threads2"] in (256, 512)
         for fam in ("uniform", "organ_pipe", "many_equals"):
             k = ti.family(fam, 1 << 20, "int32", seed=ti.seed_for(2, fam) + 3)
             assert same_bits(gpu_sort(k), oracle_mod.sort(k)), fam
@@ -344,3 +349,58 @@ def test_small_part_sizes(oracle_mod, dtype, algo):
             assert same_bits(gk, oracle_mod.sort(k)) and payload_valid(k, gk, gv), n
     finally:
         tsqs.set_option(tsqs.OPT_FINISH_ALGO, before)
+
+
+@pytest.mark.parametrize("threads", [(1024, 256), (512, 512), (1024, 512)])
+@pytest.mark.parametrize("dtype", list(ti.DTYPES))
+def test_partition_workgroup_sizes(oracle_mod, dtype, threads):
+    """The partition kernels at twice the threads with half the keys per thread
+    (TSQS_OPT_PART_THREADS1 / 2): keys and payloads as for the default sizes."""
+    import paper_1505_00558_amd as tsqs
+    tsqs.set_option(tsqs.OPT_PART_THREADS1, threads[0])
+    tsqs.set_option(tsqs.OPT_PART_THREADS2, threads[1])
+    try:
+        for fam, n in (("uniform", 300007), ("many_equals", 70001), ("organ_pipe", 200003),
+                       ("stair_steps", 123457)):
+            print("case: partition threads", threads, dtype, fam, n, flush=True)
+            k = ti.family(fam, n, dtype, seed=ti.seed_for(3, fam) + 11)
+            assert same_bits(gpu_sort(k), oracle_mod.sort(k)), (fam, n)
+            v = np.arange(n, dtype=np.uint32)
+            gk, gv = gpu_sort_pairs(k, v)
+            assert same_bits(gk, oracle_mod.sort(k)) and payload_valid(k, gk, gv), (fam, n)
+    finally:
+        tsqs.set_option(tsqs.OPT_PART_THREADS1, 512)
+        tsqs.set_option(tsqs.OPT_PART_THREADS2, 256)
+
+
+def test_tune_cache(tmp_path, monkeypatch):
+    """TSQS_TUNE_CACHE: the first tuning of a shape times candidates and appends
+    one line (this device's architecture and the shape); the same shape again
+    takes that line without timing anything and sets the same options; another
+    shape tunes and appends."""
+    import paper_1505_00558_amd as tsqs
+    keys = (tsqs.OPT_SMALL_MAX, tsqs.OPT_SAMPLES, tsqs.OPT_PART_GRID, tsqs.OPT_FINISH_GRID,
+            tsqs.OPT_FINISH_ALGO, tsqs.OPT_PART_THREADS1, tsqs.OPT_PART_THREADS2)
+    names = ("small_max", "samples", "part_grid", "finish_grid", "finish_algo", "part_threads1",
+             "part_threads2")
+    before = {k: tsqs.get_option(k) for k in keys}
+    path = tmp_path / "tune.txt"
+    monkeypatch.setenv("TSQS_TUNE_CACHE", str(path))
+    try:
+        r1 = tsqs.autotune(tsqs.INT32, 1 << 20)
+        assert r1["trials"] >= 5
+        lines = path.read_text().splitlines()
+        assert len(lines) == 1 and lines[0].startswith("gfx") and " dt=0 v=0 b=0 lg=20 | " in lines[0]
+        tsqs.set_option(tsqs.OPT_SMALL_MAX, 1024)
+        tsqs.set_option(tsqs.OPT_FINISH_ALGO, 0)
+        r2 = tsqs.autotune(tsqs.INT32, (1 << 20) - 5)     # the same ceil(log2 n)
+        assert r2["trials"] == 0
+        for k, nm in zip(keys, names):
+            assert r2[nm] == r1[nm] and tsqs.get_option(k) == r1[nm], nm
+        assert len(path.read_text().splitlines()) == 1
+        r3 = tsqs.autotune(tsqs.INT32, 1 << 18, with_payload=True)
+        assert r3["trials"] >= 5
+        assert len(path.read_text().splitlines()) == 2
+    finally:
+        for k, v in before.items():
+            tsqs.set_option(k, v)
