@@ -12,7 +12,7 @@ import numpy as np
 import pytest
 
 import tsqs_inputs as ti
-from gpu_util import gpu_sort, gpu_sort_pairs, payload_valid, same_bits
+from gpu_util import CODES, from_dev, gpu_sort, gpu_sort_pairs, payload_valid, same_bits, to_dev
 
 pytestmark = pytest.mark.gpu
 
@@ -154,39 +154,73 @@ def test_option_off(oracle_mod):
         tsqs.set_option(tsqs.OPT_PRESORT, 1)
 
 
-def test_batch_arrays(oracle_mod):
+def _as_dtype(x, dtype):
+    """The int32 pattern x as keys of another type, order kept."""
+    x = x.astype(np.int64)
+    if dtype == "int32":
+        return x.astype(np.int32)
+    if dtype == "uint32":
+        return (x + (1 << 31)).astype(np.uint32)
+    if dtype == "int64":
+        return x * 3 - (1 << 40)
+    if dtype == "uint64":
+        return (x + (1 << 40)).astype(np.uint64)
+    return x.astype(np.float32)      # |x| < 2^24: exact
+
+
+@pytest.mark.parametrize("with_vals", [False, True], ids=["keys", "pairs"])
+@pytest.mark.parametrize("dtype", list(ti.DTYPES))
+def test_batch_arrays(oracle_mod, dtype, with_vals):
     """Batches: each array that needs a pass, up to 2^16 keys, is checked by its own
     wave; arrays found in order (here: sorted, reversed, all equal) take no pass, the
-    others do."""
+    others do.  Every key type, keys alone and with payloads."""
     import paper_1505_00558_amd as tsqs
     import torch
     asc = (np.arange(N, dtype=np.int64) * 5 - 5 * (N // 2)).astype(np.int32)
-    uni = ti.family("uniform", N, "int32", seed=40)
+    uni = ti.family("uniform", N, "int32", seed=40) >> 8
     near = asc.copy()
     near[1000], near[1001] = near[1001], near[1000]
     parts = [asc[:60000], asc[60000:120000][::-1], np.full(20000, 7, np.int32), uni[:200000],
              near[:50000], asc[:3000][::-1], uni[:9000][::-1].copy(), asc[200000:400000]]
+    parts = [_as_dtype(p, dtype) for p in parts]
+    if dtype == "float32":
+        # a descending run through +0.0 and -0.0 (strictly decreasing in
+        # totalOrder, so it is reversed, -0.0 before +0.0)
+        parts[1] = np.concatenate([np.arange(30000, 0, -1) + 0.5, [0.0, -0.0],
+                                   -(np.arange(1, 30000) + 0.5)]).astype(np.float32)
     offs = np.cumsum([0] + [p.size for p in parts]).astype(np.uint64)
     keys = np.concatenate(parts)
-    for presort, want in ((1, 3), (0, 0)):
+    # small-part size of the type: 8192 4-byte records, 4096 8-byte, 2048 16-byte
+    # (8-byte keys with a payload); the 3000 reversed keys are a small part (no
+    # pass, no check) unless the records are 16 bytes
+    rec = keys.dtype.itemsize + (4 if with_vals else 0)
+    rec = 16 if rec > 8 else rec
+    small_max = 8192 * 4 // rec
+    found = 3 + (1 if 3000 > small_max else 0)
+    for presort, want in ((1, found), (0, 0)):
+        print("case: batch presort", dtype, with_vals, presort, flush=True)
         tsqs.set_option(tsqs.OPT_PRESORT, presort)
         try:
-            t = torch.from_numpy(keys.copy()).to("cuda:0")
-            v = torch.arange(keys.size, dtype=torch.int32, device="cuda:0")
-            tsqs.sort_batch(t, offs, vals=v)
+            t = to_dev(keys.copy())
+            v = torch.arange(keys.size, dtype=torch.int32, device="cuda:0") if with_vals else None
+            tsqs.sort_batch(t, offs, vals=v, dtype_code=CODES[keys.dtype])
             torch.cuda.synchronize()
             st = tsqs.get_stats()
         finally:
             tsqs.set_option(tsqs.OPT_PRESORT, 1)
-        got, gv = t.cpu().numpy(), v.cpu().numpy().astype(np.int64)
-        # found in order: 60000 sorted, 60000 reversed, 20000 equal keys (the 3000
-        # reversed keys are one small part: no pass, no check; the 200000 sorted
-        # keys are above the size a wave checks: they take the passes)
+        got = from_dev(t, keys.dtype)
+        # found in order: 60000 sorted, 60000 reversed, 20000 equal keys (and the
+        # 3000 reversed keys when they are not a small part); the 200000 sorted
+        # keys are above the size a wave checks: they take the passes
         assert st["presorted"] == want
         for a, b in zip(offs[:-1].tolist(), offs[1:].tolist()):
             assert same_bits(got[a:b], oracle_mod.sort(keys[a:b]))
-            assert np.all((gv[a:b] >= a) & (gv[a:b] < b))
-        assert np.array_equal(np.sort(gv), np.arange(keys.size)) and np.array_equal(keys[gv], got)
+        if with_vals:
+            gv = v.cpu().numpy().astype(np.int64)
+            for a, b in zip(offs[:-1].tolist(), offs[1:].tolist()):
+                assert np.all((gv[a:b] >= a) & (gv[a:b] < b))
+            assert np.array_equal(np.sort(gv), np.arange(keys.size))
+            assert same_bits(keys[gv], got)
 
 
 def test_large_arrays_skip_the_passes(oracle_mod):
