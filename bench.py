@@ -487,6 +487,27 @@ def run_batch_case(args, keys0, offs, label):
     batch = batched(tsqs.SCHEDULE_LEVELS)
     batch_p = batched(tsqs.SCHEDULE_PERSISTENT)
 
+    # the same call captured once into a graph (tsqs_graph_*), then replayed:
+    # restore (untimed), one launch
+    g = tsqs.Graph(work, offsets=offs)
+    try:
+        gms = []
+        for step in range(args.warmup + args.steps):
+            work.copy_(keys0)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            g.launch()
+            torch.cuda.synchronize()
+            if step >= args.warmup:
+                gms.append((time.perf_counter() - t0) * 1e3)
+        gst = g.stats()
+    finally:
+        g.destroy()
+    gm = float(np.median(gms))
+    batch_g = {"ms_median": gm, "ms_all": [round(x, 3) for x in gms], "keys_per_s": total / (gm / 1e3),
+               "levels": gst["levels"], "schedule": "levels, captured graph",
+               "latency_ms_p50": gm, "latency_ms_p99": gm, "sorted": device_sorted_check(work, offs)}
+
     # plain: one tsqs_sort per array on one stream from one host thread; each call
     # only enqueues, so the device runs the arrays back to back while the host
     # enqueues the next ones.  Completion times from timing events recorded after
@@ -521,12 +542,14 @@ def run_batch_case(args, keys0, offs, label):
         "total_keys": total,
         "batch": batch,
         "batch_persistent": batch_p,
+        "batch_graph": batch_g,
         "plain": {"ms": plain_ms, "keys_per_s": total / (plain_ms / 1e3),
                   "device_ms": float(grp_ms[-1]),
                   "latency_ms_p50": pct(done_ms, 50), "latency_ms_p99": pct(done_ms, 99),
                   "sorted": ok_plain, "calls": "non-blocking (enqueue only)"},
         "speedup": plain_ms / batch["ms_median"],
         "speedup_persistent": plain_ms / batch_p["ms_median"],
+        "speedup_graph": plain_ms / batch_g["ms_median"],
     }
 
 
@@ -543,10 +566,13 @@ def workload_batch(args):
         _, toffs, _, _ = ti.batch_plan(seed, args.batch_count, 4, 20, max_total=1 << 28)
         log("autotune on the capped batch shape (%d arrays)" % (toffs.size - 1))
         tuned = tsqs.autotune(tsqs.INT32, int(toffs[-1]), offsets=toffs)
-    for label, max_total in (("full", None), ("capped_2^28", 1 << 28)):
-        log("batch %s: generating %d arrays" % (label, args.batch_count))
-        keys0, offs, fams = ti.device_batch(seed, args.batch_count, 4, 20, "int32",
-                                            max_total=max_total)
+    # full: the configuration; capped: its first arrays up to 2^28 keys; small:
+    # 256 arrays of 16..4096 keys, where per-call launch cost dominates
+    for label, count, hi, max_total in (("full", args.batch_count, 20, None),
+                                        ("capped_2^28", args.batch_count, 20, 1 << 28),
+                                        ("small_256", 256, 12, None)):
+        log("batch %s: generating %d arrays" % (label, count))
+        keys0, offs, fams = ti.device_batch(seed, count, 4, hi, "int32", max_total=max_total)
         log("batch %s: %d arrays, %d keys" % (label, offs.size - 1, int(offs[-1])))
         cases.append(run_batch_case(args, keys0, offs, label))
         del keys0

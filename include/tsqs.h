@@ -240,6 +240,37 @@ typedef struct {
 int tsqs_autotune(int dt, int with_payload, size_t n, const uint64_t *h_offsets, size_t nseg,
                   void *stream, tsqs_tune_t *out);
 
+/* Graphs, for callers that sort the same buffers, of the same shape, many
+ * times (a batch of fixed array sizes refilled between sorts, a serving slot):
+ * the whole schedule of one call is captured once into a HIP graph and then
+ * replayed with one launch.
+ *
+ * tsqs_graph_create captures the sort of nmemb keys at d_keys (and payloads at
+ * d_vals, or NULL): one array when h_offsets is NULL, else the nseg arrays of
+ * h_offsets, with h_offsets[nseg] == nmemb (as tsqs_sort_batch; the offsets are
+ * copied to the device at creation and not read again).  Argument rules and
+ * limits are those of tsqs_sort / tsqs_sort_pairs / tsqs_sort_batch; a call
+ * with nothing to sort (fewer than two keys in every array) returns
+ * TSQS_EINVAL.  The options in force at creation are the graph's.  The graph
+ * owns a workspace of its own (about the size tsqs_sort would use), allocated
+ * at creation, so other calls of the library neither reuse nor regrow it.
+ * Creation waits for the device once (the buffers' first clears); it does not
+ * sort.
+ *
+ * tsqs_graph_launch enqueues one replay on stream (a hipStream_t, NULL = the
+ * default stream): it sorts whatever d_keys (and d_vals) hold when the replay
+ * runs, like the captured call.  Replays of one graph on different streams are
+ * ordered (a launch on another stream waits for the previous launch).
+ * tsqs_graph_stats waits for the last launch and reports it like
+ * tsqs_get_stats (without per-level times).  tsqs_graph_destroy waits for the
+ * last launch and frees the graph. */
+typedef struct tsqs_graph tsqs_graph_t;
+int tsqs_graph_create(void *d_keys, uint32_t *d_vals, size_t nmemb, const uint64_t *h_offsets,
+                      size_t nseg, int dt, tsqs_graph_t **out);
+int tsqs_graph_launch(tsqs_graph_t *g, void *stream);
+int tsqs_graph_stats(tsqs_graph_t *g, tsqs_stats_t *out);
+int tsqs_graph_destroy(tsqs_graph_t *g);
+
 /* Release the workspace of every device (SIII.G's manual release). */
 void tsqs_free_storage(void);
 

@@ -30,7 +30,8 @@ MAX_LEVELS = 192
 
 SYMBOLS = ["tsqs_sort", "tsqs_sort_pairs", "tsqs_sort_noalloc", "tsqs_sort_records", "tsqs_sort_batch", "tsqs_autotune",
            "tsqs_free_storage", "tsqs_set_option", "tsqs_get_option", "tsqs_get_stats",
-           "tsqs_strerror", "tsqs_version"]
+           "tsqs_strerror", "tsqs_version", "tsqs_graph_create", "tsqs_graph_launch",
+           "tsqs_graph_stats", "tsqs_graph_destroy"]
 QUEUE_SYMBOLS = ["tsqs_queue_open", "tsqs_queue_submit", "tsqs_queue_step", "tsqs_queue_poll",
                  "tsqs_queue_result", "tsqs_queue_reap", "tsqs_queue_release",
                  "tsqs_queue_info", "tsqs_queue_close"]
@@ -142,6 +143,14 @@ def load_library():
     lib.tsqs_strerror.restype = ctypes.c_char_p
     lib.tsqs_version.argtypes = []
     lib.tsqs_version.restype = ctypes.c_int
+    lib.tsqs_graph_create.argtypes = [vp, vp, sz, vp, sz, ctypes.c_int, ctypes.POINTER(vp)]
+    lib.tsqs_graph_create.restype = ctypes.c_int
+    lib.tsqs_graph_launch.argtypes = [vp, vp]
+    lib.tsqs_graph_launch.restype = ctypes.c_int
+    lib.tsqs_graph_stats.argtypes = [vp, ctypes.POINTER(Stats)]
+    lib.tsqs_graph_stats.restype = ctypes.c_int
+    lib.tsqs_graph_destroy.argtypes = [vp]
+    lib.tsqs_graph_destroy.restype = ctypes.c_int
     u64p = ctypes.POINTER(ctypes.c_uint64)
     lib.tsqs_queue_open.argtypes = [sz, vp, ctypes.POINTER(vp)]
     lib.tsqs_queue_submit.argtypes = [vp, vp, sz, ctypes.c_int, u64p]
@@ -278,6 +287,54 @@ def sort_batch(keys, offsets, vals=None, dtype_code: int | None = None):
                                           offs.ctypes.data_as(ctypes.c_void_p), nseg, dt,
                                           _stream_handle()))
     return keys
+
+
+class Graph:
+    """One sort of fixed buffers and shape captured into a HIP graph
+    (tsqs_graph_*): ``launch()`` replays it on the current stream, sorting
+    whatever the buffers hold then.  ``offsets`` as for ``sort_batch``, or None
+    for one array."""
+
+    def __init__(self, keys, offsets=None, vals=None, dtype_code: int | None = None):
+        import numpy as np
+        _check_tensor(keys, "keys")
+        vp = None
+        if vals is not None:
+            _check_tensor(vals, "vals")
+            if vals.numel() != keys.numel() or vals.element_size() != 4:
+                raise ValueError("vals must hold one 4-byte payload per key")
+            vp = ctypes.c_void_p(vals.data_ptr())
+        offs, nseg = None, 0
+        if offsets is not None:
+            offs = np.ascontiguousarray(np.asarray(offsets, dtype=np.uint64))
+            nseg = offs.size - 1
+        dt = _dtype_code(keys) if dtype_code is None else dtype_code
+        self._lib = load_library()
+        self._g = ctypes.c_void_p()
+        self._keep = (keys, vals)        # the buffers the graph sorts stay alive with it
+        _check(self._lib.tsqs_graph_create(
+            ctypes.c_void_p(keys.data_ptr()), vp, keys.numel(),
+            offs.ctypes.data_as(ctypes.c_void_p) if offs is not None else None, nseg, dt,
+            ctypes.byref(self._g)))
+
+    def launch(self) -> None:
+        _check(self._lib.tsqs_graph_launch(self._g, _stream_handle()))
+
+    def stats(self) -> dict:
+        s = Stats()
+        _check(self._lib.tsqs_graph_stats(self._g, ctypes.byref(s)))
+        return s.as_dict()
+
+    def destroy(self) -> None:
+        if self._g:
+            g, self._g = self._g, ctypes.c_void_p()
+            _check(self._lib.tsqs_graph_destroy(g))
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
 
 
 def autotune(dtype_code: int, n: int, with_payload: bool = False, offsets=None) -> dict:

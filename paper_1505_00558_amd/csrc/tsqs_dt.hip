@@ -89,7 +89,8 @@ int run_t(const CallEnv &env, const CallArgs &a) {
   const FinGeom geo = fin_geom<DT, HASV>(env.lds_budget, g_opt.small_max);
   const uint32_t small_max = geo.small_max, wave_max = geo.wave_max;
   const size_t seg_cap = w.seg_cap, big_cap = w.big_cap;
-  if (h_offs) HIPCHK(hipMemcpyAsync(w.offs, h_offs, (nroots + 1) * sizeof(uint64_t), hipMemcpyHostToDevice, s));
+  if (h_offs && !a.offs_ready)
+    HIPCHK(hipMemcpyAsync(w.offs, h_offs, (nroots + 1) * sizeof(uint64_t), hipMemcpyHostToDevice, s));
   const bool timing = g_opt.timing && env.ev;
 
   Ctx c;

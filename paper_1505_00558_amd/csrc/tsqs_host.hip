@@ -34,6 +34,21 @@ LastCall g_last;
 using namespace tsqs;
 using namespace tsqs::host;
 
+// A captured sort (tsqs_graph_*): its own workspace, so that calls of the
+// library between launches can neither reuse nor regrow the buffers the graph's
+// kernels hold.
+struct tsqs_graph {
+  int dev = 0;
+  Workspace w;
+  hipStream_t cs = nullptr;        // the capture stream
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  hipEvent_t done = nullptr;       // recorded after each launch
+  hipStream_t last = nullptr;
+  bool launched = false;
+  LastCall lc;                     // what its statistics read
+};
+
 namespace {
 
 // Buffers of tsqs_sort_records per device: the index (the sorted "pointer array"),
@@ -1012,6 +1027,124 @@ int tsqs_sort_batch(void *d_keys, uint32_t *d_vals, const uint64_t *h_offsets, s
   if (max_root <= 1) return TSQS_OK;
   if (!d_keys) return TSQS_EINVAL;
   return dispatch(d_keys, d_vals, h_offsets, nseg, total, max_root, dt, (hipStream_t)stream);
+}
+
+int tsqs_graph_create(void *d_keys, uint32_t *d_vals, size_t nmemb, const uint64_t *h_offsets,
+                      size_t nseg, int dt, tsqs_graph_t **out) {
+  if (!out) return TSQS_EINVAL;
+  *out = nullptr;
+  if (!dtype_ok(dt)) return TSQS_EUNSUPPORTED;
+  if (!d_keys) return TSQS_EINVAL;
+  uint64_t n = nmemb, max_root = nmemb;
+  size_t nroots = 1;
+  if (h_offsets) {
+    if (nseg == 0 || nseg >= (1ull << 24) || h_offsets[0] != 0) return TSQS_EINVAL;
+    max_root = 0;
+    for (size_t j = 0; j < nseg; j++) {
+      if (h_offsets[j + 1] < h_offsets[j]) return TSQS_EINVAL;
+      const uint64_t len = h_offsets[j + 1] - h_offsets[j];
+      if (len > 0xFFFFFFFFull) return TSQS_EINVAL;
+      if (len > max_root) max_root = len;
+    }
+    if (h_offsets[nseg] != nmemb) return TSQS_EINVAL;
+    nroots = nseg;
+  } else if (nmemb > 0xFFFFFFFFull) {
+    return TSQS_EINVAL;
+  }
+  if (n < 2 || max_root < 2) return TSQS_EINVAL;   // nothing to sort: no graph
+  const size_t kb = dt_bytes(dt);
+  if (((uintptr_t)d_keys % kb) != 0 || ((uintptr_t)d_vals % 4) != 0) return TSQS_EINVAL;
+  tsqs_graph *g = new (std::nothrow) tsqs_graph();
+  if (!g) return TSQS_ENOMEM;
+  auto fail = [&](int code) {
+    if (g->cs) (void)hipStreamSynchronize(g->cs);
+    if (g->exec) (void)hipGraphExecDestroy(g->exec);
+    if (g->graph) (void)hipGraphDestroy(g->graph);
+    if (g->done) (void)hipEventDestroy(g->done);
+    free_ws(g->w);
+    if (g->cs) (void)hipStreamDestroy(g->cs);
+    delete g;
+    (void)hipGetLastError();
+    return code;
+  };
+  std::lock_guard<std::mutex> lk(g_mu);
+  if (hipGetDevice(&g->dev) != hipSuccess) return fail(TSQS_EDEVICE);
+  if (hipStreamCreateWithFlags(&g->cs, hipStreamNonBlocking) != hipSuccess) return fail(TSQS_EDEVICE);
+  if (hipEventCreateWithFlags(&g->done, hipEventDisableTiming) != hipSuccess) return fail(TSQS_EDEVICE);
+  // buffers and their first clears, then the offsets, before the capture starts
+  int rc = ensure_static(g->w, g->dev, g->cs);
+  if (rc != TSQS_OK) return fail(rc);
+  const bool hv = d_vals != nullptr;
+  const FinGeom geo = geom_any(dt, g->w.lds_budget, hv);
+  const WsNeed nd = ws_need(n, nroots, kb, hv, geo.small_max, h_offsets != nullptr);
+  CallEnv env;
+  if ((rc = ws_grow(g->w, nd, hv, &env.v, g->cs)) != TSQS_OK) return fail(rc);
+  if (h_offsets &&
+      hipMemcpy(env.v.offs, h_offsets, (nroots + 1) * sizeof(uint64_t), hipMemcpyHostToDevice) != hipSuccess)
+    return fail(TSQS_EDEVICE);
+  if (hipStreamSynchronize(g->cs) != hipSuccess) return fail(TSQS_EDEVICE);
+  env.cus = g->w.cus;
+  env.lds_budget = g->w.lds_budget;
+  env.h_lvl = g->w.h_lvl;
+  env.h_stats = g->w.h_stats;
+  env.ev = nullptr;      // no per-level timing events in a graph
+  env.done = nullptr;    // the launch records the graph's own event
+  CallArgs a;
+  a.keys = d_keys; a.vals = d_vals; a.h_offs = h_offsets; a.nroots = nroots; a.n = n;
+  a.max_root = max_root; a.s = g->cs; a.offs_ready = true;
+  const LastCall saved = g_last;
+  if (hipStreamBeginCapture(g->cs, hipStreamCaptureModeThreadLocal) != hipSuccess) return fail(TSQS_EDEVICE);
+  rc = sort_any(dt, env, a);
+  g->lc = g_last;
+  g_last = saved;
+  hipGraph_t graph = nullptr;
+  const hipError_t e = hipStreamEndCapture(g->cs, &graph);
+  g->graph = graph;
+  if (rc != TSQS_OK) return fail(rc);
+  if (e != hipSuccess || !graph) return fail(TSQS_EDEVICE);
+  if (hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0) != hipSuccess) return fail(TSQS_EDEVICE);
+  g->lc.done = g->done;
+  g->lc.ev = nullptr;
+  *out = g;
+  return TSQS_OK;
+}
+
+int tsqs_graph_launch(tsqs_graph_t *g, void *stream) {
+  if (!g) return TSQS_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  // launches of one graph share its buffers: a launch on another stream starts
+  // after the previous one
+  if (g->launched && g->last != s) HIPCHK(hipStreamWaitEvent(s, g->done, 0));
+  HIPCHK(hipGraphLaunch(g->exec, s));
+  HIPCHK(hipEventRecord(g->done, s));
+  g->last = s;
+  g->launched = true;
+  return TSQS_OK;
+}
+
+int tsqs_graph_stats(tsqs_graph_t *g, tsqs_stats_t *out) {
+  if (!g || !out) return TSQS_EINVAL;
+  if (!g->launched) return TSQS_EINVAL;
+  std::lock_guard<std::mutex> lk(g_mu);
+  const LastCall saved = g_last;
+  g_last = g->lc;
+  g_last.s = g->last;
+  const int rc = stats_of_last(out);
+  g_last = saved;
+  return rc;
+}
+
+int tsqs_graph_destroy(tsqs_graph_t *g) {
+  if (!g) return TSQS_EINVAL;
+  int rc = TSQS_OK;
+  if (g->launched && hipEventSynchronize(g->done) != hipSuccess) rc = TSQS_EDEVICE;
+  if (g->exec) (void)hipGraphExecDestroy(g->exec);
+  if (g->graph) (void)hipGraphDestroy(g->graph);
+  if (g->done) (void)hipEventDestroy(g->done);
+  free_ws(g->w);
+  if (g->cs) (void)hipStreamDestroy(g->cs);
+  delete g;
+  return rc;
 }
 
 void tsqs_free_storage(void) {

@@ -160,6 +160,7 @@ struct CallArgs {
   uint64_t n = 0;
   uint64_t max_root = 0;
   hipStream_t s = nullptr;
+  bool offs_ready = false;           // the batch offsets are already in the workspace
 };
 
 extern Options g_opt;

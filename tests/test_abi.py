@@ -85,6 +85,29 @@ def test_batch_argument_errors(lib):
     assert lib.tsqs_sort_batch(fake, None, p, 1, 7, None) == -4
 
 
+def test_graph_argument_errors(lib):
+    """tsqs_graph_*: every argument error returns before any HIP call."""
+    fake = ctypes.c_void_p(0x1000)
+    out = ctypes.c_void_p()
+    ref = ctypes.byref(out)
+    assert lib.tsqs_graph_create(fake, None, 100, None, 0, 0, None) == -1      # no out
+    assert lib.tsqs_graph_create(fake, None, 100, None, 0, 7, ref) == -4       # dtype
+    assert lib.tsqs_graph_create(None, None, 100, None, 0, 0, ref) == -1       # no keys
+    assert lib.tsqs_graph_create(fake, None, 1, None, 0, 0, ref) == -1         # nothing to sort
+    assert lib.tsqs_graph_create(fake, None, 1 << 32, None, 0, 0, ref) == -1   # too long
+    assert lib.tsqs_graph_create(ctypes.c_void_p(0x1002), None, 100, None, 0, 0, ref) == -1  # alignment
+    p, keep = _offs([0, 5, 3])
+    assert lib.tsqs_graph_create(fake, None, 3, p, 2, 0, ref) == -1            # decreasing
+    p, keep = _offs([0, 5, 9])
+    assert lib.tsqs_graph_create(fake, None, 10, p, 2, 0, ref) == -1           # total != nmemb
+    p, keep = _offs([0, 1, 2])
+    assert lib.tsqs_graph_create(fake, None, 2, p, 2, 0, ref) == -1            # arrays <= 1
+    assert not out.value
+    assert lib.tsqs_graph_launch(None, None) == -1
+    assert lib.tsqs_graph_stats(None, None) == -1
+    assert lib.tsqs_graph_destroy(None) == -1
+
+
 def test_options(lib):
     import paper_1505_00558_amd as tsqs
     old = tsqs.get_option(tsqs.OPT_SMALL_MAX)
