@@ -112,9 +112,13 @@ enum {
   TSQS_OPT_PART_THREADS1 = 14, /* workgroup size of the one-level partition kernel: 512
                                 (default; 32 4-byte keys per thread) or 1024 (16 per
                                 thread); a chunk is the same 16384 keys either way */
-  TSQS_OPT_PART_THREADS2 = 15  /* workgroup size of the two-level partition kernel: 256
+  TSQS_OPT_PART_THREADS2 = 15, /* workgroup size of the two-level partition kernel: 256
                                 (default; 32 4-byte keys per thread) or 512 (16 per
                                 thread); a chunk is the same 8192 keys either way */
+  TSQS_OPT_WORKSPACE_CAP = 16  /* bytes the per-device workspace of the sort calls may
+                                hold (0 = no cap, the default); a call that would grow
+                                it past the cap returns TSQS_ENOMEM before it allocates,
+                                frees or launches anything (the keys are untouched) */
 };
 
 #define TSQS_MAX_LEVELS 192

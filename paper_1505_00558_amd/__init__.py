@@ -24,7 +24,7 @@ NOALLOC_SCRATCH_BYTES = 32 << 20
 OPT_SMALL_MAX, OPT_SAMPLES, OPT_DEPTH_FACTOR, OPT_PIVOT_MODE = 1, 2, 3, 4
 OPT_SEED, OPT_TIMING, OPT_PART_GRID, OPT_FINISH_GRID, OPT_FINISH_ALGO = 5, 6, 7, 8, 9
 OPT_PRESORT, OPT_SCHEDULE, OPT_ITER_CAP, OPT_QUEUE_DIRECT = 10, 11, 12, 13
-OPT_PART_THREADS1, OPT_PART_THREADS2 = 14, 15
+OPT_PART_THREADS1, OPT_PART_THREADS2, OPT_WORKSPACE_CAP = 14, 15, 16
 SCHEDULE_LEVELS, SCHEDULE_PERSISTENT = 0, 1
 MAX_LEVELS = 192
 
@@ -34,7 +34,7 @@ SYMBOLS = ["tsqs_sort", "tsqs_sort_pairs", "tsqs_sort_noalloc", "tsqs_sort_recor
            "tsqs_graph_stats", "tsqs_graph_destroy"]
 QUEUE_SYMBOLS = ["tsqs_queue_open", "tsqs_queue_submit", "tsqs_queue_step", "tsqs_queue_poll",
                  "tsqs_queue_result", "tsqs_queue_reap", "tsqs_queue_release",
-                 "tsqs_queue_info", "tsqs_queue_close"]
+                 "tsqs_queue_cancel", "tsqs_queue_info", "tsqs_queue_close"]
 
 
 class Stats(ctypes.Structure):
@@ -160,6 +160,7 @@ def load_library():
                                       ctypes.POINTER(sz)]
     lib.tsqs_queue_reap.argtypes = [vp, vp, sz, ctypes.POINTER(sz)]
     lib.tsqs_queue_release.argtypes = [vp, ctypes.c_uint64]
+    lib.tsqs_queue_cancel.argtypes = [vp, ctypes.c_uint64]
     lib.tsqs_queue_info.argtypes = [vp, u64p, u64p, u64p, u64p, u64p]
     lib.tsqs_queue_close.argtypes = [vp]
     for name in QUEUE_SYMBOLS:
@@ -448,6 +449,16 @@ class Queue:
     def release(self, ticket: int) -> None:
         _check(self._lib.tsqs_queue_release(self._q, int(ticket)))
         self._keep.pop(int(ticket), None)
+
+    def cancel(self, ticket: int) -> bool:
+        """Drop a queued request (or release a done one): True; False if it is
+        running (release it when done)."""
+        rc = self._lib.tsqs_queue_cancel(self._q, int(ticket))
+        if rc == EAGAIN:
+            return False
+        _check(rc)
+        self._keep.pop(int(ticket), None)
+        return True
 
     def info(self) -> dict:
         v = [ctypes.c_uint64() for _ in range(5)]

@@ -105,9 +105,29 @@ int ws_quiesce(Workspace &w) {
   return TSQS_OK;
 }
 
-// Workspace buffers of the allocating entry points, grown to what the call needs.
+// Device bytes the workspace holds once grown to what nd needs.
+size_t ws_bytes_after(const Workspace &w, const WsNeed &nd, bool hasv) {
+  auto mx = [](size_t a, size_t b) { return a > b ? a : b; };
+  size_t t = mx(w.s_bytes, nd.s_bytes);
+  if (hasv || w.v_cap) t += 2 * mx(w.v_cap, hasv ? nd.v_elems : 0) * sizeof(uint32_t);
+  const size_t seg = mx(w.seg_cap, nd.seg_cap);
+  t += 2 * seg * (sizeof(Seg) + kCtrStride * sizeof(unsigned long long));
+  t += 2 * mx(w.slot_cap, nd.slot_cap) * sizeof(FinItem);
+  t += (mx(w.band_cap, nd.band_cap) + mx(w.big_cap, nd.big_cap)) * sizeof(FinItem);
+  t += mx(w.off_cap, nd.offs) * sizeof(uint64_t);
+  t += mx(w.qcap, nd.qcap) * (sizeof(Task) + sizeof(unsigned long long));
+  t += mx(w.part_cap, nd.part_cap) * (sizeof(TPart) + kCtrStride * sizeof(unsigned long long));
+  t += mx(w.hist_cap, nd.hist_cap) * 256 * sizeof(uint32_t);
+  t += (mx(w.lband_cap, nd.lband_cap) + mx(w.sfin_cap, nd.sfin_cap)) * sizeof(FinItem);
+  return t;
+}
+
+// Workspace buffers of the allocating entry points, grown to what the call needs
+// (TSQS_ENOMEM, with nothing allocated or freed, past TSQS_OPT_WORKSPACE_CAP).
 int ws_grow(Workspace &w, const WsNeed &nd, bool hasv, WsView *v, hipStream_t s) {
   int rc;
+  if (g_opt.workspace_cap > 0 && ws_bytes_after(w, nd, hasv) > (size_t)g_opt.workspace_cap)
+    return TSQS_ENOMEM;
   const bool grows = w.s_bytes < nd.s_bytes || (hasv && w.v_cap < nd.v_elems) || w.seg_cap < nd.seg_cap ||
                      w.slot_cap < nd.slot_cap || w.band_cap < nd.band_cap || w.big_cap < nd.big_cap ||
                      (nd.offs && w.off_cap < nd.offs) || w.qcap < nd.qcap || w.part_cap < nd.part_cap ||
@@ -754,6 +774,31 @@ int tsqs_queue_release(tsqs_queue_t *q, uint64_t ticket) {
   return TSQS_OK;
 }
 
+int tsqs_queue_cancel(tsqs_queue_t *q, uint64_t ticket) {
+  if (!q) return TSQS_EINVAL;
+  std::lock_guard<std::mutex> lk(q->mu);
+  auto it = q->reqs.find(ticket);
+  if (it == q->reqs.end()) return TSQS_EINVAL;
+  QReq &r = it->second;
+  if (r.state == 1) return TSQS_EAGAIN;        // its device work is enqueued
+  if (r.state == 2) {
+    // done: the same as a release (a one-key request may wait in the reap list)
+    if (r.n > 1) {
+      arena_give(q, r.boff, r.bytes);
+      if (!r.direct) q->free_ids.push_back(r.id);
+    }
+    for (auto p = q->reap.begin(); p != q->reap.end(); ++p)
+      if (*p == ticket) { q->reap.erase(p); break; }
+    q->n_done--;
+    q->reqs.erase(it);
+    return TSQS_OK;
+  }
+  for (auto p = q->pending.begin(); p != q->pending.end(); ++p)
+    if (*p == ticket) { q->pending.erase(p); break; }
+  q->reqs.erase(it);
+  return TSQS_OK;
+}
+
 int tsqs_queue_info(tsqs_queue_t *q, uint64_t *queued, uint64_t *running, uint64_t *done,
                     uint64_t *arena_used, uint64_t *arena_bytes) {
   if (!q) return TSQS_EINVAL;
@@ -1189,6 +1234,7 @@ int tsqs_set_option(int key, int64_t v) {
     case TSQS_OPT_QUEUE_DIRECT: if (v < 0 || v > 0xFFFFFFFFll) return TSQS_EINVAL; g_opt.queue_direct = v; return TSQS_OK;
     case TSQS_OPT_PART_THREADS1: if (v != kPartNT1 && v != 2 * kPartNT1) return TSQS_EINVAL; g_opt.part_threads1 = v; return TSQS_OK;
     case TSQS_OPT_PART_THREADS2: if (v != kPartNT2 && v != 2 * kPartNT2) return TSQS_EINVAL; g_opt.part_threads2 = v; return TSQS_OK;
+    case TSQS_OPT_WORKSPACE_CAP: if (v < 0) return TSQS_EINVAL; g_opt.workspace_cap = v; return TSQS_OK;
     default: return TSQS_EUNSUPPORTED;
   }
 }
@@ -1211,6 +1257,7 @@ int64_t tsqs_get_option(int key) {
     case TSQS_OPT_QUEUE_DIRECT: return g_opt.queue_direct;
     case TSQS_OPT_PART_THREADS1: return g_opt.part_threads1;
     case TSQS_OPT_PART_THREADS2: return g_opt.part_threads2;
+    case TSQS_OPT_WORKSPACE_CAP: return g_opt.workspace_cap;
     default: return INT64_MIN;
   }
 }

@@ -52,6 +52,7 @@ struct Options {
   int64_t queue_direct = 1 << 22;   // TSQS_OPT_QUEUE_DIRECT
   int64_t part_threads1 = kPartNT1;  // TSQS_OPT_PART_THREADS1
   int64_t part_threads2 = kPartNT2;  // TSQS_OPT_PART_THREADS2
+  int64_t workspace_cap = 0;         // TSQS_OPT_WORKSPACE_CAP (bytes, 0: none)
 };
 
 constexpr unsigned long long kDefaultIterCap = 1ull << 23;

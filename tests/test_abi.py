@@ -147,6 +147,11 @@ def test_options(lib):
             for v in ok[::-1]:
                 assert lib.tsqs_set_option(key, v) == 0
                 assert tsqs.get_option(key) == v
+        assert tsqs.get_option(tsqs.OPT_WORKSPACE_CAP) == 0
+        assert lib.tsqs_set_option(tsqs.OPT_WORKSPACE_CAP, -1) == -1
+        assert lib.tsqs_set_option(tsqs.OPT_WORKSPACE_CAP, 1 << 20) == 0
+        assert tsqs.get_option(tsqs.OPT_WORKSPACE_CAP) == 1 << 20
+        assert lib.tsqs_set_option(tsqs.OPT_WORKSPACE_CAP, 0) == 0
         assert lib.tsqs_set_option(999, 1) == -4
         assert tsqs.get_option(999) == -(1 << 63)
     finally:
@@ -184,6 +189,7 @@ def test_queue_argument_errors(lib):
     assert lib.tsqs_queue_poll(None, 1) == -1
     assert lib.tsqs_queue_result(None, 1, None, None) == -1
     assert lib.tsqs_queue_release(None, 1) == -1
+    assert lib.tsqs_queue_cancel(None, 1) == -1
     assert lib.tsqs_queue_reap(None, None, 0, None) == -1
     assert lib.tsqs_queue_info(None, None, None, None, None, None) == -1
     assert lib.tsqs_queue_close(None) == -1

@@ -199,3 +199,58 @@ def test_queue_direct_keeps_caller_stats(direct_min):
     assert bool(torch.equal(again, torch.sort(ti.device_family("organ_pipe", 70001, "int32", seed=78)).values))
     assert bool(torch.equal(mine, ref))
     q.close()
+
+
+def test_queue_cancel(oracle_mod):
+    """A queued request can be cancelled (never admitted; the rest of the queue
+    completes as before); a running one cannot (TSQS_EAGAIN); a done one is
+    released; a cancelled ticket is unknown afterwards."""
+    import paper_1505_00558_amd as tsqs
+    q = tsqs.Queue(256 << 20)
+    cap = q.info()["arena_bytes"]
+    n = (cap // 4) // 3 - 64                            # three int32 requests fill the arena
+    arrs = [ti.family(f, n, "int32", seed=60 + j) for j, f in
+            enumerate(["uniform", "organ_pipe", "many_equals", "stair_steps", "uniform"])]
+    srcs = [to_dev(a) for a in arrs]
+    tks = [q.submit(t) for t in srcs]
+    q.step()
+    assert q.poll(tks[3]) == q.QUEUED and q.poll(tks[0]) == q.RUNNING
+    assert q.cancel(tks[3])                             # queued: dropped
+    with pytest.raises(tsqs.TsqsError):
+        q.poll(tks[3])
+    assert not q.cancel(tks[0])                         # running: not cancelled
+    _drain(q, tks[:3])
+    assert q.cancel(tks[2])                             # done: released
+    for tk, a in zip(tks[:2], arrs[:2]):
+        assert same_bits(from_dev(q.result(tk).clone(), np.int32), oracle_mod.sort(a))
+        q.release(tk)
+    _drain(q, [tks[4]])
+    assert same_bits(from_dev(q.result(tks[4]).clone(), np.int32), oracle_mod.sort(arrs[4]))
+    q.release(tks[4])
+    info = q.info()
+    assert info["queued"] == 0 and info["running"] == 0 and info["arena_used"] == 0
+    q.close()
+
+
+def test_workspace_cap_reports_enomem(oracle_mod):
+    """TSQS_OPT_WORKSPACE_CAP: a sort that would grow the workspace past the cap
+    returns TSQS_ENOMEM without touching the keys; under the cap, or with it
+    lifted, the same sort succeeds."""
+    import paper_1505_00558_amd as tsqs
+    import torch
+    tsqs.free_storage()                                 # start from an empty workspace
+    k = ti.family("uniform", 1 << 22, "int32", seed=71)
+    t = to_dev(k)
+    tsqs.set_option(tsqs.OPT_WORKSPACE_CAP, 4 << 20)    # far below the 16 MiB scratch copy
+    try:
+        with pytest.raises(tsqs.TsqsError) as e:
+            tsqs.sort(t)
+        assert "-2" in str(e.value)
+        torch.cuda.synchronize()
+        assert same_bits(from_dev(t, np.int32), k)      # untouched
+        tsqs.set_option(tsqs.OPT_WORKSPACE_CAP, 256 << 20)
+        tsqs.sort(t)
+        torch.cuda.synchronize()
+        assert same_bits(from_dev(t, np.int32), oracle_mod.sort(k))
+    finally:
+        tsqs.set_option(tsqs.OPT_WORKSPACE_CAP, 0)
