@@ -115,10 +115,25 @@ enum {
   TSQS_OPT_PART_THREADS2 = 15, /* workgroup size of the two-level partition kernel: 256
                                 (default; 32 4-byte keys per thread) or 512 (16 per
                                 thread); a chunk is the same 8192 keys either way */
-  TSQS_OPT_WORKSPACE_CAP = 16  /* bytes the per-device workspace of the sort calls may
+  TSQS_OPT_WORKSPACE_CAP = 16, /* bytes the per-device workspace of the sort calls may
                                 hold (0 = no cap, the default); a call that would grow
                                 it past the cap returns TSQS_ENOMEM before it allocates,
                                 frees or launches anything (the keys are untouched) */
+  TSQS_OPT_DEBUG = 17        /* 1 = debug shadows for tsqs_sort / _pairs / _batch /
+                                _records and graphs created while on (3 n words more
+                                workspace, no presortedness check): every store of a
+                                partition pass is checked to land on a slot that no
+                                other key of the same part's pass took (the chunk
+                                reservations are disjoint) and that is not final; every
+                                slot of the keys receives its final key exactly once (a
+                                band or a small part), and all of them do.  A violation
+                                sets TSQS_ERR_SHADOW in tsqs_stats_t.error_flags
+                                (tsqs_get_stats returns TSQS_EINTERNAL).  0 = off
+                                (default).  2 and 3 are test modes of the checks: as
+                                1, with one shadow entry planted before the sort (slot
+                                0 of the keys already final / slot 0 of the scratch
+                                copy already stored by the root's pass), so that a
+                                correct sort reports TSQS_ERR_SHADOW */
 };
 
 #define TSQS_MAX_LEVELS 192
@@ -146,9 +161,18 @@ typedef struct {
   uint64_t tail_keys;            /* keys of those parts */
   uint64_t tail_bytes;           /* their algorithmic bytes, 2 * keys * (key+payload bytes) */
   uint64_t select_rounds;        /* radix digits fixed by grid-wide exact-pivot selection */
-  uint32_t error_flags;          /* device error bits of the call (0 = none) */
+  uint32_t error_flags;          /* device error bits of the call (0 = none; TSQS_ERR_*) */
   uint32_t schedule;             /* TSQS_OPT_SCHEDULE of the call */
 } tsqs_stats_t;
+
+/* Bits of tsqs_stats_t.error_flags. */
+#define TSQS_ERR_SEG_CAP 1u     /* a level's part table was full */
+#define TSQS_ERR_FIN_CAP 2u     /* a small-part or band table was full */
+#define TSQS_ERR_LEVEL 4u       /* more levels than the level table holds */
+#define TSQS_ERR_COUNT 8u       /* class counts that do not fit their part */
+#define TSQS_ERR_QUEUE 16u      /* persistent schedule: task ring or part pool full */
+#define TSQS_ERR_ITER 32u       /* persistent schedule: iteration cap reached */
+#define TSQS_ERR_SHADOW 128u    /* TSQS_OPT_DEBUG: a shadow check failed */
 
 /* Sort nmemb keys of type dt at device pointer d_keys, in place (the paper's
  * problem statement, abstract and SVII).  nmemb <= 1 is a no-op.  nmemb must

@@ -24,7 +24,8 @@ NOALLOC_SCRATCH_BYTES = 32 << 20
 OPT_SMALL_MAX, OPT_SAMPLES, OPT_DEPTH_FACTOR, OPT_PIVOT_MODE = 1, 2, 3, 4
 OPT_SEED, OPT_TIMING, OPT_PART_GRID, OPT_FINISH_GRID, OPT_FINISH_ALGO = 5, 6, 7, 8, 9
 OPT_PRESORT, OPT_SCHEDULE, OPT_ITER_CAP, OPT_QUEUE_DIRECT = 10, 11, 12, 13
-OPT_PART_THREADS1, OPT_PART_THREADS2, OPT_WORKSPACE_CAP = 14, 15, 16
+OPT_PART_THREADS1, OPT_PART_THREADS2, OPT_WORKSPACE_CAP, OPT_DEBUG = 14, 15, 16, 17
+ERR_SHADOW = 128
 SCHEDULE_LEVELS, SCHEDULE_PERSISTENT = 0, 1
 MAX_LEVELS = 192
 

@@ -30,6 +30,13 @@ namespace {
 // keys each).
 template <int DT, bool HASV, bool WIDE>
 void launch_pass(const Ctx &c, int d, bool two, int grid, hipStream_t s) {
+  if (c.dbg) {
+    // debug shadows: the checking instances, at the default workgroup sizes
+    hipLaunchKernelGGL((k_partition<DT, HASV, WIDE, false, 1, true>), dim3(grid), dim3(kPartNT1), 0, s, c, d);
+    if (two)
+      hipLaunchKernelGGL((k_partition<DT, HASV, WIDE, true, 1, true>), dim3(grid), dim3(kPartNT2), 0, s, c, d);
+    return;
+  }
   if (g_opt.part_threads1 == 2 * kPartNT1)
     hipLaunchKernelGGL((k_partition<DT, HASV, WIDE, false, 2>), dim3(grid), dim3(2 * kPartNT1), 0, s, c, d);
   else
@@ -43,7 +50,9 @@ void launch_pass(const Ctx &c, int d, bool two, int grid, hipStream_t s) {
 
 template <int DT, bool HASV>
 int launch_finish(const Ctx &c, int d, int grid, size_t lds, hipStream_t s) {
-  if (g_opt.finish_algo == 0)
+  if (c.dbg)   // debug shadows: the checking instance of the default algorithm
+    hipLaunchKernelGGL((k_finish<DT, HASV, 3, true>), dim3(grid), dim3(kFinNT), lds, s, c, d);
+  else if (g_opt.finish_algo == 0)
     hipLaunchKernelGGL((k_finish<DT, HASV, 0>), dim3(grid), dim3(kFinNT), lds, s, c, d);
   else if (g_opt.finish_algo == 1)
     hipLaunchKernelGGL((k_finish<DT, HASV, 1>), dim3(grid), dim3(kFinNT), lds, s, c, d);
@@ -56,17 +65,17 @@ int launch_finish(const Ctx &c, int d, int grid, size_t lds, hipStream_t s) {
 
 // Workgroups of the persistent kernel: as many as fit on the device at once
 // (it needs no more, and no co-residency).
-template <int DT, bool HASV, bool WIDE>
+template <int DT, bool HASV, bool WIDE, bool DBG>
 int persist_grid(int cus, size_t lds) {
   static int per_cu = -1;
   static size_t per_cu_lds = 0;
   if (per_cu < 0 || per_cu_lds != lds) {
-    if (lds > 65536 && hipFuncSetAttribute((const void *)k_persist<DT, HASV, WIDE>,
+    if (lds > 65536 && hipFuncSetAttribute((const void *)k_persist<DT, HASV, WIDE, DBG>,
                                            hipFuncAttributeMaxDynamicSharedMemorySize,
                                            (int)lds) != hipSuccess)
       return -1;
     int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_persist<DT, HASV, WIDE>, kPNT, lds) != hipSuccess)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_persist<DT, HASV, WIDE, DBG>, kPNT, lds) != hipSuccess)
       return -1;
     per_cu = nb > 0 ? nb : 1;
     per_cu_lds = lds;
@@ -102,7 +111,10 @@ int run_t(const CallEnv &env, const CallArgs &a) {
   c.stats = w.stats;
   c.err = (unsigned int *)(w.stats + kStripes * kStatWords);
   // the presortedness check of a single array that needs a pass
-  c.pre = (g_opt.presort && !h_offs && n > small_max)
+  // debug shadows: every key takes the passes (no presortedness check), and
+  // every store is checked against the shadows
+  c.dbg = w.dbg;
+  c.pre = (g_opt.presort && !c.dbg && !h_offs && n > small_max)
               ? (unsigned int *)(w.stats + kStripes * kStatWords + 8) : nullptr;
   c.roots = h_offs ? w.offs : nullptr;
   c.root_recs = nullptr;
@@ -119,7 +131,7 @@ int run_t(const CallEnv &env, const CallArgs &a) {
   c.nroots = (uint32_t)nroots;
   c.small_max = small_max;
   c.wave_max = wave_max;
-  c.presort_roots = (g_opt.presort && h_offs) ? 1u : 0u;   // batches: each array by its wave
+  c.presort_roots = (g_opt.presort && !c.dbg && h_offs) ? 1u : 0u;   // batches: each array by its wave
   c.samples = (uint32_t)g_opt.samples;
   c.depth_factor = (uint32_t)g_opt.depth_factor;
   c.pivot_mode = (uint32_t)g_opt.pivot_mode;
@@ -130,7 +142,10 @@ int run_t(const CallEnv &env, const CallArgs &a) {
   // 32-bit byte offsets within a part suffice unless a part reaches 4 GiB
   const bool wide = (uint64_t)max_root * sizeof(typename Codec<DT>::B) > 0xFFFFFFFFull;
   const size_t plds = persist_lds<DT, HASV>();
-  const int pgrid = wide ? persist_grid<DT, HASV, true>(env.cus, plds) : persist_grid<DT, HASV, false>(env.cus, plds);
+  const int pgrid = c.dbg ? (wide ? persist_grid<DT, HASV, true, true>(env.cus, plds)
+                                  : persist_grid<DT, HASV, false, true>(env.cus, plds))
+                          : (wide ? persist_grid<DT, HASV, true, false>(env.cus, plds)
+                                  : persist_grid<DT, HASV, false, false>(env.cus, plds));
   if (pgrid <= 0) return TSQS_EDEVICE;
   c.p.task = w.task; c.p.seq = w.seq; c.p.ctl = w.ctl;
   c.p.parts = w.parts; c.p.pctr = w.pctr; c.p.hist = w.hist; c.p.bands = w.bands;
@@ -165,12 +180,20 @@ int run_t(const CallEnv &env, const CallArgs &a) {
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)fin_lds));
     HIPCHK(hipFuncSetAttribute((const void *)k_finish_list<DT, HASV, 3>,
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)fin_lds));
+    if (c.dbg) {
+      HIPCHK(hipFuncSetAttribute((const void *)k_finish<DT, HASV, 3, true>,
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)fin_lds));
+      HIPCHK(hipFuncSetAttribute((const void *)k_finish_list<DT, HASV, 3, true>,
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)fin_lds));
+    }
   }
   const size_t waves_init = (nroots + kPlanNW - 1) / kPlanNW;
   int init_grid = (int)(waves_init < (size_t)(4 * env.cus) ? waves_init : (size_t)(4 * env.cus));
   if (init_grid < 1) init_grid = 1;
 
   hipLaunchKernelGGL(k_reset, dim3(1), dim3(256), 0, s, c);
+  if (c.dbg) hipLaunchKernelGGL(k_dbg_clear, dim3(4 * env.cus), dim3(256), 0, s, c);
+  if (c.dbg && g_opt.debug >= 2) hipLaunchKernelGGL(k_dbg_plant, dim3(1), dim3(64), 0, s, c, (int)g_opt.debug);
   if (c.pre) {
     const uint64_t pre_chunks = (n + (uint64_t)kPreNT * kPreRows - 1) / ((uint64_t)kPreNT * kPreRows);
     const int scan_grid = (int)(pre_chunks < (uint64_t)(8 * env.cus) ? pre_chunks : (uint64_t)(8 * env.cus));
@@ -213,13 +236,19 @@ int run_t(const CallEnv &env, const CallArgs &a) {
   }
   const int seed_grid = 4 * env.cus;
   hipLaunchKernelGGL((k_seed<DT, HASV>), dim3(seed_grid), dim3(kPlanNT), 0, s, c, (int)expected);
-  if (wide)
+  if (c.dbg && wide)
+    hipLaunchKernelGGL((k_persist<DT, HASV, true, true>), dim3(c.p.grid), dim3(kPNT), plds, s, c);
+  else if (c.dbg)
+    hipLaunchKernelGGL((k_persist<DT, HASV, false, true>), dim3(c.p.grid), dim3(kPNT), plds, s, c);
+  else if (wide)
     hipLaunchKernelGGL((k_persist<DT, HASV, true>), dim3(c.p.grid), dim3(kPNT), plds, s, c);
   else
     hipLaunchKernelGGL((k_persist<DT, HASV, false>), dim3(c.p.grid), dim3(kPNT), plds, s, c);
   HIPCHK(hipGetLastError());
   // the small parts the persistent kernel listed
-  if (g_opt.finish_algo == 0)
+  if (c.dbg)
+    hipLaunchKernelGGL((k_finish_list<DT, HASV, 3, true>), dim3(fin_grid), dim3(kFinNT), fin_lds, s, c);
+  else if (g_opt.finish_algo == 0)
     hipLaunchKernelGGL((k_finish_list<DT, HASV, 0>), dim3(fin_grid), dim3(kFinNT), fin_lds, s, c);
   else if (g_opt.finish_algo == 1)
     hipLaunchKernelGGL((k_finish_list<DT, HASV, 1>), dim3(fin_grid), dim3(kFinNT), fin_lds, s, c);
@@ -227,6 +256,7 @@ int run_t(const CallEnv &env, const CallArgs &a) {
     hipLaunchKernelGGL((k_finish_list<DT, HASV, 2>), dim3(fin_grid), dim3(kFinNT), fin_lds, s, c);
   else
     hipLaunchKernelGGL((k_finish_list<DT, HASV, 3>), dim3(fin_grid), dim3(kFinNT), fin_lds, s, c);
+  if (c.dbg) hipLaunchKernelGGL(k_dbg_end, dim3(4 * env.cus), dim3(256), 0, s, c);
   HIPCHK(hipGetLastError());
   if (env.done) HIPCHK(hipEventRecord(env.done, s));
 
@@ -292,6 +322,7 @@ int queue_tick(tsqs_queue *q, QGroup &G) {
   c.done_cap = kQMaxReq;
   c.fin_roots_only = 0;
   c.p = PCtx();
+  c.dbg = nullptr;
   c.root_level = d;
   c.ring = 1;
   c.n = 0;

@@ -76,6 +76,7 @@ void free_ws(Workspace &w) {
   (void)hipFree(w.task); (void)hipFree(w.seq); (void)hipFree(w.ctl);
   (void)hipFree(w.parts); (void)hipFree(w.pctr); (void)hipFree(w.hist); (void)hipFree(w.bands);
   (void)hipFree(w.sfin);
+  (void)hipFree(w.dbg);
   if (w.done) (void)hipEventDestroy(w.done);
   w = Workspace();
 }
@@ -119,6 +120,7 @@ size_t ws_bytes_after(const Workspace &w, const WsNeed &nd, bool hasv) {
   t += mx(w.part_cap, nd.part_cap) * (sizeof(TPart) + kCtrStride * sizeof(unsigned long long));
   t += mx(w.hist_cap, nd.hist_cap) * 256 * sizeof(uint32_t);
   t += (mx(w.lband_cap, nd.lband_cap) + mx(w.sfin_cap, nd.sfin_cap)) * sizeof(FinItem);
+  t += mx(w.dbg_cap, nd.dbg) * sizeof(unsigned int);
   return t;
 }
 
@@ -184,6 +186,7 @@ int ws_grow(Workspace &w, const WsNeed &nd, bool hasv, WsView *v, hipStream_t s)
   }
   if ((rc = grow(&w.bands, &w.lband_cap, nd.lband_cap)) != TSQS_OK) return rc;
   if ((rc = grow(&w.sfin, &w.sfin_cap, nd.sfin_cap)) != TSQS_OK) return rc;
+  if (nd.dbg && (rc = grow(&w.dbg, &w.dbg_cap, nd.dbg)) != TSQS_OK) return rc;
   if (g_opt.timing && !w.ev_ok) {
     for (int i = 0; i < 2 * kMaxLevels; i++) HIPCHK(hipEventCreate(&w.ev[i]));
     w.ev_ok = true;
@@ -197,6 +200,7 @@ int ws_grow(Workspace &w, const WsNeed &nd, bool hasv, WsView *v, hipStream_t s)
   v->hist = w.hist; v->bands = w.bands; v->sfin = w.sfin;
   v->qcap = w.qcap; v->part_cap = w.part_cap; v->hist_cap = w.hist_cap; v->band_cap = w.lband_cap;
   v->sfin_cap = w.sfin_cap;
+  v->dbg = nd.dbg ? w.dbg : nullptr;
   return TSQS_OK;
 }
 
@@ -239,7 +243,8 @@ int dispatch(void *keys, uint32_t *vals, const uint64_t *h_offs, size_t nroots, 
   if (!dtype_ok(dt)) return TSQS_EUNSUPPORTED;
   const bool hv = vals != nullptr;
   const FinGeom geo = geom_any(dt, w.lds_budget, hv);
-  const WsNeed nd = ws_need(n, nroots, dt_bytes(dt), hv, geo.small_max, h_offs != nullptr);
+  WsNeed nd = ws_need(n, nroots, dt_bytes(dt), hv, geo.small_max, h_offs != nullptr);
+  if (g_opt.debug) nd.dbg = 3 * (size_t)n;
   CallEnv env;
   // one workspace per device: a call on another stream starts after the last one
   if (w.done_rec && w.last_stream != s) HIPCHK(hipStreamWaitEvent(s, w.done, 0));
@@ -1121,7 +1126,8 @@ int tsqs_graph_create(void *d_keys, uint32_t *d_vals, size_t nmemb, const uint64
   if (rc != TSQS_OK) return fail(rc);
   const bool hv = d_vals != nullptr;
   const FinGeom geo = geom_any(dt, g->w.lds_budget, hv);
-  const WsNeed nd = ws_need(n, nroots, kb, hv, geo.small_max, h_offsets != nullptr);
+  WsNeed nd = ws_need(n, nroots, kb, hv, geo.small_max, h_offsets != nullptr);
+  if (g_opt.debug) nd.dbg = 3 * (size_t)n;
   CallEnv env;
   if ((rc = ws_grow(g->w, nd, hv, &env.v, g->cs)) != TSQS_OK) return fail(rc);
   if (h_offsets &&
@@ -1235,6 +1241,7 @@ int tsqs_set_option(int key, int64_t v) {
     case TSQS_OPT_PART_THREADS1: if (v != kPartNT1 && v != 2 * kPartNT1) return TSQS_EINVAL; g_opt.part_threads1 = v; return TSQS_OK;
     case TSQS_OPT_PART_THREADS2: if (v != kPartNT2 && v != 2 * kPartNT2) return TSQS_EINVAL; g_opt.part_threads2 = v; return TSQS_OK;
     case TSQS_OPT_WORKSPACE_CAP: if (v < 0) return TSQS_EINVAL; g_opt.workspace_cap = v; return TSQS_OK;
+    case TSQS_OPT_DEBUG: if (v < 0 || v > 3) return TSQS_EINVAL; g_opt.debug = v; return TSQS_OK;
     default: return TSQS_EUNSUPPORTED;
   }
 }
@@ -1258,6 +1265,7 @@ int64_t tsqs_get_option(int key) {
     case TSQS_OPT_PART_THREADS1: return g_opt.part_threads1;
     case TSQS_OPT_PART_THREADS2: return g_opt.part_threads2;
     case TSQS_OPT_WORKSPACE_CAP: return g_opt.workspace_cap;
+    case TSQS_OPT_DEBUG: return g_opt.debug;
     default: return INT64_MIN;
   }
 }

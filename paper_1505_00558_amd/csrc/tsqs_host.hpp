@@ -53,6 +53,7 @@ struct Options {
   int64_t part_threads1 = kPartNT1;  // TSQS_OPT_PART_THREADS1
   int64_t part_threads2 = kPartNT2;  // TSQS_OPT_PART_THREADS2
   int64_t workspace_cap = 0;         // TSQS_OPT_WORKSPACE_CAP (bytes, 0: none)
+  int64_t debug = 0;                 // TSQS_OPT_DEBUG
 };
 
 constexpr unsigned long long kDefaultIterCap = 1ull << 23;
@@ -78,12 +79,14 @@ struct WsView {
   FinItem *bands = nullptr;
   FinItem *sfin = nullptr;
   size_t qcap = 0, part_cap = 0, hist_cap = 0, band_cap = 0, sfin_cap = 0;
+  unsigned int *dbg = nullptr;          // debug shadows (3 n words), or null
 };
 
 // Element counts a call needs (see ws_need).
 struct WsNeed {
   size_t s_bytes = 0, v_elems = 0, seg_cap = 0, slot_cap = 0, band_cap = 0, big_cap = 0, offs = 0;
   size_t qcap = 0, part_cap = 0, hist_cap = 0, lband_cap = 0, sfin_cap = 0;   // persistent schedule
+  size_t dbg = 0;                      // debug shadow words (TSQS_OPT_DEBUG): 3 n, else 0
 };
 
 // Per-device workspace of the allocating entry points: grows to the largest
@@ -118,6 +121,8 @@ struct Workspace {
   unsigned long long *pctr = nullptr;
   uint32_t *hist = nullptr;
   FinItem *bands = nullptr;
+  size_t dbg_cap = 0;
+  unsigned int *dbg = nullptr;
   // the last call's completion: later calls on another stream wait for it,
   // buffers are freed or regrown only after it
   hipEvent_t done = nullptr;

@@ -74,6 +74,8 @@ enum { kStFallback = 0, kStSmallParts = 1, kStSmallKeys = 2, kStBandKeys = 3, kS
 constexpr uint32_t kErrSegCap = 1, kErrFinCap = 2, kErrLevel = 4, kErrCount = 8;
 constexpr uint32_t kErrQueue = 16;   // persistent schedule: task ring or part pool full
 constexpr uint32_t kErrIter = 32;    // persistent schedule: a workgroup reached its iteration cap
+constexpr uint32_t kErrShadow = 128; // debug shadows: a slot written twice by one part's pass,
+                                     // a store over a final slot, a slot finalised twice or never
 
 // ---- order-preserving codes (compares are done on these, never on floats) --
 
@@ -275,6 +277,10 @@ struct Ctx {
   uint32_t big_cap;
   uint32_t presort_roots;            // 1: k_init checks each root for order itself (batches)
   PCtx p;                            // persistent schedule (p.parts null: none)
+  // debug shadows (null: off), 3 n words: [0, n) and [n, 2n) the depth + 1 of the
+  // part whose pass last stored each slot of K and of S, [2n, 3n) 1 once a slot
+  // of K holds its final key (a band or a small part)
+  unsigned int *dbg;
 };
 
 // ---- wave helpers ------------------------------------------------------------
@@ -524,6 +530,19 @@ __device__ inline void req_final(const Ctx &c, uint32_t req, uint32_t n) {
   }
 }
 
+// Debug shadows.  A part's pass stores each slot of its range (in the other
+// buffer) once: a slot that already holds this part's stamp was reserved twice.
+// The stamp is the part's depth + 1; a slot lies in one part per depth, so the
+// stamps of earlier passes never match.
+__device__ inline void dbg_store(const Ctx &c, bool to_k, uint64_t i, uint32_t depth) {
+  const uint32_t old = atomicExch(&c.dbg[(to_k ? 0ull : c.n) + i], depth + 1u);
+  if (old == depth + 1u) atomicOr(c.err, kErrShadow);
+  if (to_k && c.dbg[2ull * c.n + i] != 0u) atomicOr(c.err, kErrShadow);   // over a final slot
+}
+// A slot of K receives its final key (band fill, small part, a part of one key).
+__device__ inline void dbg_final(const Ctx &c, uint64_t i) {
+  if (atomicExch(&c.dbg[2ull * c.n + i], 1u) != 0u) atomicOr(c.err, kErrShadow);
+}
 // Writes the small-part item of a child into its fixed slot of the wave or the
 // workgroup array and an empty item into the other (one lane).  A single key
 // already in K needs no work and is final at once.
@@ -538,6 +557,7 @@ __device__ inline void put_small(const Ctx &c, uint32_t slot, uint64_t off, uint
   it.len = (real && !wave) ? len : 0u;
   c.fin[slot] = it;
   if (!real && len == 1 && c.req_left) req_final(c, req, 1u);
+  if (!real && len == 1 && c.dbg) dbg_final(c, off);
 }
 
 // Band of a part: short bands go to the part's band slot, long ones are cut
@@ -822,6 +842,29 @@ static __global__ void k_reset(Ctx c) {
 }
 
 // Clears n words (setup of a fixed ring; no memset nodes in captured work).
+static __global__ void k_dbg_clear(Ctx c) {
+  const uint64_t m = 3ull * c.n, st = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m; i += st) c.dbg[i] = 0u;
+}
+// Test modes of the shadows (TSQS_OPT_DEBUG 2, 3): one entry planted before the
+// sort, as if a slot had been finalised already (2: slot 0 of K) or stored by
+// the root's pass already (3: slot 0 of S, the stamp of depth 0), so that a
+// correct sort must report a shadow error.
+static __global__ void k_dbg_plant(Ctx c, int mode) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    if (mode == 2) c.dbg[2ull * c.n] = 1u;
+    else c.dbg[c.n] = 1u;
+  }
+}
+// After the sort: every slot of K holds its final key.
+static __global__ void k_dbg_end(Ctx c) {
+  const uint64_t st = (uint64_t)gridDim.x * blockDim.x;
+  bool bad = false;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < c.n; i += st)
+    bad |= c.dbg[2ull * c.n + i] == 0u;
+  if (bad) atomicOr(c.err, kErrShadow);
+}
+
 static __global__ void k_zero(unsigned long long *p, uint64_t n) {
   for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
     p[i] = 0ull;
@@ -1130,7 +1173,7 @@ struct PartLds {
 // TWO are skipped), workgroup of NT threads.  ctr: the parts' counter lines.
 // WIDE: some part may span 4 GiB or more of keys or payloads.  SP: pointer to
 // the records (constant address space when they are read-only for the kernel).
-template <int DT, bool HASV, bool WIDE, bool TWO, int NT, int KPT_ = 0, typename SP>
+template <int DT, bool HASV, bool WIDE, bool TWO, int NT, int KPT_ = 0, bool DBG = false, typename SP>
 __device__ __attribute__((always_inline)) inline void partition_chunks(
     const Ctx &c, SP segs, unsigned long long *ctr, uint32_t nseg, uint32_t t0, uint32_t t1,
     PartLds<DT, HASV, TWO, NT, KPT_> &L) {
@@ -1388,6 +1431,7 @@ __device__ __attribute__((always_inline)) inline void partition_chunks(
         if (lt || gt) {
           *at<WIDE>(Yp, pos) = key[it];
           if constexpr (HASV) *at<WIDE>(VYp, pos) = val[it];
+          if constexpr (DBG) dbg_store(c, odd, s.off + pos, s.depth);
         }
         if constexpr (HASV) {
           const unsigned long long em = om & ~(lm | gm);
@@ -1553,6 +1597,7 @@ __device__ __attribute__((always_inline)) inline void partition_chunks(
         if (in && pos < s.len) {
           *at<WIDE>(Yp, pos) = key[it];
           if constexpr (HASV) *at<WIDE>(VYp, pos) = val[it];
+          if constexpr (DBG) dbg_store(c, odd, s.off + pos, s.depth);
         }
         opaque_s(r0); opaque_s(r1); opaque_s(r2); opaque_s(r3);
         // four items at a time (keys only; with payloads one): enough overlap to
@@ -1608,7 +1653,7 @@ __device__ __attribute__((always_inline)) inline void partition_chunks(
 // type, so each has the registers, and the occupancy, its own work needs).
 // WGX = 2: twice the threads per workgroup, half the keys per thread (the same
 // chunks: the planning's chunk counts hold for either).
-template <int DT, bool HASV, bool WIDE, bool TWO, int WGX = 1>
+template <int DT, bool HASV, bool WIDE, bool TWO, int WGX = 1, bool DBG = false>
 __global__ __launch_bounds__((TWO ? kPartNT2 : kPartNT1) * WGX) void k_partition(Ctx c, int d) {
   constexpr int NT = (TWO ? kPartNT2 : kPartNT1) * WGX;
   constexpr int KPT_ = WGX == 1 ? 0 : PartCfg<DT, HASV, TWO>::KPT / WGX;
@@ -1628,7 +1673,7 @@ __global__ __launch_bounds__((TWO ? kPartNT2 : kPartNT1) * WGX) void k_partition
   // become scalar loads even after this kernel's own stores
   const CSeg *segs = (const CSeg *)((d & 1) ? c.seg1 : c.seg0);
   unsigned long long *ctr = (d & 1) ? c.ctr1 : c.ctr0;
-  partition_chunks<DT, HASV, WIDE, TWO, NT, KPT_>(c, segs, ctr, nseg, t0, t1, L);
+  partition_chunks<DT, HASV, WIDE, TWO, NT, KPT_, DBG>(c, segs, ctr, nseg, t0, t1, L);
 }
 
 // After level d: bands, small children, next-level parts with pivots (a wave per
@@ -1974,7 +2019,7 @@ __device__ inline void cross_stage(typename R::T (&v)[E], bool take_min, int add
 // together rather than one read and wait per store: slots [len, NT*E) lie in
 // the part's LDS area (NT*E is the part's padded power-of-two size) and are
 // read but never stored; a payload is gathered only for a slot below len.
-template <int DT, bool HASV, int NT, int E>
+template <int DT, bool HASV, int NT, int E, bool DBG>
 __device__ __attribute__((always_inline)) inline void write_part(
     const Ctx &c, const typename Rec<typename Codec<DT>::B, HASV>::T *lds, const uint32_t *srcV,
     typename Codec<DT>::B *K, uint64_t off, uint32_t len, uint32_t t) {
@@ -2001,6 +2046,7 @@ __device__ __attribute__((always_inline)) inline void write_part(
       if (x < len) {
         K[off + x] = Codec<DT>::dec(R::code(o[g]));
         if constexpr (HASV) c.V[off + x] = pv[i0 + g];
+        if constexpr (DBG) dbg_final(c, off + x);
       }
     }
   }
@@ -2008,7 +2054,7 @@ __device__ __attribute__((always_inline)) inline void write_part(
 
 // Sort one small part of len <= NT*E keys with NT threads (one wave or the whole
 // workgroup), E consecutive elements per thread, and write it to K (and V).
-template <int DT, bool HASV, int NT, int E>
+template <int DT, bool HASV, int NT, int E, bool DBG>
 __device__ void sort_group(const Ctx &c, const FinItem &it,
                            typename Rec<typename Codec<DT>::B, HASV>::T *lds, uint32_t t) {
   using B = typename Codec<DT>::B;
@@ -2083,7 +2129,7 @@ __device__ void sort_group(const Ctx &c, const FinItem &it,
 #pragma unroll
   for (int i = 0; i < E; i++) lds[lds_pad(t * E + i)] = v[i];
   group_sync<NT>();
-  write_part<DT, HASV, NT, E>(c, lds, srcV, K, off, len, t);
+  write_part<DT, HASV, NT, E, DBG>(c, lds, srcV, K, off, len, t);
   if (c.req_left) __threadfence();
   group_sync<NT>();
   if (c.req_left && t == 0) req_final(c, it.kind >> 2, len);
@@ -2112,7 +2158,7 @@ __device__ inline uint32_t hyb_run(uint32_t Lp) {
 //   B[bi+E-1-i] are exactly those E records, in bitonic order (Batcher's
 //   merge), and a half-cleaner network in registers sorts them: 2E independent
 //   LDS reads per thread and no dependent chain.
-template <int DT, bool HASV, int NT, int E, bool REG, bool HYB>
+template <int DT, bool HASV, int NT, int E, bool REG, bool HYB, bool DBG>
 __device__ __attribute__((always_inline)) void merge_group(const Ctx &c, const FinItem &it,
                             typename Rec<typename Codec<DT>::B, HASV>::T *lds, uint32_t t) {
   using B = typename Codec<DT>::B;
@@ -2246,13 +2292,13 @@ __device__ __attribute__((always_inline)) void merge_group(const Ctx &c, const F
     }
   }
   group_sync<NT>();
-  write_part<DT, HASV, NT, E>(c, lds, srcV, K, off, len, t);
+  write_part<DT, HASV, NT, E, DBG>(c, lds, srcV, K, off, len, t);
   if (c.req_left) __threadfence();
   group_sync<NT>();
   if (c.req_left && t == 0) req_final(c, it.kind >> 2, len);
 }
 
-template <int DT, bool HASV>
+template <int DT, bool HASV, bool DBG = false>
 __device__ inline void fill_band(const Ctx &c, const FinItem &it, uint32_t t, uint32_t nt) {
   using B = typename Codec<DT>::B;
   B *K = (B *)c.K;
@@ -2260,6 +2306,7 @@ __device__ inline void fill_band(const Ctx &c, const FinItem &it, uint32_t t, ui
   for (uint32_t q = t; q < it.len; q += nt) {
     K[it.off + q] = kv;
     if constexpr (HASV) c.V[it.off + q] = c.VE[it.src + q];
+    if constexpr (DBG) dbg_final(c, it.off + q);
   }
 }
 
@@ -2272,7 +2319,7 @@ __device__ inline void fill_band(const Ctx &c, const FinItem &it, uint32_t t, ui
 // after cross-lane bitonic merging of runs of up to a wave (merge_group).
 // One small part sorted by a workgroup of NTW threads (the algorithm's
 // records per thread chosen by the part's padded size).
-template <int DT, bool HASV, int ALGO, int NTW>
+template <int DT, bool HASV, int ALGO, int NTW, bool DBG>
 __device__ __attribute__((always_inline)) inline void finish_group(
     const Ctx &c, const FinItem &it, typename Rec<typename Codec<DT>::B, HASV>::T *lds, uint32_t tid) {
   constexpr bool BITONIC = ALGO == 0, REG = ALGO == 2, HYB = ALGO >= 2;
@@ -2280,24 +2327,24 @@ __device__ __attribute__((always_inline)) inline void finish_group(
   const uint32_t P = next_pow2(it.len);
   constexpr int ME = max_e<T>();
   if constexpr (BITONIC) {
-    if (P <= 4 * NTW) sort_group<DT, HASV, NTW, 4>(c, it, lds, tid);
-    else if (P <= 8 * NTW || ME < 16) sort_group<DT, HASV, NTW, 8>(c, it, lds, tid);
+    if (P <= 4 * NTW) sort_group<DT, HASV, NTW, 4, DBG>(c, it, lds, tid);
+    else if (P <= 8 * NTW || ME < 16) sort_group<DT, HASV, NTW, 8, DBG>(c, it, lds, tid);
     else if constexpr (ME >= 16) {
-      if (P <= 16 * NTW || ME < 32) sort_group<DT, HASV, NTW, 16>(c, it, lds, tid);
-      else if constexpr (ME >= 32) sort_group<DT, HASV, NTW, 32>(c, it, lds, tid);
+      if (P <= 16 * NTW || ME < 32) sort_group<DT, HASV, NTW, 16, DBG>(c, it, lds, tid);
+      else if constexpr (ME >= 32) sort_group<DT, HASV, NTW, 32, DBG>(c, it, lds, tid);
     }
   } else {
-    if (P <= 4 * NTW) merge_group<DT, HASV, NTW, 4, REG, HYB>(c, it, lds, tid);
-    else if (P <= 8 * NTW || ME < 16) merge_group<DT, HASV, NTW, 8, REG, HYB>(c, it, lds, tid);
+    if (P <= 4 * NTW) merge_group<DT, HASV, NTW, 4, REG, HYB, DBG>(c, it, lds, tid);
+    else if (P <= 8 * NTW || ME < 16) merge_group<DT, HASV, NTW, 8, REG, HYB, DBG>(c, it, lds, tid);
     else if constexpr (ME >= 16) {
-      if (P <= 16 * NTW || ME < 32) merge_group<DT, HASV, NTW, 16, REG, HYB>(c, it, lds, tid);
-      else if constexpr (ME >= 32) merge_group<DT, HASV, NTW, 32, REG, HYB>(c, it, lds, tid);
+      if (P <= 16 * NTW || ME < 32) merge_group<DT, HASV, NTW, 16, REG, HYB, DBG>(c, it, lds, tid);
+      else if constexpr (ME >= 32) merge_group<DT, HASV, NTW, 32, REG, HYB, DBG>(c, it, lds, tid);
     }
   }
 }
 
 // One small part of at most wave_max keys sorted by a wave.
-template <int DT, bool HASV, int ALGO>
+template <int DT, bool HASV, int ALGO, bool DBG>
 __device__ __attribute__((always_inline)) inline void finish_wave(
     const Ctx &c, const FinItem &it, typename Rec<typename Codec<DT>::B, HASV>::T *wl, uint32_t lane) {
   constexpr bool BITONIC = ALGO == 0, REG = ALGO == 2, HYB = ALGO >= 2;
@@ -2305,27 +2352,27 @@ __device__ __attribute__((always_inline)) inline void finish_wave(
   const uint32_t P = next_pow2(it.len);
   constexpr int ME = max_e<T>();
   if constexpr (BITONIC) {
-    if (P <= 64) sort_group<DT, HASV, kWave, 1>(c, it, wl, lane);
-    else if (P <= 128) sort_group<DT, HASV, kWave, 2>(c, it, wl, lane);
-    else if (P <= 256) sort_group<DT, HASV, kWave, 4>(c, it, wl, lane);
-    else if (P <= 512 || ME < 16) sort_group<DT, HASV, kWave, 8>(c, it, wl, lane);
+    if (P <= 64) sort_group<DT, HASV, kWave, 1, DBG>(c, it, wl, lane);
+    else if (P <= 128) sort_group<DT, HASV, kWave, 2, DBG>(c, it, wl, lane);
+    else if (P <= 256) sort_group<DT, HASV, kWave, 4, DBG>(c, it, wl, lane);
+    else if (P <= 512 || ME < 16) sort_group<DT, HASV, kWave, 8, DBG>(c, it, wl, lane);
     else if constexpr (ME >= 16) {
-      if (P <= 1024 || ME < 32) sort_group<DT, HASV, kWave, 16>(c, it, wl, lane);
-      else if constexpr (ME >= 32) sort_group<DT, HASV, kWave, 32>(c, it, wl, lane);
+      if (P <= 1024 || ME < 32) sort_group<DT, HASV, kWave, 16, DBG>(c, it, wl, lane);
+      else if constexpr (ME >= 32) sort_group<DT, HASV, kWave, 32, DBG>(c, it, wl, lane);
     }
   } else {
-    if (P <= 64) merge_group<DT, HASV, kWave, 1, REG, HYB>(c, it, wl, lane);
-    else if (P <= 128) merge_group<DT, HASV, kWave, 2, REG, HYB>(c, it, wl, lane);
-    else if (P <= 256) merge_group<DT, HASV, kWave, 4, REG, HYB>(c, it, wl, lane);
-    else if (P <= 512 || ME < 16) merge_group<DT, HASV, kWave, 8, REG, HYB>(c, it, wl, lane);
+    if (P <= 64) merge_group<DT, HASV, kWave, 1, REG, HYB, DBG>(c, it, wl, lane);
+    else if (P <= 128) merge_group<DT, HASV, kWave, 2, REG, HYB, DBG>(c, it, wl, lane);
+    else if (P <= 256) merge_group<DT, HASV, kWave, 4, REG, HYB, DBG>(c, it, wl, lane);
+    else if (P <= 512 || ME < 16) merge_group<DT, HASV, kWave, 8, REG, HYB, DBG>(c, it, wl, lane);
     else if constexpr (ME >= 16) {
-      if (P <= 1024 || ME < 32) merge_group<DT, HASV, kWave, 16, REG, HYB>(c, it, wl, lane);
-      else if constexpr (ME >= 32) merge_group<DT, HASV, kWave, 32, REG, HYB>(c, it, wl, lane);
+      if (P <= 1024 || ME < 32) merge_group<DT, HASV, kWave, 16, REG, HYB, DBG>(c, it, wl, lane);
+      else if constexpr (ME >= 32) merge_group<DT, HASV, kWave, 32, REG, HYB, DBG>(c, it, wl, lane);
     }
   }
 }
 
-template <int DT, bool HASV, int ALGO>
+template <int DT, bool HASV, int ALGO, bool DBG = false>
 __global__ __launch_bounds__(kFinNT) __attribute__((amdgpu_waves_per_eu(4))) void k_finish(Ctx c, int d) {
   using B = typename Codec<DT>::B;
   using R = Rec<B, HASV>;
@@ -2342,7 +2389,7 @@ __global__ __launch_bounds__(kFinNT) __attribute__((amdgpu_waves_per_eu(4))) voi
   for (uint32_t ii = blockIdx.x; ii < nbig + nslots; ii += gridDim.x) {
     if (ii < nbig) {
       const FinItem bg = c.big[ii];
-      fill_band<DT, HASV>(c, bg, tid, kFinNT);
+      fill_band<DT, HASV, DBG>(c, bg, tid, kFinNT);
       if (c.req_left) {
         __threadfence();
         __syncthreads();
@@ -2354,7 +2401,7 @@ __global__ __launch_bounds__(kFinNT) __attribute__((amdgpu_waves_per_eu(4))) voi
     const uint32_t slot = q < nchild ? q : 4 * c.seg_cap + (q - nchild);
     const FinItem it = c.fin[slot];
     if (it.len == 0) continue;
-    finish_group<DT, HASV, ALGO, kFinNT>(c, it, lds, tid);
+    finish_group<DT, HASV, ALGO, kFinNT, DBG>(c, it, lds, tid);
   }
   const uint32_t wv = tid / kWave, lane = tid & 63u;
   T *wl = lds + (size_t)wv * lds_pad(c.wave_max);
@@ -2363,7 +2410,7 @@ __global__ __launch_bounds__(kFinNT) __attribute__((amdgpu_waves_per_eu(4))) voi
     if (q >= nslots) {
       const FinItem bd = c.band[q - nslots];
       if (bd.len) {
-        fill_band<DT, HASV>(c, bd, lane, kWave);
+        fill_band<DT, HASV, DBG>(c, bd, lane, kWave);
         if (c.req_left) {
           __threadfence();
           __builtin_amdgcn_wave_barrier();
@@ -2375,12 +2422,12 @@ __global__ __launch_bounds__(kFinNT) __attribute__((amdgpu_waves_per_eu(4))) voi
     const uint32_t slot = q < nchild ? q : 4 * c.seg_cap + (q - nchild);
     const FinItem it = c.finw[slot];
     if (it.len == 0) continue;
-    finish_wave<DT, HASV, ALGO>(c, it, wl, lane);
+    finish_wave<DT, HASV, ALGO, DBG>(c, it, wl, lane);
   }
 }
 
 // The small parts the persistent kernel listed (after it has ended).
-template <int DT, bool HASV, int ALGO>
+template <int DT, bool HASV, int ALGO, bool DBG = false>
 __global__ __launch_bounds__(kFinNT) __attribute__((amdgpu_waves_per_eu(4))) void k_finish_list(Ctx c) {
   using T = typename Rec<typename Codec<DT>::B, HASV>::T;
   extern __shared__ unsigned char smem[];
@@ -2389,12 +2436,12 @@ __global__ __launch_bounds__(kFinNT) __attribute__((amdgpu_waves_per_eu(4))) voi
   if (nf + nw > c.p.sfin_cap) return;   // overflow (reported by the persistent kernel)
   const uint32_t tid = threadIdx.x;
   for (unsigned long long i = blockIdx.x; i < nf; i += gridDim.x)
-    finish_group<DT, HASV, ALGO, kFinNT>(c, c.p.sfin[i], lds, tid);
+    finish_group<DT, HASV, ALGO, kFinNT, DBG>(c, c.p.sfin[i], lds, tid);
   const uint32_t wv = tid / kWave, lane = tid & 63u;
   T *wl = lds + (size_t)wv * lds_pad(c.wave_max);
   for (unsigned long long i = (unsigned long long)blockIdx.x * kFinNW + wv; i < nw;
        i += (unsigned long long)gridDim.x * kFinNW)
-    finish_wave<DT, HASV, ALGO>(c, c.p.sfin[c.p.sfin_cap - 1 - i], wl, lane);
+    finish_wave<DT, HASV, ALGO, DBG>(c, c.p.sfin[c.p.sfin_cap - 1 - i], wl, lane);
 }
 
 }  // namespace tsqs

@@ -103,6 +103,8 @@ __device__ inline void persist_child(const Ctx &c, PersistCtl &P, uint64_t off, 
         else persist_abort(c, kErrQueue);
         stat_add(c, kStSmallParts, 1ull);
         stat_add(c, kStSmallKeys, len);
+      } else if (c.dbg) {
+        dbg_final(c, off);   // one key already in K: final in place
       }
       atomicAdd(&P.final_keys, len);
     }
@@ -148,7 +150,7 @@ __device__ inline void persist_child(const Ctx &c, PersistCtl &P, uint64_t off, 
 }
 
 // Plans pool part id after its partition (whole workgroup).
-template <int DT, bool HASV>
+template <int DT, bool HASV, bool DBG>
 __device__ void persist_plan(const Ctx &c, PersistCtl &P, unsigned char *area, uint32_t id) {
   const uint32_t tid = threadIdx.x, wv = tid >> 6, lane = tid & 63u;
   const Seg s = c.p.parts[id].s;
@@ -210,7 +212,7 @@ __device__ void persist_plan(const Ctx &c, PersistCtl &P, unsigned char *area, u
   for (int b = 0; b < 3; b++) {
     if (band[b].len == 0) continue;
     if (band[b].len <= kBandChunk) {
-      fill_band<DT, HASV>(c, band[b], tid, kPNT);
+      fill_band<DT, HASV, DBG>(c, band[b], tid, kPNT);
       band_now += band[b].len;
     } else if (wv == 0) {
       uint32_t bid = ~0u;
@@ -244,7 +246,7 @@ __device__ void persist_plan(const Ctx &c, PersistCtl &P, unsigned char *area, u
 }
 
 // A partition task.
-template <int DT, bool HASV, bool WIDE>
+template <int DT, bool HASV, bool WIDE, bool DBG>
 __device__ void persist_part(const Ctx &c, PersistCtl &P, unsigned char *area, const Task &t) {
   const uint32_t tid = threadIdx.x;
   TPart *tp = c.p.parts + t.id;
@@ -252,10 +254,10 @@ __device__ void persist_part(const Ctx &c, PersistCtl &P, unsigned char *area, c
   unsigned long long *ctr = c.p.pctr + (size_t)t.id * kCtrStride;
   if (flags & kSegTwo) {
     auto &L = *reinterpret_cast<PartLds<DT, HASV, true, kPNT> *>(area);
-    partition_chunks<DT, HASV, WIDE, true, kPNT>(c, (const Seg *)&tp->s, ctr, 1u, t.c0, t.c1, L);
+    partition_chunks<DT, HASV, WIDE, true, kPNT, 0, DBG>(c, (const Seg *)&tp->s, ctr, 1u, t.c0, t.c1, L);
   } else {
     auto &L = *reinterpret_cast<PartLds<DT, HASV, false, kPNT> *>(area);
-    partition_chunks<DT, HASV, WIDE, false, kPNT>(c, (const Seg *)&tp->s, ctr, 1u, t.c0, t.c1, L);
+    partition_chunks<DT, HASV, WIDE, false, kPNT, 0, DBG>(c, (const Seg *)&tp->s, ctr, 1u, t.c0, t.c1, L);
   }
   __syncthreads();
   if (tid == 0) {
@@ -267,7 +269,7 @@ __device__ void persist_part(const Ctx &c, PersistCtl &P, unsigned char *area, c
   __syncthreads();
   if (!P.last) return;
   __threadfence();
-  persist_plan<DT, HASV>(c, P, area, t.id);
+  persist_plan<DT, HASV, DBG>(c, P, area, t.id);
 }
 
 // A select task: histogram of the current digit over its chunks.
@@ -370,7 +372,7 @@ __device__ void persist_select(const Ctx &c, PersistCtl &P, unsigned char *area,
 }
 
 // The persistent kernel.
-template <int DT, bool HASV, bool WIDE>
+template <int DT, bool HASV, bool WIDE, bool DBG = false>
 __global__ __launch_bounds__(kPNT) void k_persist(Ctx c) {
   extern __shared__ __align__(16) unsigned char smem[];
   PersistCtl &P = *reinterpret_cast<PersistCtl *>(smem);
@@ -399,7 +401,7 @@ __global__ __launch_bounds__(kPNT) void k_persist(Ctx c) {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     const Task t = P.task;
     if (t.kind == kTaskPart) {
-      persist_part<DT, HASV, WIDE>(c, P, area, t);
+      persist_part<DT, HASV, WIDE, DBG>(c, P, area, t);
     } else if (t.kind == kTaskSelect) {
       persist_select<DT, HASV>(c, P, area, t);
     } else {
@@ -409,7 +411,7 @@ __global__ __launch_bounds__(kPNT) void k_persist(Ctx c) {
       it.off = b.off + at;
       it.src = b.src + at;
       it.len = b.len - (uint32_t)at < kBandChunk ? b.len - (uint32_t)at : kBandChunk;
-      fill_band<DT, HASV>(c, it, tid, kPNT);
+      fill_band<DT, HASV, DBG>(c, it, tid, kPNT);
       __syncthreads();
       if (tid == 0) atomicSub(&c.p.ctl[kQLeft], (unsigned long long)it.len);
     }

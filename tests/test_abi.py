@@ -152,6 +152,11 @@ def test_options(lib):
         assert lib.tsqs_set_option(tsqs.OPT_WORKSPACE_CAP, 1 << 20) == 0
         assert tsqs.get_option(tsqs.OPT_WORKSPACE_CAP) == 1 << 20
         assert lib.tsqs_set_option(tsqs.OPT_WORKSPACE_CAP, 0) == 0
+        assert tsqs.get_option(tsqs.OPT_DEBUG) == 0
+        assert lib.tsqs_set_option(tsqs.OPT_DEBUG, 1) == 0 and tsqs.get_option(tsqs.OPT_DEBUG) == 1
+        assert lib.tsqs_set_option(tsqs.OPT_DEBUG, 4) == -1
+        assert lib.tsqs_set_option(tsqs.OPT_DEBUG, -1) == -1
+        assert lib.tsqs_set_option(tsqs.OPT_DEBUG, 0) == 0
         assert lib.tsqs_set_option(999, 1) == -4
         assert tsqs.get_option(999) == -(1 << 63)
     finally:
