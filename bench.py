@@ -23,8 +23,8 @@ bytes-weighted mean.
 ``cpu_baseline`` times the CPU oracle (single-threaded Triple State QuickSort)
 on a bounded sample of the same workload.
 
-Other workloads (``--workload``): plain1m, pairs64, float32, batch, serve; each
-prints its own JSON line.
+Other workloads (``--workload``): plain1m, pairs64, float32, batch, serve, paper,
+records, adversarial; each prints its own JSON line.
 """
 from __future__ import annotations
 
@@ -424,6 +424,68 @@ def workload_float32(args):
             [(ti.special_float32(ti.seed_for(3, 2), m), None)],
             "%d float32 N(0,1) keys with the same specials" % m)
     return out
+
+
+def workload_adversarial(args):
+    """The depth-limit fallback: 2^26 uniform int32 keys sorted with exact-minimum
+    pivots (TSQS_OPT_PIVOT_MODE 1, the test mode that drives every pivot to the
+    extreme), against the same keys with sampled pivots.  The first split keeps
+    nearly every key, so the part's subtree takes exact medians from there on:
+    grid-wide radix selection rounds (reads) and a one-level pass per level.
+    ``frac_lower_bound`` counts the partition and persistent-kernel passes' bytes
+    only (not the selection rounds' reads) over the sort time, against 8 TB/s."""
+    import torch
+    import paper_1505_00558_amd as tsqs
+    import tsqs_inputs as ti
+    n = 1 << 26
+    keys0 = ti.device_family("uniform", n, "int32", seed=ti.seed_for(2, "uniform") + 3)
+    work = torch.empty_like(keys0)
+
+    def timed(mode):
+        tsqs.set_option(tsqs.OPT_PIVOT_MODE, mode)
+        try:
+            ms = []
+            for step in range(args.warmup + args.steps):
+                work.copy_(keys0)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                tsqs.sort(work)
+                torch.cuda.synchronize()
+                if step >= args.warmup:
+                    ms.append((time.perf_counter() - t0) * 1e3)
+            st = tsqs.get_stats()
+        finally:
+            tsqs.set_option(tsqs.OPT_PIVOT_MODE, 0)
+        return float(np.median(ms)), st
+
+    ms_n, st_n = timed(0)
+    ms_a, st_a = timed(1)
+    ok = bool(torch.equal(work, torch.sort(keys0).values))
+    moved = st_a["partition_bytes"] + st_a["tail_bytes"]
+    return {
+        "metric": METRIC,
+        "value": n / (ms_a / 1e3),
+        "unit": "keys/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_a,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int32",
+        "data": "synthetic",
+        "config": {"workload": "depth-limit fallback: 2^26 uniform int32 keys, exact-minimum "
+                               "pivots (TSQS_OPT_PIVOT_MODE 1)", "n": n},
+        "sorted": ok,
+        "normal_ms": ms_n,
+        "slowdown": ms_a / ms_n,
+        "fallback_parts": st_a["fallback_parts"],
+        "select_rounds": st_a["select_rounds"],
+        "tail_keys": st_a["tail_keys"],
+        "pass_bytes": moved,
+        "frac_lower_bound": moved / (ms_a / 1e3) / 1e9 / PEAK_GBS,
+    }
 
 
 def device_sorted_check(keys, offs) -> bool:
@@ -846,7 +908,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="large",
                     choices=["large", "plain1m", "pairs64", "float32", "batch", "serve", "paper",
-                             "records"])
+                             "records", "adversarial"])
     ap.add_argument("--records-log2n", type=int, default=26)
     ap.add_argument("--paper-log2n", type=int, default=20)
     ap.add_argument("--log2n", type=int, default=28)
@@ -879,7 +941,7 @@ def main():
     fn = {"large": workload_large, "plain1m": workload_plain1m, "pairs64": workload_pairs64,
           "float32": workload_float32, "batch": workload_batch,
           "serve": workload_serve, "paper": workload_paper,
-          "records": workload_records}.get(args.workload)
+          "records": workload_records, "adversarial": workload_adversarial}.get(args.workload)
     if fn is None:
         print("bench.py: workload %s is not available" % args.workload, file=sys.stderr)
         sys.exit(2)
