@@ -271,7 +271,10 @@ int tsqs_autotune(int dt, int with_payload, size_t n, const uint64_t *h_offsets,
 /* Graphs, for callers that sort the same buffers, of the same shape, many
  * times (a batch of fixed array sizes refilled between sorts, a serving slot):
  * the whole schedule of one call is captured once into a HIP graph and then
- * replayed with one launch.
+ * replayed with one launch.  The operation of a replay is that of tsqs_sort /
+ * tsqs_sort_batch (the paper's problem statement, abstract and SVII; the
+ * repeated calls of SIX's overhead tests); the graph itself has no paper
+ * counterpart. 
  *
  * tsqs_graph_create captures the sort of nmemb keys at d_keys (and payloads at
  * d_vals, or NULL): one array when h_offsets is NULL, else the nseg arrays of

@@ -86,8 +86,9 @@ int tsqs_queue_reap(tsqs_queue_t *q, uint64_t *tickets, size_t cap, size_t *coun
 
 /* Give a done request's arena space back (TSQS_EAGAIN if it is not done). */
 int tsqs_queue_release(tsqs_queue_t *q, uint64_t ticket);
-/* Cancel a request: one still queued is dropped (never admitted, its source
- * never read), a done one is released; the ticket becomes invalid (TSQS_OK).
+/* Cancel a request (serving only; no paper counterpart): one still queued is
+ * dropped (never admitted, its source never read), a done one is released; the
+ * ticket becomes invalid (TSQS_OK).
  * TSQS_EAGAIN for a running request (its device work is enqueued: release it
  * when done), TSQS_EINVAL for an unknown ticket. */
 int tsqs_queue_cancel(tsqs_queue_t *q, uint64_t ticket);
