@@ -14,6 +14,7 @@
 #include "tsqs_host.hpp"
 #include "tsqs_queue_state.hpp"
 
+#include <atomic>
 #include <cstring>
 
 #ifndef TSQS_DT
@@ -24,12 +25,36 @@ namespace tsqs {
 namespace host {
 namespace {
 
+// Workgroups of the two-level partition instance when TSQS_OPT_PART_GRID is 0.
+// For 4-byte elements (keys without payload), as many as are resident at once
+// (the occupancy of this instance): each workgroup owns a fixed run of chunks,
+// so a second round of workgroups would finish after the first, and the pass is
+// latency-bound enough that the fifth workgroup per CU pays (measured on 2^28
+// int32: 5 per CU, all resident, 0.56 ms per pass; 4 per CU 0.58 ms; 6 per CU,
+// one round and a straggler, 0.60 ms).  Wider elements move twice the bytes per
+// chunk and keep 4 per CU (2^28 int64: 0.96 ms per pass at 4, 0.97 at 5).
+template <int DT, bool HASV, bool WIDE, int WGX>
+int resident_grid(int cus) {
+  if (HASV || sizeof(typename Codec<DT>::B) > 4) return 4 * cus;
+  static std::atomic<int> per_cu{0};
+  int nb = per_cu.load(std::memory_order_relaxed);
+  if (nb == 0) {
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_partition<DT, HASV, WIDE, true, WGX>,
+                                                     WGX * kPartNT2, 0) != hipSuccess || nb < 1)
+      nb = 4;
+    per_cu.store(nb, std::memory_order_relaxed);
+  }
+  return nb * cus;
+}
+
 // The partition kernels of level d: the one-level kernel, then (d > 0 or
 // `two`) the two-level kernel, each at the workgroup size the options choose
 // (TSQS_OPT_PART_THREADS1 / 2: the default, or twice the threads with half the
-// keys each).
+// keys each).  grid: the one-level kernel's workgroups, and the two-level
+// kernel's when TSQS_OPT_PART_GRID sets them; cus: compute units.
 template <int DT, bool HASV, bool WIDE>
-void launch_pass(const Ctx &c, int d, bool two, int grid, hipStream_t s) {
+void launch_pass(const Ctx &c, int d, bool two, int grid, int cus, hipStream_t s) {
+  const bool fixed = g_opt.part_grid > 0;
   if (c.dbg) {
     // debug shadows: the checking instances, at the default workgroup sizes
     hipLaunchKernelGGL((k_partition<DT, HASV, WIDE, false, 1, true>), dim3(grid), dim3(kPartNT1), 0, s, c, d);
@@ -42,10 +67,13 @@ void launch_pass(const Ctx &c, int d, bool two, int grid, hipStream_t s) {
   else
     hipLaunchKernelGGL((k_partition<DT, HASV, WIDE, false, 1>), dim3(grid), dim3(kPartNT1), 0, s, c, d);
   if (!two) return;
-  if (g_opt.part_threads2 == 2 * kPartNT2)
-    hipLaunchKernelGGL((k_partition<DT, HASV, WIDE, true, 2>), dim3(grid), dim3(2 * kPartNT2), 0, s, c, d);
-  else
-    hipLaunchKernelGGL((k_partition<DT, HASV, WIDE, true, 1>), dim3(grid), dim3(kPartNT2), 0, s, c, d);
+  if (g_opt.part_threads2 == 2 * kPartNT2) {
+    const int g2 = fixed ? grid : resident_grid<DT, HASV, WIDE, 2>(cus);
+    hipLaunchKernelGGL((k_partition<DT, HASV, WIDE, true, 2>), dim3(g2), dim3(2 * kPartNT2), 0, s, c, d);
+  } else {
+    const int g2 = fixed ? grid : resident_grid<DT, HASV, WIDE, 1>(cus);
+    hipLaunchKernelGGL((k_partition<DT, HASV, WIDE, true, 1>), dim3(g2), dim3(kPartNT2), 0, s, c, d);
+  }
 }
 
 template <int DT, bool HASV>
@@ -220,9 +248,9 @@ int run_t(const CallEnv &env, const CallArgs &a) {
     if (timing) HIPCHK(hipEventRecord(env.ev[2 * d], s));
     if (idle) {
     } else if (wide) {
-      launch_pass<DT, HASV, true>(c, d, d > 0, part_grid, s);
+      launch_pass<DT, HASV, true>(c, d, d > 0, part_grid, env.cus, s);
     } else {
-      launch_pass<DT, HASV, false>(c, d, d > 0, part_grid, s);
+      launch_pass<DT, HASV, false>(c, d, d > 0, part_grid, env.cus, s);
     }
     if (timing) HIPCHK(hipEventRecord(env.ev[2 * d + 1], s));
     if (!idle) hipLaunchKernelGGL((k_plan<DT, HASV>), dim3(plan_grid), dim3(kPlanNT), 0, s, c, d);
@@ -348,8 +376,8 @@ int queue_tick(tsqs_queue *q, QGroup &G) {
     hipLaunchKernelGGL((k_init<DT, false>), dim3(wgs < (uint32_t)grid ? wgs : (uint32_t)grid),
                        dim3(kPlanNT), 0, G.s, c);
   }
-  if ((uint64_t)G.max_n * G.kb > 0xFFFFFFFFull) launch_pass<DT, false, true>(c, d, true, grid, G.s);
-  else launch_pass<DT, false, false>(c, d, true, grid, G.s);
+  if ((uint64_t)G.max_n * G.kb > 0xFFFFFFFFull) launch_pass<DT, false, true>(c, d, true, grid, q->cus, G.s);
+  else launch_pass<DT, false, false>(c, d, true, grid, q->cus, G.s);
   hipLaunchKernelGGL((k_plan<DT, false>), dim3(grid), dim3(kPlanNT), 0, G.s, c, d);
   const int fgrid = g_opt.finish_grid > 0 ? (int)g_opt.finish_grid : kFinGridPerCu * q->cus;
   if (g_opt.finish_algo == 0)

@@ -1408,7 +1408,7 @@ int tsqs_autotune(int dt, int with_payload, size_t n, const uint64_t *h_offsets,
   };
   for (int64_t t : {2048, 4096, 8192}) try_value(&Options::small_max, t);
   for (int64_t v : {31, 63}) try_value(&Options::samples, v);
-  for (int64_t m : {2, 4, 8}) try_value(&Options::part_grid, m * cus);
+  for (int64_t m : {2, 4, 5, 6, 8}) try_value(&Options::part_grid, m * cus);
   for (int64_t m : {8, 16, 32}) try_value(&Options::finish_grid, m * cus);
   for (int64_t a : {0, 1, 2, 3}) try_value(&Options::finish_algo, a);
   // workgroup size against keys per thread (the same chunk of keys)
