@@ -82,7 +82,7 @@ enum {
   TSQS_OPT_TIMING = 6,       /* 1 = time every partition launch with HIP events */
   TSQS_OPT_PART_GRID = 7,    /* workgroups of the partition kernels (0 = auto: 4 per CU;
                                 for the two-level kernel over 4-byte keys without
-                                payload, as many as are resident at once, 5 per CU) */
+                                payload, as many as are resident at once, 7 per CU) */
   TSQS_OPT_FINISH_GRID = 8,  /* workgroups of the finish kernel (0 = auto: 32 per CU) */
   TSQS_OPT_FINISH_ALGO = 9,  /* small parts: 0 = bitonic sorting network, 1 = per-thread
                                 sorting network + merge-path merging in LDS, one output

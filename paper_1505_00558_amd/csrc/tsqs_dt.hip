@@ -27,12 +27,12 @@ namespace {
 
 // Workgroups of the two-level partition instance when TSQS_OPT_PART_GRID is 0.
 // For 4-byte elements (keys without payload), as many as are resident at once
-// (the occupancy of this instance): each workgroup owns a fixed run of chunks,
-// so a second round of workgroups would finish after the first, and the pass is
-// latency-bound enough that the fifth workgroup per CU pays (measured on 2^28
-// int32: 5 per CU, all resident, 0.56 ms per pass; 4 per CU 0.58 ms; 6 per CU,
-// one round and a straggler, 0.60 ms).  Wider elements move twice the bytes per
-// chunk and keep 4 per CU (2^28 int64: 0.96 ms per pass at 4, 0.97 at 5).
+// (the occupancy of this instance, 7 per CU): each workgroup owns a fixed run of
+// chunks, so a second round of workgroups would finish after the first, and the
+// pass is latency-bound enough that every resident workgroup pays (2^28 int32,
+// passes in all: 4.9 ms at 7 per CU, 5.05 at 5, 5.2 at 4; a grid one round
+// larger than fits left a straggler round).  Wider elements move twice the bytes
+// per chunk and keep 4 per CU (2^28 int64: passes 8.94 ms at 4, 9.06 at 5).
 template <int DT, bool HASV, bool WIDE, int WGX>
 int resident_grid(int cus) {
   if (HASV || sizeof(typename Codec<DT>::B) > 4) return 4 * cus;

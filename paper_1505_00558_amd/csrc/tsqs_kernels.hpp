@@ -1282,6 +1282,12 @@ __device__ __attribute__((always_inline)) inline void partition_chunks(
     // keys (and payloads) of this thread: KPT items, VEC consecutive per load
     auto load = [&](auto full_tag, B (&key)[KPT], uint32_t (&val)[HASV ? KPT : 1]) __attribute__((always_inline)) {
       constexpr bool FULL = decltype(full_tag)::value;
+      // per-load offsets recomputed each chunk from an opaque copy of the thread
+      // index: hoisted out of the chunk loop they held a register each (the
+      // two-level kernel for 4-byte keys: 96 -> 73 registers)
+      uint32_t tv = tid;
+      opaque_v(tv);
+      const uint4 *wv0 = g.win + tv;
 #pragma unroll
       for (int j = 0; j < NLOAD; j++) {
         uint4 v = make_uint4(0u, 0u, 0u, 0u);
@@ -1289,8 +1295,8 @@ __device__ __attribute__((always_inline)) inline void partition_chunks(
           // blocks outside the part hold stale values: the range masks drop them
           v = stage[j * NT + tid];
         } else {
-          const uint32_t e0 = (uint32_t)(j * NT + tid) * VEC;
-          if (FULL || (e0 + VEC > lo && e0 < hi)) v = g.win[j * NT + tid];
+          const uint32_t e0 = (uint32_t)(j * NT + tv) * VEC;
+          if (FULL || (e0 + VEC > lo && e0 < hi)) v = wv0[j * NT];
         }
         if constexpr (KB == 4) {
           key[j * VEC + 0] = v.x; key[j * VEC + 1] = v.y; key[j * VEC + 2] = v.z; key[j * VEC + 3] = v.w;
@@ -1653,13 +1659,22 @@ __device__ __attribute__((always_inline)) inline void partition_chunks(
   }
 }
 
+// The two-level instance for 4-byte keys without payload asks for 7 waves per
+// SIMD (at most 72 registers, no spills): its chunks are latency-bound, and 2^28
+// int32 passes take 4.9 ms at 7 workgroups per CU, 5.0 at 6 and 5.05 at 5.
+template <int DT, bool HASV, bool TWO, int WGX, bool DBG>
+constexpr int part_waves() {
+  return (TWO && !HASV && sizeof(typename Codec<DT>::B) == 4 && WGX == 1 && !DBG) ? 7 : 1;
+}
+
 // One partition level: every chunk of every part of level d whose pass type is
 // TWO (two-level parts); the parts of the other type are skipped (a kernel per
 // type, so each has the registers, and the occupancy, its own work needs).
 // WGX = 2: twice the threads per workgroup, half the keys per thread (the same
 // chunks: the planning's chunk counts hold for either).
 template <int DT, bool HASV, bool WIDE, bool TWO, int WGX = 1, bool DBG = false>
-__global__ __launch_bounds__((TWO ? kPartNT2 : kPartNT1) * WGX) void k_partition(Ctx c, int d) {
+__global__ __launch_bounds__((TWO ? kPartNT2 : kPartNT1) * WGX)
+__attribute__((amdgpu_waves_per_eu(part_waves<DT, HASV, TWO, WGX, DBG>()))) void k_partition(Ctx c, int d) {
   constexpr int NT = (TWO ? kPartNT2 : kPartNT1) * WGX;
   constexpr int KPT_ = WGX == 1 ? 0 : PartCfg<DT, HASV, TWO>::KPT / WGX;
   static_assert(PartCfg<DT, HASV, TWO, NT, KPT_>::CH == PartCfg<DT, HASV, TWO>::CH, "chunk");
