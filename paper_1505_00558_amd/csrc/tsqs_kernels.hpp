@@ -1979,6 +1979,14 @@ __device__ inline void merge_regs_dir(typename R::T (&v)[E], bool asc) {
 }
 
 __device__ inline uint32_t lds_pad(uint32_t x) { return x + (x >> 5); }
+// lds_pad(i * NT + t) for t < NT, NT a multiple of 32: a base per thread plus a
+// constant per i, which the LDS instructions take as their immediate offset (the
+// compiler, not knowing t < NT, kept one register per i across parts)
+template <int NT>
+__device__ inline uint32_t lds_stripe(uint32_t i, uint32_t t) {
+  static_assert(NT % 32 == 0, "stripe");
+  return i * (uint32_t)(NT + NT / 32) + t + (t >> 5);
+}
 
 template <int NT>
 __device__ inline void group_sync() {
@@ -2045,12 +2053,16 @@ __device__ __attribute__((always_inline)) inline void write_part(
     typename Codec<DT>::B *K, uint64_t off, uint32_t len, uint32_t t) {
   using R = Rec<typename Codec<DT>::B, HASV>;
   constexpr int WB = E < 8 ? E : 8;
+  // the thread index as an opaque value: the slot indices below are recomputed
+  // per part instead of held in registers across parts
+  uint32_t tv = t;
+  opaque_v(tv);
   uint32_t pv[HASV ? E : 1];
   if constexpr (HASV) {
 #pragma unroll
     for (int i = 0; i < E; i++) {
-      const uint32_t x = (uint32_t)i * NT + t;
-      const uint32_t li = x < len ? R::idx(lds[lds_pad(x)]) : 0u;
+      const uint32_t x = (uint32_t)i * NT + tv;
+      const uint32_t li = x < len ? R::idx(lds[lds_stripe<NT>(i, tv)]) : 0u;
       pv[i] = srcV[off + li];
     }
     group_sync<NT>();   // every payload is read before any is overwritten (in-place parts)
@@ -2059,10 +2071,10 @@ __device__ __attribute__((always_inline)) inline void write_part(
   for (int i0 = 0; i0 < E; i0 += WB) {
     typename R::T o[WB];
 #pragma unroll
-    for (int g = 0; g < WB; g++) o[g] = lds[lds_pad((uint32_t)(i0 + g) * NT + t)];
+    for (int g = 0; g < WB; g++) o[g] = lds[lds_stripe<NT>(i0 + g, tv)];
 #pragma unroll
     for (int g = 0; g < WB; g++) {
-      const uint32_t x = (uint32_t)(i0 + g) * NT + t;
+      const uint32_t x = (uint32_t)(i0 + g) * NT + tv;
       if (x < len) {
         K[off + x] = Codec<DT>::dec(R::code(o[g]));
         if constexpr (HASV) c.V[off + x] = pv[i0 + g];
@@ -2193,20 +2205,23 @@ __device__ __attribute__((always_inline)) void merge_group(const Ctx &c, const F
   const uint32_t Lp = (len + E - 1) / E * E;
   const bool act = t * (uint32_t)E < Lp;
   // coalesced load into LDS (unconditional loads, index clamped into the part,
-  // issued eight at a time)
+  // issued eight at a time); the slot indices come from an opaque copy of the
+  // thread index, recomputed per part rather than held across parts
+  uint32_t tv = t;
+  opaque_v(tv);
   constexpr int LB = E < 8 ? E : 8;
 #pragma unroll
   for (int i0 = 0; i0 < E; i0 += LB) {
     B kin[LB];
 #pragma unroll
     for (int g = 0; g < LB; g++) {
-      const uint32_t x = (uint32_t)(i0 + g) * NT + t;
+      const uint32_t x = (uint32_t)(i0 + g) * NT + tv;
       kin[g] = src[off + (x < len ? x : len - 1)];
     }
 #pragma unroll
     for (int g = 0; g < LB; g++) {
-      const uint32_t x = (uint32_t)(i0 + g) * NT + t;
-      if (x < Lp) lds[lds_pad(x)] = x < len ? R::make(Codec<DT>::enc(kin[g]), x) : R::pad();
+      const uint32_t x = (uint32_t)(i0 + g) * NT + tv;
+      if (x < Lp) lds[lds_stripe<NT>(i0 + g, tv)] = x < len ? R::make(Codec<DT>::enc(kin[g]), x) : R::pad();
     }
   }
   group_sync<NT>();

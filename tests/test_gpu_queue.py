@@ -201,10 +201,14 @@ def test_queue_direct_keeps_caller_stats(direct_min):
     q.close()
 
 
-def test_queue_cancel(oracle_mod):
+@pytest.mark.parametrize("direct_min", [0], indirect=True)
+def test_queue_cancel(oracle_mod, direct_min):
     """A queued request can be cancelled (never admitted; the rest of the queue
     completes as before); a running one cannot (TSQS_EAGAIN); a done one is
-    released; a cancelled ticket is unknown afterwards."""
+    released; a cancelled ticket is unknown afterwards.  Every request goes
+    through the ticks (one level per step), so a request admitted by one step
+    is still running after it: by the single-array schedule it could finish
+    before the poll."""
     import paper_1505_00558_amd as tsqs
     q = tsqs.Queue(256 << 20)
     cap = q.info()["arena_bytes"]
